@@ -1,0 +1,207 @@
+/*
+ * n2f.h -- C ABI of the Noise2Fast per-image train-and-denoise library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the one stated in the Theoretical Background of Noise2Fast
+ * (Lequyer et al., arXiv 2108.10209): given one noisy image x = s + n, find a
+ * network f with f(x) ~ s, using nothing but x.  The method (Methods section,
+ * "Noise2Fast Implementation Details"):
+ *   1. standardise x (no clipping) and checkerboard-downsample it into four
+ *      half-size images (the "up" and "left" downsample equations, Fig. 1);
+ *   2. train a small feed-forward net (eight 3x3 conv+ReLU layers of width
+ *      64, then a 1x1 conv and a sigmoid; Fig. 2a) on the four (input,
+ *      target) pairs of the Methods table, one pair per Adam step (lr 1e-3,
+ *      batch size 1), with a binary cross-entropy loss;
+ *   3. after every epoch run the full image through the net and take the
+ *      MSE against the noisy input; stop once 100 epochs pass without a new
+ *      best score and return the mean of the last 100 validation outputs.
+ * Multi-channel images train one single-output network per channel, each
+ * seeing every input channel (Fig. 2a caption).
+ *
+ * Conventions
+ *  - Every call returns an n2f_status: 0 success, < 0 error, > 0 warning.
+ *    n2f_last_error() returns a message for the calling thread's last error.
+ *    No exception or abort crosses the ABI.
+ *  - Images are FP32, planar C x H x W (CHW), in DEVICE memory owned by the
+ *    caller.  The library never frees or keeps them beyond a run's life.
+ *  - All device memory a run uses comes from one caller-provided device
+ *    workspace of at least n2f_workspace_bytes() bytes; the library makes
+ *    no device allocation of its own.  The workspace must stay alive and
+ *    untouched until n2f_run_destroy().
+ *  - Work is queued on the caller's HIP stream.  Calls marked "synchronises"
+ *    wait for that stream; the others return once the work is queued.
+ *  - A run is not thread-safe; distinct runs are independent.
+ *  - Parameter vectors exchanged with the host use the canonical layout of
+ *    one output-channel network: W1 (64, C, 3, 3), b1 (64), W2..W8
+ *    (64, 64, 3, 3) each followed by its bias (64), W9 (1, 64, 1, 1), b9 (1),
+ *    each flattened in C order (n2f_param_count() floats in total).
+ */
+#ifndef N2F_H
+#define N2F_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int n2f_status;
+
+#define N2F_OK          0
+#define N2F_EINVAL     (-1)   /* bad argument: size, pointer, non-finite input, config */
+#define N2F_ENOMEM     (-2)   /* workspace smaller than n2f_workspace_bytes() */
+#define N2F_EDEVICE    (-3)   /* a HIP runtime call failed */
+#define N2F_ESTATE     (-4)   /* call not valid in the run's current state */
+#define N2F_ENUMERIC   (-5)   /* a validation score became NaN or infinite */
+#define N2F_WCONSTANT   1     /* constant image: returned unchanged, nothing trained */
+#define N2F_WCAPPED     2     /* max_epochs reached before the stopping rule fired */
+
+#define N2F_FP32 0            /* convolutions on FP32 MFMA */
+#define N2F_BF16 1            /* convolutions on BF16 MFMA, FP32 accumulate, FP32 master weights */
+
+typedef struct n2f_config {
+    int    n_layers;          /* 3x3 conv layers; only 8 is supported */
+    int    width;             /* channels per conv layer; only 64 is supported */
+    float  lr;                /* Adam step size (Methods: 1e-3) */
+    float  beta1, beta2, eps; /* Adam moments and epsilon (Kingma and Ba defaults) */
+    int    patience;          /* epochs without a new best before stopping (Methods: 100) */
+    int    max_epochs;        /* safety cap (not in the paper); >= 1 */
+    int    fixed_epochs;      /* > 0: run exactly this many epochs, output the last validation output */
+    int    pair_order[4];     /* order of the four training pairs within an epoch */
+    int    precision;         /* N2F_FP32 or N2F_BF16 */
+    unsigned long long init_seed; /* SplitMix64 seed of the initial weights */
+} n2f_config;
+
+typedef struct n2f_run n2f_run;
+
+/* Fill *cfg with the paper's settings: 8 layers of width 64, Adam lr 1e-3,
+ * betas 0.9/0.999, eps 1e-8, patience 100, max_epochs 2000, early stopping,
+ * pairs in table order, FP32, seed 0. */
+void n2f_config_default(n2f_config* cfg);
+
+/* Message describing the calling thread's most recent error ("" if none). */
+const char* n2f_last_error(void);
+
+/* Number of parameters of one output-channel network for C input channels. */
+n2f_status n2f_param_count(int C, const n2f_config* cfg, size_t* count);
+
+/* Host-only: the initial weights the library draws for a run, written to
+ * host buffer theta (C * n2f_param_count floats, network k at offset
+ * k * count).  Every weight and bias of a layer is U(-1/sqrt(fan_in),
+ * +1/sqrt(fan_in)) (fan_in = Cin*kh*kw; the paper leaves initialisation
+ * open); value i of network k is (2u - 1) * bound rounded once to FP32,
+ * with u the top 53 bits of SplitMix64 output number k*count + i of `seed`. */
+n2f_status n2f_init_params(int C, const n2f_config* cfg, unsigned long long seed, float* theta);
+
+/* Device workspace bytes a run on an H x W x C image needs (H, W >= 2,
+ * 1 <= C <= 3).  This figure is also the unit of HBM admission when runs
+ * share a GPU. */
+n2f_status n2f_workspace_bytes(int H, int W, int C, const n2f_config* cfg, size_t* bytes);
+
+/* Create a run: validates arguments, standardises the image (per-image
+ * min-max to [0, 1], no clipping), builds the four checkerboard downsamples
+ * (even sizes; an odd last row/column is left out of them only) and draws
+ * the initial weights from cfg->init_seed.  d_in: device CHW image, read
+ * during this call only.  Synchronises.  Returns N2F_WCONSTANT for a
+ * constant image (the run then only supports n2f_result, which copies the
+ * input), N2F_EINVAL for non-finite input. */
+n2f_status n2f_run_create(n2f_run** run, const float* d_in, int H, int W, int C,
+                          const n2f_config* cfg, void* d_ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* Release the run's host state.  The workspace may be reused afterwards. */
+n2f_status n2f_run_destroy(n2f_run* run);
+
+/* One training step of network `net` (0 <= net < C) on pair `pair`
+ * (0: up-even -> up-odd, 1: up-odd -> up-even, 2: left-even -> left-odd,
+ * 3: left-odd -> left-even; the Methods table): forward pass, BCE against
+ * channel `net` of the target, backward pass, one Adam step.  Queued. */
+n2f_status n2f_train_step(n2f_run* run, int net, int pair);
+
+/* Validation of network `net` after an epoch: full-image forward pass, MSE
+ * against channel `net` of the standardised input summed in FP64, then the
+ * stopping rule (strict improvement resets the running sum of outputs;
+ * otherwise the output is added).  Synchronises and reports the score, whether
+ * it improved on the best and whether the network is finished.  Any pointer
+ * may be NULL.  Returns N2F_ENUMERIC if the score is not finite. */
+n2f_status n2f_validate(n2f_run* run, int net, double* v, int* improved, int* done);
+
+/* Run whole epochs (four steps in cfg->pair_order, then validation) of
+ * network `net` until it is finished or `max_epochs_now` epochs have run;
+ * the device decides the stopping rule and the host polls it every few
+ * epochs.  *done (may be NULL) reports whether the network finished.
+ * Synchronises.  Returns N2F_WCAPPED when the run hit cfg->max_epochs. */
+n2f_status n2f_run_epochs(n2f_run* run, int net, int max_epochs_now, int* done);
+
+/* Write the denoised image (CHW, input units: lo + (hi - lo) * output) to
+ * device buffer d_out: per channel the mean of the outputs since the best
+ * epoch, the best output if none followed it, or the last output in
+ * fixed-epoch mode.  Queued. */
+n2f_status n2f_result(n2f_run* run, float* d_out);
+
+/* One-shot denoise: create, train every network to its stopping rule,
+ * write d_out, destroy.  Synchronises. */
+n2f_status n2f_denoise(const float* d_in, float* d_out, int H, int W, int C,
+                       const n2f_config* cfg, void* d_ws, size_t ws_bytes,
+                       hipStream_t stream);
+
+/* ---- state exchange (checkpoint/resume and teacher-forced testing) ---- */
+
+/* Copy network `net`'s parameters, Adam moments and step count to host
+ * buffers (canonical layout, n2f_param_count floats each; any may be NULL).
+ * Synchronises. */
+n2f_status n2f_get_state(n2f_run* run, int net, float* theta, float* m, float* v, long long* t);
+
+/* Overwrite network `net`'s parameters, moments and step count from host
+ * buffers (NULL m or v means zeros).  Synchronises. */
+n2f_status n2f_set_state(n2f_run* run, int net, const float* theta, const float* m,
+                         const float* v, long long t);
+
+/* Gradient (canonical layout, host buffer) that the last Adam step of
+ * network `net` used, and that step's mean BCE loss.  Synchronises. */
+n2f_status n2f_get_grad(n2f_run* run, int net, float* g, double* loss);
+
+/* Apply one Adam step to network `net` with the host gradient g (canonical
+ * layout) instead of a computed one.  Synchronises. */
+n2f_status n2f_debug_adam(n2f_run* run, int net, const float* g);
+
+/* Stopping-rule state of network `net`: epochs validated, best epoch,
+ * epochs since the best, best score; any pointer may be NULL.  Synchronises. */
+n2f_status n2f_get_progress(n2f_run* run, int net, int* epoch, int* best_epoch,
+                            int* since_best, double* best);
+
+/* Validation scores of network `net`, epochs 1..n (n <= epochs run), to a
+ * host buffer.  Synchronises. */
+n2f_status n2f_get_history(n2f_run* run, int net, int n, double* v);
+
+/* Per-image extremes used by the standardisation (exact min and max). */
+n2f_status n2f_get_lohi(n2f_run* run, float* lo, float* hi);
+
+/* Copy an intermediate image to device buffer d_out (CHW, FP32):
+ * which = 0..3: the downsamples up-even (C x H' x W'/2), up-odd,
+ * left-even (C x H'/2 x W'), left-odd; 4: the standardised image
+ * (C x H x W); 5 + k: the last validation output of network k
+ * (H x W, standardised units).  Queued. */
+n2f_status n2f_get_image(n2f_run* run, int which, float* d_out);
+
+/* ---- kernel timing ----
+ * While profiling is on, every launch of the instrumented kernel classes is
+ * bracketed by HIP events on the stream it runs on.  Classes:
+ * N2F_K_CONV_FWD (64->64 forward, training and validation), N2F_K_CONV_BWD
+ * (64->64 data gradient), N2F_K_WGRAD (64->64 weight gradient).
+ * n2f_profile_begin clears earlier records; n2f_profile_read synchronises
+ * the recorded events and returns, for one class, the summed kernel time,
+ * the number of launches and the pixels those launches processed.
+ * Process-wide; not thread-safe. */
+#define N2F_K_CONV_FWD 0
+#define N2F_K_CONV_BWD 1
+#define N2F_K_WGRAD    2
+n2f_status n2f_profile_begin(void);
+n2f_status n2f_profile_read(int kernel_class, double* total_ms, long long* launches, long long* pixels);
+n2f_status n2f_profile_end(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* N2F_H */

@@ -1,0 +1,862 @@
+// Host runtime of the Noise2Fast library: argument checks, workspace
+// carving, weight initialisation, the per-step and per-epoch launch
+// sequences, and state exchange.  See include/n2f.h for the contract.
+#include "n2f.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "n2f_internal.h"
+
+using namespace n2f;
+
+namespace {
+
+thread_local std::string g_err;
+
+n2f_status fail(n2f_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define N2F_HIP(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(N2F_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// SplitMix64 (Steele, Lea and Flood 2014), counter form.
+inline unsigned long long splitmix64(unsigned long long seed, unsigned long long n) {
+    unsigned long long z = seed + (n + 1ULL) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// Shapes of one network in canonical order: (cin, kernel taps) per layer.
+struct CanonLayer {
+    int cout, cin, taps;
+};
+
+std::vector<CanonLayer> canon_layers(int C) {
+    std::vector<CanonLayer> v;
+    int cin = C;
+    for (int l = 0; l < kLayers; ++l) {
+        v.push_back({kWidth, cin, kTaps});
+        cin = kWidth;
+    }
+    v.push_back({1, kWidth, 1});
+    return v;
+}
+
+ParamTable make_table(int C, int nsplit, int hsplit) {
+    ParamTable pt{};
+    int off = 0;
+    long long poff = 0;
+    for (int l = 0; l <= kLayers; ++l) {
+        const int cin = (l == 0) ? C : kWidth;
+        pt.cin[l] = cin;
+        pt.off[l] = off;
+        pt.n[l] = (l < kLayers) ? kTaps * cin * kWidth + kWidth : kHeadN;
+        pt.split[l] = (l < kLayers) ? nsplit : hsplit;
+        pt.poff[l] = poff;
+        off += pt.n[l];
+        poff += (long long)pt.split[l] * pt.n[l];
+    }
+    pt.total = off;
+    return pt;
+}
+
+long long partial_floats(const ParamTable& pt) {
+    return pt.poff[kLayers] + (long long)pt.split[kLayers] * pt.n[kLayers];
+}
+
+// Canonical (OIHW per layer) <-> internal (tap-major W[t][ci][co]) maps.
+void canon_to_internal(const float* src, float* dst, int C, const ParamTable& pt) {
+    const auto L = canon_layers(C);
+    int co_off = 0;
+    for (int l = 0; l <= kLayers; ++l) {
+        const CanonLayer& cl = L[l];
+        const float* s = src + co_off;
+        float* d = dst + pt.off[l];
+        if (l < kLayers) {
+            for (int co = 0; co < cl.cout; ++co)
+                for (int ci = 0; ci < cl.cin; ++ci)
+                    for (int t = 0; t < kTaps; ++t) d[(t * cl.cin + ci) * kWidth + co] = s[(co * cl.cin + ci) * kTaps + t];
+            std::memcpy(d + kTaps * cl.cin * kWidth, s + kTaps * cl.cin * kWidth, sizeof(float) * kWidth);
+        } else {
+            std::memcpy(d, s, sizeof(float) * kHeadN);
+        }
+        co_off += pt.n[l];
+    }
+}
+
+void internal_to_canon(const float* src, float* dst, int C, const ParamTable& pt) {
+    const auto L = canon_layers(C);
+    int co_off = 0;
+    for (int l = 0; l <= kLayers; ++l) {
+        const CanonLayer& cl = L[l];
+        const float* s = src + pt.off[l];
+        float* d = dst + co_off;
+        if (l < kLayers) {
+            for (int co = 0; co < cl.cout; ++co)
+                for (int ci = 0; ci < cl.cin; ++ci)
+                    for (int t = 0; t < kTaps; ++t) d[(co * cl.cin + ci) * kTaps + t] = s[(t * cl.cin + ci) * kWidth + co];
+            std::memcpy(d + kTaps * cl.cin * kWidth, s + kTaps * cl.cin * kWidth, sizeof(float) * kWidth);
+        } else {
+            std::memcpy(d, s, sizeof(float) * kHeadN);
+        }
+        co_off += pt.n[l];
+    }
+}
+
+// Workspace carve-out of one run.
+struct Plan {
+    int H, W, C, Hc, Wc, P, bf;
+    int hu, wu, hl, wl;       // up and left training image shapes
+    int nsplit, hsplit, vblk, mmblk, max_trace;
+    ParamTable pt;
+    size_t o_misc, o_xs, o_ds[4], o_net[3], net_bytes;
+    size_t n_state, n_theta, n_pack32, n_pack16, n_trace, n_img;
+    size_t o_act, o_dlt, o_part, o_lpart, o_vpart, bytes;
+    size_t act_elems, dlt_elems;
+    // offsets inside one network's block
+    size_t s_state, s_theta, s_m, s_v, s_g, s_fwd, s_bwd, s_fwd16, s_bwd16, s_trace, s_S, s_yb, s_y;
+};
+
+n2f_status check_cfg(const n2f_config* cfg) {
+    if (!cfg) return fail(N2F_EINVAL, "config is NULL");
+    if (cfg->n_layers != kLayers || cfg->width != kWidth)
+        return fail(N2F_EINVAL, "only 8 layers of width 64 are supported");
+    if (!(cfg->lr > 0.f) || !(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) || !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f) ||
+        !(cfg->eps > 0.f))
+        return fail(N2F_EINVAL, "bad Adam hyper-parameters");
+    if (cfg->patience < 1 || cfg->max_epochs < 1 || cfg->fixed_epochs < 0)
+        return fail(N2F_EINVAL, "patience and max_epochs must be >= 1, fixed_epochs >= 0");
+    if (cfg->precision != N2F_FP32 && cfg->precision != N2F_BF16) return fail(N2F_EINVAL, "unknown precision");
+    if (cfg->precision == N2F_BF16) return fail(N2F_EINVAL, "BF16 precision is not built yet");
+    int seen[4] = {0, 0, 0, 0};
+    for (int i = 0; i < 4; ++i) {
+        if (cfg->pair_order[i] < 0 || cfg->pair_order[i] > 3 || seen[cfg->pair_order[i]]++)
+            return fail(N2F_EINVAL, "pair_order must be a permutation of 0..3");
+    }
+    return N2F_OK;
+}
+
+n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
+    n2f_status s = check_cfg(cfg);
+    if (s != N2F_OK) return s;
+    if (H < 2 || W < 2 || C < 1 || C > 3) return fail(N2F_EINVAL, "need H, W >= 2 and 1 <= C <= 3");
+    if ((long long)H * W > (1LL << 28)) return fail(N2F_EINVAL, "image too large");
+    Plan q{};
+    q.H = H;
+    q.W = W;
+    q.C = C;
+    q.bf = cfg->precision == N2F_BF16;
+    q.Hc = H & ~1;
+    q.Wc = W & ~1;
+    q.hu = q.Hc;
+    q.wu = q.Wc / 2;
+    q.hl = q.Hc / 2;
+    q.wl = q.Wc;
+    q.P = q.Hc * q.Wc / 2;
+    q.nsplit = std::max(wgrad_splits(q.hu, q.wu), wgrad_splits(q.hl, q.wl));
+    q.hsplit = head_splits(q.P);
+    const long long HW = (long long)H * W;
+    q.vblk = (int)std::max(1LL, std::min((HW + 1023) / 1024, 1024LL));
+    q.mmblk = (int)std::max(1LL, std::min((HW * C + 4095) / 4096, 1024LL));
+    q.max_trace = std::max(cfg->max_epochs, cfg->fixed_epochs) + 1;
+    q.pt = make_table(C, q.nsplit, q.hsplit);
+
+    size_t o = 0;
+    q.o_misc = o;
+    o += align_up(4096 + sizeof(float) * 2 * 1024);
+    q.o_xs = o;
+    o += align_up(sizeof(float) * HW * C);
+    for (int i = 0; i < 4; ++i) {
+        q.o_ds[i] = o;
+        o += align_up(sizeof(float) * (size_t)q.P * C);
+    }
+    // one network's block
+    size_t n = 0;
+    q.s_state = n;
+    n += align_up(sizeof(DevState));
+    const size_t tb = align_up(sizeof(float) * q.pt.total);
+    q.s_theta = n;
+    n += tb;
+    q.s_m = n;
+    n += tb;
+    q.s_v = n;
+    n += tb;
+    q.s_g = n;
+    n += tb;
+    const size_t pk = (size_t)(kLayers - 1) * kPackN;
+    q.s_fwd = n;
+    n += q.bf ? 0 : align_up(sizeof(float) * pk);
+    q.s_bwd = n;
+    n += q.bf ? 0 : align_up(sizeof(float) * pk);
+    q.s_fwd16 = n;
+    n += q.bf ? align_up(sizeof(uint16_t) * pk) : 0;
+    q.s_bwd16 = n;
+    n += q.bf ? align_up(sizeof(uint16_t) * pk) : 0;
+    q.s_trace = n;
+    n += align_up(sizeof(double) * q.max_trace);
+    q.s_S = n;
+    n += align_up(sizeof(float) * HW);
+    q.s_yb = n;
+    n += align_up(sizeof(float) * HW);
+    q.s_y = n;
+    n += align_up(sizeof(float) * HW);
+    q.net_bytes = n;
+    for (int k = 0; k < C; ++k) {
+        q.o_net[k] = o;
+        o += n;
+    }
+    const size_t es = q.bf ? 2 : 4;
+    q.act_elems = (size_t)std::max<long long>(8LL * q.P, 2LL * HW) * kWidth;
+    q.dlt_elems = (size_t)q.P * kWidth;
+    q.o_act = o;
+    o += align_up(es * q.act_elems);
+    q.o_dlt = o;
+    o += 2 * align_up(es * q.dlt_elems);
+    q.o_part = o;
+    o += align_up(sizeof(float) * partial_floats(q.pt));
+    q.o_lpart = o;
+    o += align_up(sizeof(double) * kMaxSplit);
+    q.o_vpart = o;
+    o += align_up(sizeof(double) * 1024);
+    q.bytes = o;
+    *p = q;
+    return N2F_OK;
+}
+
+// Kernel-class timing with HIP events on the launch stream (see n2f.h).
+struct ProfRec {
+    int cls;
+    long long npix;
+    hipEvent_t a, b;
+};
+struct Profiler {
+    bool on = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+} g_prof;
+
+hipEvent_t prof_event() {
+    if (g_prof.used < g_prof.pool.size()) return g_prof.pool[g_prof.used++];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_prof.pool.push_back(e);
+    g_prof.used++;
+    return e;
+}
+
+template <class F>
+hipError_t timed(int cls, long long npix, hipStream_t s, F&& f) {
+    if (!g_prof.on) return f();
+    hipEvent_t a = prof_event(), b = prof_event();
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    e = f();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    g_prof.recs.push_back({cls, npix, a, b});
+    return e;
+}
+
+}  // namespace
+
+struct n2f_run {
+    Plan pl;
+    n2f_config cfg;
+    hipStream_t stream;
+    char* ws;
+    bool constant;
+    const float* in_keep;  // only for constant images (copied at create)
+    float lo, hi;
+    // device pointers
+    float* lohi;
+    float* mmpart;
+    unsigned* mmcnt;
+    int* nonfinite;
+    float* xs;
+    float* ds[4];
+    struct Net {
+        DevState* st;
+        float *theta, *m, *v, *g, *fwd, *bwd;
+        uint16_t *fwd16, *bwd16;
+        double* trace;
+        float *S, *yb, *y;
+    } net[3];
+    char* act;
+    char* dlt[2];
+    float* part;
+    double* lpart;
+    double* vpart;
+    bool host_done[3];
+    int host_epochs[3];
+    std::vector<float> staging;
+};
+
+namespace {
+
+template <typename T>
+T* at(char* base, size_t off) {
+    return reinterpret_cast<T*>(base + off);
+}
+
+n2f_status check_run(n2f_run* r, int net) {
+    if (!r) return fail(N2F_EINVAL, "run is NULL");
+    if (r->constant) return fail(N2F_ESTATE, "constant image: nothing to train");
+    if (net < 0 || net >= r->pl.C) return fail(N2F_EINVAL, "network index out of range");
+    return N2F_OK;
+}
+
+void* act_layer(n2f_run* r, int i, size_t npix) {
+    const size_t es = r->pl.bf ? 2 : 4;
+    return r->act + es * (size_t)i * npix * kWidth;
+}
+
+// Images and shapes of training pair `pair`.
+void pair_io(n2f_run* r, int pair, const float** in, const float** tgt, int* h, int* w) {
+    static const int src[4] = {0, 1, 2, 3}, dst[4] = {1, 0, 3, 2};
+    *in = r->ds[src[pair]];
+    *tgt = r->ds[dst[pair]];
+    if (pair < 2) {
+        *h = r->pl.hu;
+        *w = r->pl.wu;
+    } else {
+        *h = r->pl.hl;
+        *w = r->pl.wl;
+    }
+}
+
+n2f_status enqueue_train_step(n2f_run* r, int k, int pair) {
+    const Plan& pl = r->pl;
+    n2f_run::Net& N = r->net[k];
+    const float *in, *tgt;
+    int h, w;
+    pair_io(r, pair, &in, &tgt, &h, &w);
+    const size_t npix = (size_t)h * w;
+    const int bf = pl.bf;
+    const ParamTable& pt = pl.pt;
+    hipStream_t s = r->stream;
+    auto Wl = [&](int l) { return N.theta + pt.off[l]; };                       // layer l, 0-based
+    auto Bl = [&](int l) { return N.theta + pt.off[l] + kTaps * pt.cin[l] * kWidth; };
+    auto fwdpk = [&](int l) -> const void* {
+        return bf ? (const void*)(N.fwd16 + (size_t)(l - 1) * kPackN) : (const void*)(N.fwd + (size_t)(l - 1) * kPackN);
+    };
+    auto bwdpk = [&](int l) -> const void* {
+        return bf ? (const void*)(N.bwd16 + (size_t)(l - 1) * kPackN) : (const void*)(N.bwd + (size_t)(l - 1) * kPackN);
+    };
+    // forward with stash: act layer i holds a_{i+1}
+    N2F_HIP(launch_conv1(in, pl.C, Wl(0), Bl(0), act_layer(r, 0, npix), bf, h, w, N.st, s));
+    for (int l = 1; l < kLayers; ++l)
+        N2F_HIP(timed(N2F_K_CONV_FWD, (long long)npix, s, [&] {
+            return launch_conv_fwd(act_layer(r, l - 1, npix), fwdpk(l), Bl(l), act_layer(r, l, npix), bf, h, w, N.st, s);
+        }));
+    // head, BCE gradient
+    const float* w9 = N.theta + pt.off[kLayers];
+    N2F_HIP(launch_head_train(act_layer(r, kLayers - 1, npix), tgt, pl.C, k, w9, w9 + kWidth, r->dlt[0],
+                              r->part + pt.poff[kLayers], r->lpart, pt.split[kLayers], bf, (long long)npix, N.st, s));
+    // backward: layer l (0-based 7..1) takes delta of its output
+    int cur = 0;
+    for (int l = kLayers - 1; l >= 1; --l) {
+        N2F_HIP(timed(N2F_K_WGRAD, (long long)npix, s, [&] {
+            return launch_wgrad(act_layer(r, l - 1, npix), r->dlt[cur], r->part + pt.poff[l], pt.split[l], bf, h, w,
+                                N.st, s);
+        }));
+        N2F_HIP(timed(N2F_K_CONV_BWD, (long long)npix, s, [&] {
+            return launch_conv_bwd(r->dlt[cur], bwdpk(l), act_layer(r, l - 1, npix), r->dlt[1 - cur], bf, h, w, N.st, s);
+        }));
+        cur = 1 - cur;
+    }
+    N2F_HIP(launch_wgrad1(in, pl.C, r->dlt[cur], r->part + pt.poff[0], pt.split[0], bf, h, w, N.st, s));
+    N2F_HIP(launch_adam(N.theta, N.m, N.v, N.g, r->part, nullptr, pt, r->cfg.lr, (double)r->cfg.beta1,
+                        (double)r->cfg.beta2, r->cfg.eps, N.fwd, N.bwd, N.fwd16, N.bwd16, N.st, s));
+    return N2F_OK;
+}
+
+n2f_status enqueue_validate(n2f_run* r, int k) {
+    const Plan& pl = r->pl;
+    n2f_run::Net& N = r->net[k];
+    const ParamTable& pt = pl.pt;
+    const int bf = pl.bf;
+    const size_t npix = (size_t)pl.H * pl.W;
+    hipStream_t s = r->stream;
+    auto buf = [&](int i) { return act_layer(r, i & 1, npix); };
+    auto Bl = [&](int l) { return N.theta + pt.off[l] + kTaps * pt.cin[l] * kWidth; };
+    N2F_HIP(launch_conv1(r->xs, pl.C, N.theta + pt.off[0], Bl(0), buf(0), bf, pl.H, pl.W, N.st, s));
+    for (int l = 1; l < kLayers; ++l) {
+        const void* pk = bf ? (const void*)(N.fwd16 + (size_t)(l - 1) * kPackN) : (const void*)(N.fwd + (size_t)(l - 1) * kPackN);
+        N2F_HIP(timed(N2F_K_CONV_FWD, (long long)npix, s,
+                      [&] { return launch_conv_fwd(buf(l - 1), pk, Bl(l), buf(l), bf, pl.H, pl.W, N.st, s); }));
+    }
+    const float* w9 = N.theta + pt.off[kLayers];
+    N2F_HIP(launch_head_val(buf(kLayers - 1), r->xs, pl.C, k, w9, w9 + kWidth, N.y, r->vpart, pl.vblk, bf,
+                            (long long)npix, N.st, N.trace, s));
+    N2F_HIP(launch_accumulate(N.y, N.S, N.yb, (long long)npix, N.st, s));
+    return N2F_OK;
+}
+
+n2f_status read_state(n2f_run* r, int k, DevState* out) {
+    N2F_HIP(hipMemcpyAsync(out, r->net[k].st, sizeof(DevState), hipMemcpyDeviceToHost, r->stream));
+    N2F_HIP(hipStreamSynchronize(r->stream));
+    return N2F_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void n2f_config_default(n2f_config* cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->n_layers = kLayers;
+    cfg->width = kWidth;
+    cfg->lr = 1e-3f;
+    cfg->beta1 = 0.9f;
+    cfg->beta2 = 0.999f;
+    cfg->eps = 1e-8f;
+    cfg->patience = 100;
+    cfg->max_epochs = 2000;
+    cfg->fixed_epochs = 0;
+    for (int i = 0; i < 4; ++i) cfg->pair_order[i] = i;
+    cfg->precision = N2F_FP32;
+    cfg->init_seed = 0;
+}
+
+const char* n2f_last_error(void) { return g_err.c_str(); }
+
+n2f_status n2f_param_count(int C, const n2f_config* cfg, size_t* count) {
+    n2f_status s = check_cfg(cfg);
+    if (s != N2F_OK) return s;
+    if (C < 1 || C > 3 || !count) return fail(N2F_EINVAL, "need 1 <= C <= 3 and a non-NULL count");
+    *count = (size_t)make_table(C, 1, 1).total;
+    return N2F_OK;
+}
+
+n2f_status n2f_init_params(int C, const n2f_config* cfg, unsigned long long seed, float* theta) {
+    size_t np;
+    n2f_status s = n2f_param_count(C, cfg, &np);
+    if (s != N2F_OK) return s;
+    if (!theta) return fail(N2F_EINVAL, "theta is NULL");
+    const auto L = canon_layers(C);
+    for (int k = 0; k < C; ++k) {
+        size_t i = 0;
+        for (const CanonLayer& cl : L) {
+            const int fan_in = cl.cin * cl.taps;
+            const double bound = 1.0 / std::sqrt((double)fan_in);
+            const size_t nl = (size_t)cl.cout * cl.cin * cl.taps + cl.cout;
+            for (size_t j = 0; j < nl; ++j, ++i) {
+                const unsigned long long z = splitmix64(seed, (unsigned long long)k * np + i);
+                const double u = (double)(z >> 11) * 0x1.0p-53;
+                theta[(size_t)k * np + i] = (float)((2.0 * u - 1.0) * bound);
+            }
+        }
+    }
+    return N2F_OK;
+}
+
+n2f_status n2f_workspace_bytes(int H, int W, int C, const n2f_config* cfg, size_t* bytes) {
+    if (!bytes) return fail(N2F_EINVAL, "bytes is NULL");
+    Plan p;
+    n2f_status s = make_plan(H, W, C, cfg, &p);
+    if (s != N2F_OK) return s;
+    *bytes = p.bytes;
+    return N2F_OK;
+}
+
+n2f_status n2f_run_create(n2f_run** out, const float* d_in, int H, int W, int C, const n2f_config* cfg,
+                          void* d_ws, size_t ws_bytes, hipStream_t stream) {
+    if (!out) return fail(N2F_EINVAL, "run pointer is NULL");
+    *out = nullptr;
+    if (!d_in || !d_ws) return fail(N2F_EINVAL, "input or workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(N2F_EINVAL, "workspace must be 256-byte aligned");
+    Plan pl;
+    n2f_status s = make_plan(H, W, C, cfg, &pl);
+    if (s != N2F_OK) return s;
+    if (ws_bytes < pl.bytes)
+        return fail(N2F_ENOMEM, "workspace too small: need " + std::to_string(pl.bytes) + " bytes");
+    n2f_run* r = new (std::nothrow) n2f_run();
+    if (!r) return fail(N2F_ENOMEM, "host allocation failed");
+    r->pl = pl;
+    r->cfg = *cfg;
+    r->stream = stream;
+    r->ws = static_cast<char*>(d_ws);
+    r->constant = false;
+    r->in_keep = nullptr;
+    char* b = r->ws;
+    char* misc = b + pl.o_misc;
+    r->lohi = at<float>(misc, 0);
+    r->mmcnt = at<unsigned>(misc, 64);
+    r->nonfinite = at<int>(misc, 128);
+    r->mmpart = at<float>(misc, 4096);
+    r->xs = at<float>(b, pl.o_xs);
+    for (int i = 0; i < 4; ++i) r->ds[i] = at<float>(b, pl.o_ds[i]);
+    for (int k = 0; k < C; ++k) {
+        char* nb = b + pl.o_net[k];
+        n2f_run::Net& N = r->net[k];
+        N.st = at<DevState>(nb, pl.s_state);
+        N.theta = at<float>(nb, pl.s_theta);
+        N.m = at<float>(nb, pl.s_m);
+        N.v = at<float>(nb, pl.s_v);
+        N.g = at<float>(nb, pl.s_g);
+        N.fwd = pl.bf ? nullptr : at<float>(nb, pl.s_fwd);
+        N.bwd = pl.bf ? nullptr : at<float>(nb, pl.s_bwd);
+        N.fwd16 = pl.bf ? at<uint16_t>(nb, pl.s_fwd16) : nullptr;
+        N.bwd16 = pl.bf ? at<uint16_t>(nb, pl.s_bwd16) : nullptr;
+        N.trace = at<double>(nb, pl.s_trace);
+        N.S = at<float>(nb, pl.s_S);
+        N.yb = at<float>(nb, pl.s_yb);
+        N.y = at<float>(nb, pl.s_y);
+        r->host_done[k] = false;
+        r->host_epochs[k] = 0;
+    }
+    r->act = b + pl.o_act;
+    const size_t es = pl.bf ? 2 : 4;
+    r->dlt[0] = b + pl.o_dlt;
+    r->dlt[1] = b + pl.o_dlt + align_up(es * pl.dlt_elems);
+    r->part = at<float>(b, pl.o_part);
+    r->lpart = at<double>(b, pl.o_lpart);
+    r->vpart = at<double>(b, pl.o_vpart);
+
+    auto bail = [&](n2f_status st) {
+        delete r;
+        return st;
+    };
+    hipStream_t sm = stream;
+    if (hipMemsetAsync(misc, 0, 4096, sm) != hipSuccess) return bail(fail(N2F_EDEVICE, "memset failed"));
+    const long long n = (long long)H * W * C;
+    if (launch_minmax(d_in, n, r->mmpart, pl.mmblk, r->mmcnt, r->lohi, r->nonfinite, sm) != hipSuccess)
+        return bail(fail(N2F_EDEVICE, "minmax launch failed"));
+    float lohi[2];
+    int nonfin = 0;
+    if (hipMemcpyAsync(lohi, r->lohi, sizeof(lohi), hipMemcpyDeviceToHost, sm) != hipSuccess ||
+        hipMemcpyAsync(&nonfin, r->nonfinite, sizeof(int), hipMemcpyDeviceToHost, sm) != hipSuccess ||
+        hipStreamSynchronize(sm) != hipSuccess)
+        return bail(fail(N2F_EDEVICE, "reading min/max failed"));
+    if (nonfin) return bail(fail(N2F_EINVAL, "input holds NaN or infinite values"));
+    r->lo = lohi[0];
+    r->hi = lohi[1];
+    if (!(lohi[1] > lohi[0])) {
+        r->constant = true;
+        r->in_keep = d_in;
+        // keep a copy of the input inside the workspace (xs has room for it)
+        if (hipMemcpyAsync(r->xs, d_in, sizeof(float) * n, hipMemcpyDeviceToDevice, sm) != hipSuccess ||
+            hipStreamSynchronize(sm) != hipSuccess)
+            return bail(fail(N2F_EDEVICE, "copy failed"));
+        *out = r;
+        g_err = "constant image";
+        return N2F_WCONSTANT;
+    }
+    if (launch_prepare(d_in, H, W, C, r->lohi, r->xs, r->ds[0], r->ds[1], r->ds[2], r->ds[3], sm) != hipSuccess)
+        return bail(fail(N2F_EDEVICE, "prepare launch failed"));
+    // initial weights, drawn on the host and copied once
+    std::vector<float> th0((size_t)C * pl.pt.total), internal(pl.pt.total);
+    n2f_init_params(C, cfg, cfg->init_seed, th0.data());
+    for (int k = 0; k < C; ++k) {
+        n2f_run::Net& N = r->net[k];
+        canon_to_internal(th0.data() + (size_t)k * pl.pt.total, internal.data(), C, pl.pt);
+        if (hipMemcpyAsync(N.theta, internal.data(), sizeof(float) * pl.pt.total, hipMemcpyHostToDevice, sm) !=
+                hipSuccess ||
+            hipMemsetAsync(N.m, 0, sizeof(float) * pl.pt.total, sm) != hipSuccess ||
+            hipMemsetAsync(N.v, 0, sizeof(float) * pl.pt.total, sm) != hipSuccess ||
+            hipMemsetAsync(N.g, 0, sizeof(float) * pl.pt.total, sm) != hipSuccess ||
+            hipMemsetAsync(N.S, 0, sizeof(float) * H * W, sm) != hipSuccess ||
+            hipMemsetAsync(N.yb, 0, sizeof(float) * H * W, sm) != hipSuccess ||
+            hipMemsetAsync(N.y, 0, sizeof(float) * H * W, sm) != hipSuccess ||
+            launch_init_state(N.st, cfg->patience, cfg->max_epochs, cfg->fixed_epochs, sm) != hipSuccess ||
+            launch_pack(N.theta, pl.pt, N.fwd, N.bwd, N.fwd16, N.bwd16, sm) != hipSuccess ||
+            hipStreamSynchronize(sm) != hipSuccess)  // host buffer must outlive the copy
+            return bail(fail(N2F_EDEVICE, "initialising network state failed"));
+    }
+    *out = r;
+    return N2F_OK;
+}
+
+n2f_status n2f_run_destroy(n2f_run* r) {
+    if (!r) return fail(N2F_EINVAL, "run is NULL");
+    delete r;
+    return N2F_OK;
+}
+
+n2f_status n2f_train_step(n2f_run* r, int net, int pair) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    if (pair < 0 || pair > 3) return fail(N2F_EINVAL, "pair must be 0..3");
+    if (r->host_done[net]) return fail(N2F_ESTATE, "network already finished");
+    return enqueue_train_step(r, net, pair);
+}
+
+n2f_status n2f_validate(n2f_run* r, int net, double* v, int* improved, int* done) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    if (r->host_done[net]) return fail(N2F_ESTATE, "network already finished");
+    s = enqueue_validate(r, net);
+    if (s != N2F_OK) return s;
+    DevState st;
+    s = read_state(r, net, &st);
+    if (s != N2F_OK) return s;
+    r->host_done[net] = st.done != 0;
+    r->host_epochs[net] = st.epoch;
+    if (v) *v = st.last_v;
+    if (improved) *improved = st.improved;
+    if (done) *done = st.done;
+    if (st.nonfinite) return fail(N2F_ENUMERIC, "validation score is not finite");
+    return N2F_OK;
+}
+
+n2f_status n2f_run_epochs(n2f_run* r, int net, int max_now, int* done) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    if (max_now < 1) return fail(N2F_EINVAL, "max_epochs_now must be >= 1");
+    DevState st;
+    int ran = 0;
+    while (!r->host_done[net] && ran < max_now) {
+        // queue a few epochs ahead, then poll the device-side stopping rule
+        const int batch = std::min(max_now - ran, 4);
+        for (int e = 0; e < batch; ++e) {
+            for (int i = 0; i < 4; ++i) {
+                s = enqueue_train_step(r, net, r->cfg.pair_order[i]);
+                if (s != N2F_OK) return s;
+            }
+            s = enqueue_validate(r, net);
+            if (s != N2F_OK) return s;
+        }
+        ran += batch;
+        s = read_state(r, net, &st);
+        if (s != N2F_OK) return s;
+        r->host_done[net] = st.done != 0;
+        r->host_epochs[net] = st.epoch;
+    }
+    s = read_state(r, net, &st);
+    if (s != N2F_OK) return s;
+    if (done) *done = st.done;
+    if (st.nonfinite) return fail(N2F_ENUMERIC, "validation score is not finite");
+    if (st.capped) return N2F_WCAPPED;
+    return N2F_OK;
+}
+
+n2f_status n2f_result(n2f_run* r, float* d_out) {
+    if (!r || !d_out) return fail(N2F_EINVAL, "run or output is NULL");
+    const Plan& pl = r->pl;
+    const long long npix = (long long)pl.H * pl.W;
+    if (r->constant) {
+        N2F_HIP(hipMemcpyAsync(d_out, r->xs, sizeof(float) * npix * pl.C, hipMemcpyDeviceToDevice, r->stream));
+        return N2F_WCONSTANT;
+    }
+    for (int k = 0; k < pl.C; ++k) {
+        n2f_run::Net& N = r->net[k];
+        N2F_HIP(launch_finalize(N.y, N.S, N.yb, r->lohi, d_out + (size_t)k * npix, npix, N.st, r->stream));
+    }
+    return N2F_OK;
+}
+
+n2f_status n2f_denoise(const float* d_in, float* d_out, int H, int W, int C, const n2f_config* cfg, void* d_ws,
+                       size_t ws_bytes, hipStream_t stream) {
+    n2f_run* r = nullptr;
+    n2f_status s = n2f_run_create(&r, d_in, H, W, C, cfg, d_ws, ws_bytes, stream);
+    if (s < 0) return s;
+    n2f_status warn = N2F_OK;
+    if (s == N2F_OK) {
+        const int cap = cfg->fixed_epochs > 0 ? cfg->fixed_epochs : cfg->max_epochs;
+        for (int k = 0; k < C; ++k) {
+            int done = 0;
+            s = n2f_run_epochs(r, k, cap, &done);
+            if (s < 0) {
+                n2f_run_destroy(r);
+                return s;
+            }
+            if (s == N2F_WCAPPED) warn = N2F_WCAPPED;
+        }
+    }
+    s = n2f_result(r, d_out);
+    if (s >= 0 && hipStreamSynchronize(stream) != hipSuccess) s = fail(N2F_EDEVICE, "synchronise failed");
+    n2f_run_destroy(r);
+    if (s < 0) return s;
+    return s == N2F_WCONSTANT ? s : warn;
+}
+
+n2f_status n2f_get_state(n2f_run* r, int net, float* theta, float* m, float* v, long long* t) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    const ParamTable& pt = r->pl.pt;
+    n2f_run::Net& N = r->net[net];
+    std::vector<float> tmp(pt.total);
+    float* dsts[3] = {theta, m, v};
+    float* srcs[3] = {N.theta, N.m, N.v};
+    for (int i = 0; i < 3; ++i) {
+        if (!dsts[i]) continue;
+        N2F_HIP(hipMemcpyAsync(tmp.data(), srcs[i], sizeof(float) * pt.total, hipMemcpyDeviceToHost, r->stream));
+        N2F_HIP(hipStreamSynchronize(r->stream));
+        internal_to_canon(tmp.data(), dsts[i], r->pl.C, pt);
+    }
+    if (t) {
+        DevState st;
+        s = read_state(r, net, &st);
+        if (s != N2F_OK) return s;
+        *t = st.t;
+    }
+    return N2F_OK;
+}
+
+n2f_status n2f_set_state(n2f_run* r, int net, const float* theta, const float* m, const float* v, long long t) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    if (!theta || t < 0) return fail(N2F_EINVAL, "theta is NULL or t < 0");
+    const ParamTable& pt = r->pl.pt;
+    n2f_run::Net& N = r->net[net];
+    std::vector<float> tmp(pt.total);
+    const float* srcs[3] = {theta, m, v};
+    float* dsts[3] = {N.theta, N.m, N.v};
+    for (int i = 0; i < 3; ++i) {
+        if (srcs[i]) {
+            canon_to_internal(srcs[i], tmp.data(), r->pl.C, pt);
+            N2F_HIP(hipMemcpyAsync(dsts[i], tmp.data(), sizeof(float) * pt.total, hipMemcpyHostToDevice, r->stream));
+            N2F_HIP(hipStreamSynchronize(r->stream));
+        } else {
+            N2F_HIP(hipMemsetAsync(dsts[i], 0, sizeof(float) * pt.total, r->stream));
+        }
+    }
+    N2F_HIP(launch_pack(N.theta, pt, N.fwd, N.bwd, N.fwd16, N.bwd16, r->stream));
+    DevState st;
+    s = read_state(r, net, &st);
+    if (s != N2F_OK) return s;
+    st.t = t;
+    N2F_HIP(hipMemcpyAsync(N.st, &st, sizeof(DevState), hipMemcpyHostToDevice, r->stream));
+    N2F_HIP(hipStreamSynchronize(r->stream));
+    return N2F_OK;
+}
+
+n2f_status n2f_get_grad(n2f_run* r, int net, float* g, double* loss) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    const ParamTable& pt = r->pl.pt;
+    if (g) {
+        std::vector<float> tmp(pt.total);
+        N2F_HIP(hipMemcpyAsync(tmp.data(), r->net[net].g, sizeof(float) * pt.total, hipMemcpyDeviceToHost, r->stream));
+        N2F_HIP(hipStreamSynchronize(r->stream));
+        internal_to_canon(tmp.data(), g, r->pl.C, pt);
+    }
+    if (loss) {
+        DevState st;
+        s = read_state(r, net, &st);
+        if (s != N2F_OK) return s;
+        *loss = st.loss;
+    }
+    return N2F_OK;
+}
+
+n2f_status n2f_debug_adam(n2f_run* r, int net, const float* g) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    if (!g) return fail(N2F_EINVAL, "gradient is NULL");
+    if (r->host_done[net]) return fail(N2F_ESTATE, "network already finished");
+    const ParamTable& pt = r->pl.pt;
+    n2f_run::Net& N = r->net[net];
+    std::vector<float> tmp(pt.total);
+    canon_to_internal(g, tmp.data(), r->pl.C, pt);
+    // stage the injected gradient in the partial-sum buffer (unused between steps)
+    N2F_HIP(hipMemcpyAsync(r->part, tmp.data(), sizeof(float) * pt.total, hipMemcpyHostToDevice, r->stream));
+    N2F_HIP(launch_adam(N.theta, N.m, N.v, N.g, r->part, r->part, pt, r->cfg.lr, (double)r->cfg.beta1,
+                        (double)r->cfg.beta2, r->cfg.eps, N.fwd, N.bwd, N.fwd16, N.bwd16, N.st, r->stream));
+    N2F_HIP(hipStreamSynchronize(r->stream));
+    return N2F_OK;
+}
+
+n2f_status n2f_get_progress(n2f_run* r, int net, int* epoch, int* best_epoch, int* since_best, double* best) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    DevState st;
+    s = read_state(r, net, &st);
+    if (s != N2F_OK) return s;
+    if (epoch) *epoch = st.epoch;
+    if (best_epoch) *best_epoch = st.best_epoch;
+    if (since_best) *since_best = st.n_since;
+    if (best) *best = st.best;
+    return N2F_OK;
+}
+
+n2f_status n2f_get_history(n2f_run* r, int net, int n, double* v) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    DevState st;
+    s = read_state(r, net, &st);
+    if (s != N2F_OK) return s;
+    if (n < 0 || n > st.epoch || (n > 0 && !v)) return fail(N2F_EINVAL, "n exceeds the epochs run");
+    if (n == 0) return N2F_OK;
+    N2F_HIP(hipMemcpyAsync(v, r->net[net].trace, sizeof(double) * n, hipMemcpyDeviceToHost, r->stream));
+    N2F_HIP(hipStreamSynchronize(r->stream));
+    return N2F_OK;
+}
+
+n2f_status n2f_get_lohi(n2f_run* r, float* lo, float* hi) {
+    if (!r) return fail(N2F_EINVAL, "run is NULL");
+    if (lo) *lo = r->lo;
+    if (hi) *hi = r->hi;
+    return N2F_OK;
+}
+
+n2f_status n2f_get_image(n2f_run* r, int which, float* d_out) {
+    if (!r || !d_out) return fail(N2F_EINVAL, "run or output is NULL");
+    if (r->constant) return fail(N2F_ESTATE, "constant image: nothing prepared");
+    const Plan& pl = r->pl;
+    if (which >= 0 && which < 4) {
+        const int h = which < 2 ? pl.hu : pl.hl, w = which < 2 ? pl.wu : pl.wl;
+        N2F_HIP(launch_extract(r->ds[which], h, w, pl.C, d_out, r->stream));
+    } else if (which == 4) {
+        N2F_HIP(launch_extract(r->xs, pl.H, pl.W, pl.C, d_out, r->stream));
+    } else if (which >= 5 && which < 5 + pl.C) {
+        N2F_HIP(hipMemcpyAsync(d_out, r->net[which - 5].y, sizeof(float) * pl.H * pl.W, hipMemcpyDeviceToDevice,
+                               r->stream));
+    } else {
+        return fail(N2F_EINVAL, "unknown image index");
+    }
+    return N2F_OK;
+}
+
+n2f_status n2f_profile_begin(void) {
+    g_prof.recs.clear();
+    g_prof.used = 0;
+    g_prof.on = true;
+    return N2F_OK;
+}
+
+n2f_status n2f_profile_read(int cls, double* total_ms, long long* launches, long long* pixels) {
+    if (cls < N2F_K_CONV_FWD || cls > N2F_K_WGRAD) return fail(N2F_EINVAL, "unknown kernel class");
+    double ms = 0.0;
+    long long n = 0, px = 0;
+    for (const ProfRec& rec : g_prof.recs) {
+        if (rec.cls != cls) continue;
+        N2F_HIP(hipEventSynchronize(rec.b));
+        float t = 0.f;
+        N2F_HIP(hipEventElapsedTime(&t, rec.a, rec.b));
+        ms += t;
+        n += 1;
+        px += rec.npix;
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = n;
+    if (pixels) *pixels = px;
+    return N2F_OK;
+}
+
+n2f_status n2f_profile_end(void) {
+    g_prof.on = false;
+    return N2F_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,218 @@
+// 3x3, 64->64 convolutions of the Noise2Fast network as implicit GEMMs on
+// the gfx950 matrix cores (the Methods network: eight 3x3 conv+ReLU layers).
+//
+//   forward      out[p][co]  = relu(b[co] + sum_{t,ci} in[p+off(t)][ci] * W[t][ci][co])
+//   data grad    d_in[p][ci] = [a[p][ci] > 0] * sum_{t,co} d[p+off(t)][co] * W[8-t][ci][co]
+//   weight grad  dW[t][ci][co] = sum_p in[p+off(t)][ci] * d[p][co],  db[co] = sum_p d[p][co]
+//
+// with off(t) = (t/3 - 1, t%3 - 1) and zero padding.  The data gradient is
+// the forward form with flipped taps and transposed per-tap weights, so both
+// run through one kernel that takes a packed operand.
+//
+// Tiling (FP32 path): a 256-thread block owns a 16x16 pixel tile.  The
+// 18x18x64 input halo is staged once in LDS (pixel stride 68 floats: 16-byte
+// aligned rows, and 8 consecutive pixels of a 128-bit read land on 32
+// distinct banks).  Each of the 4 waves computes 4 tile rows x 64 output
+// channels as 4x4 MFMA 16x16x4 tiles; a lane reads 4 consecutive input
+// channels with one 128-bit LDS load and feeds them to 4 MFMA steps (the K
+// order inside each 16-channel chunk is permuted identically for A and B).
+// B operands stream from the packed weights in L2.
+#include "n2f_internal.h"
+
+namespace n2f {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 16;
+constexpr int kHalo = kTile + 2;
+constexpr int kHS = 68;  // LDS floats per staged pixel
+
+__device__ __forceinline__ bool finished(const DevState* st) { return st != nullptr && st->done; }
+
+// Stage the (16+2)^2 x 64 halo around tile (x0, y0) of a channels-last FP32
+// activation into LDS, zero outside the image.
+__device__ __forceinline__ void stage_halo_f32(float* halo, const float* __restrict__ in, int x0, int y0, int h,
+                                               int w) {
+    for (int idx = threadIdx.x; idx < kHalo * kHalo * 16; idx += 256) {
+        const int pix = idx >> 4, q = idx & 15;
+        const int hy = pix / kHalo, hx = pix - hy * kHalo;
+        const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+        floatx4 v = {0.f, 0.f, 0.f, 0.f};
+        if (gy >= 0 && gy < h && gx >= 0 && gx < w)
+            v = *reinterpret_cast<const floatx4*>(in + ((long long)gy * w + gx) * kWidth + 4 * q);
+        *reinterpret_cast<floatx4*>(halo + pix * kHS + 4 * q) = v;
+    }
+}
+
+// MODE 0: forward with bias + ReLU.  MODE 1: data gradient masked by [a > 0].
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv_f32(const float* __restrict__ in, const float* __restrict__ wpk,
+                                                  const float* __restrict__ bias, const float* __restrict__ mask,
+                                                  float* __restrict__ out, int h, int w, const DevState* st) {
+    if (finished(st)) return;
+    __shared__ __attribute__((aligned(16))) float halo[kHalo * kHalo * kHS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    stage_halo_f32(halo, in, x0, y0, h, w);
+    __syncthreads();
+
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const floatx4* wp = reinterpret_cast<const floatx4*>(wpk);
+    for (int t = 0; t < kTaps; ++t) {
+        const int dy = t / 3, dx = t - 3 * (t / 3);
+        const float* hrow = halo + ((4 * wv + dy) * kHalo + n + dx) * kHS + 4 * g;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            floatx4 a[4], b[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = wp[(t * 16 + 4 * cc + g) * 64 + 16 * j + n];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const floatx4*>(hrow + i * kHalo * kHS + 16 * cc);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+        }
+    }
+
+    // D row (pixel x within the tile) = 4g + r, column (channel) = n.
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int gy = y0 + 4 * wv + i;
+        if (gy >= h) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int co = 16 * j + n;
+            float bv = 0.f;
+            if (MODE == 0) bv = bias[co];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gx = x0 + 4 * g + r;
+                if (gx >= w) continue;
+                const long long o = ((long long)gy * w + gx) * kWidth + co;
+                float v = acc[i][j][r];
+                if (MODE == 0) v = fmaxf(v + bv, 0.f);
+                else v = (mask[o] > 0.f) ? v : 0.f;
+                out[o] = v;
+            }
+        }
+    }
+}
+
+// Weight gradient of a 64->64 layer.  Block b accumulates tiles b, b + S,
+// b + 2S, ... of 16x16 pixels and writes one partial [9*64*64 + 64].
+// GEMM view: M = (t, ci) = 576 rows, N = co = 64, K = pixels; each wave owns
+// 144 rows (9 M-tiles of 16) x 64 columns and takes 4 pixels per MFMA.
+__global__ __launch_bounds__(256) void k_wgrad_f32(const float* __restrict__ src, const float* __restrict__ dlt,
+                                                   float* __restrict__ part, int h, int w, const DevState* st) {
+    if (finished(st)) return;
+    __shared__ __attribute__((aligned(16))) float halo[kHalo * kHalo * kHS];
+    __shared__ __attribute__((aligned(16))) float dt[kTile * kTile * kHS];
+    __shared__ float dbs[4][kWidth];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    const int tiles_x = (w + kTile - 1) / kTile, tiles_y = (h + kTile - 1) / kTile;
+    const int ntiles = tiles_x * tiles_y;
+
+    floatx4 acc[9][4];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float dbacc = 0.f;
+
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
+        stage_halo_f32(halo, src, x0, y0, h, w);
+        for (int idx = threadIdx.x; idx < kTile * kTile * 16; idx += 256) {
+            const int p = idx >> 4, q = idx & 15;
+            const int gy = y0 + (p >> 4), gx = x0 + (p & 15);
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            if (gy < h && gx < w) v = *reinterpret_cast<const floatx4*>(dlt + ((long long)gy * w + gx) * kWidth + 4 * q);
+            *reinterpret_cast<floatx4*>(dt + p * kHS + 4 * q) = v;
+        }
+        __syncthreads();
+        {
+            const int co = threadIdx.x & 63, pg = threadIdx.x >> 6;
+            float s = 0.f;
+            for (int p = pg * 64; p < pg * 64 + 64; ++p) s += dt[p * kHS + co];
+            dbs[pg][co] = s;
+        }
+        for (int kk = 0; kk < 64; ++kk) {
+            const int p = 4 * kk + g;
+            const int py = p >> 4, px = p & 15;
+            float b[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = dt[p * kHS + 16 * j + n];
+#pragma unroll
+            for (int ib = 0; ib < 9; ++ib) {
+                const int mb = 9 * wv + ib;
+                const int t = mb >> 2, ci0 = (mb & 3) * 16;
+                const int dy = t / 3, dx = t - 3 * (t / 3);
+                const float a = halo[((py + dy) * kHalo + px + dx) * kHS + ci0 + n];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[ib][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[j], acc[ib][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < kWidth) dbacc += ((dbs[0][threadIdx.x] + dbs[1][threadIdx.x]) + dbs[2][threadIdx.x]) + dbs[3][threadIdx.x];
+    }
+
+    float* pp = part + (long long)blockIdx.x * kConvN;
+#pragma unroll
+    for (int ib = 0; ib < 9; ++ib) {
+        const int mb = 9 * wv + ib;
+        const int t = mb >> 2, ci0 = (mb & 3) * 16;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pp[(t * 64 + ci0 + 4 * g + r) * 64 + 16 * j + n] = acc[ib][j][r];
+    }
+    if (threadIdx.x < kWidth) pp[kConvW + threadIdx.x] = dbacc;
+}
+
+}  // namespace
+
+hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, void* out, int bf16, int h, int w,
+                           const DevState* st, hipStream_t s) {
+    if (bf16) return hipErrorNotSupported;
+    dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
+    hipLaunchKernelGGL(k_conv_f32<0>, grid, dim3(256), 0, s, (const float*)in, (const float*)wpk, bias,
+                       (const float*)nullptr, (float*)out, h, w, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, void* out, int bf16, int h, int w,
+                           const DevState* st, hipStream_t s) {
+    if (bf16) return hipErrorNotSupported;
+    dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
+    hipLaunchKernelGGL(k_conv_f32<1>, grid, dim3(256), 0, s, (const float*)dlt, (const float*)wpk,
+                       (const float*)nullptr, (const float*)mask, (float*)out, h, w, st);
+    return hipGetLastError();
+}
+
+int wgrad_splits(int h, int w) {
+    const int tiles = ((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile);
+    return tiles < kMaxSplit ? tiles : kMaxSplit;
+}
+
+hipError_t launch_wgrad(const void* src, const void* dlt, float* part, int nsplit, int bf16, int h, int w,
+                        const DevState* st, hipStream_t s) {
+    if (bf16) return hipErrorNotSupported;
+    hipLaunchKernelGGL(k_wgrad_f32, dim3(nsplit), dim3(256), 0, s, (const float*)src, (const float*)dlt, part, h, w,
+                       st);
+    return hipGetLastError();
+}
+
+}  // namespace n2f

@@ -1,0 +1,100 @@
+// Internal interfaces shared by the host runtime (n2f_api.cpp) and the
+// kernel translation units.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace n2f {
+
+constexpr int kWidth = 64;        // channels of every hidden layer
+constexpr int kLayers = 8;        // 3x3 conv layers
+constexpr int kTaps = 9;
+constexpr int kConvW = kTaps * kWidth * kWidth;   // weights of a 64->64 layer
+constexpr int kConvN = kConvW + kWidth;           // ... plus its bias
+constexpr int kHeadN = kWidth + 1;                // 1x1 head: 64 weights + bias
+constexpr int kMaxSplit = 256;                    // max pixel splits of a weight gradient
+
+// Per-network state that lives in device memory.  The stopping rule is
+// decided on the device so that whole epochs can be queued without a host
+// round trip; every epoch kernel returns at once when `done` is set.
+struct DevState {
+    double best;          // best validation score so far (+inf at start)
+    double last_v;        // score of the last validation
+    double loss;          // mean BCE of the last training step
+    long long t;          // Adam steps taken
+    int epoch;            // validations done
+    int best_epoch;       // epoch of `best` (1-based), 0 before the first
+    int n_since;          // validations since the best one
+    int improved;         // last validation improved on the best
+    int done;             // network finished (rule fired, cap hit, or numeric failure)
+    int capped;           // finished by max_epochs
+    int pending;          // a validation output waits to be folded into the running sum
+    int nonfinite;        // a non-finite score was seen
+    int patience, max_epochs, fixed_epochs;
+    unsigned cnt_val, cnt_adam, cnt_acc, cnt_loss;   // last-block counters
+    int pad_;
+};
+
+// Where each trainable tensor of one network sits.  The internal ("tap
+// major") layout of a 3x3 layer is W[t][ci][co] followed by b[co]; the head
+// is w9[c] followed by b9.  Weight-gradient partial sums of layer l use the
+// same per-layer layout, one copy per pixel split.
+struct ParamTable {
+    int off[kLayers + 1];     // offset of layer l (0-based, 8 = head) in theta
+    int n[kLayers + 1];       // floats of layer l
+    int cin[kLayers + 1];     // input channels of layer l
+    int split[kLayers + 1];   // number of partial copies of layer l
+    long long poff[kLayers + 1];  // offset of layer l's partials in the partial buffer
+    int total;                // parameters of one network
+};
+
+// Packed convolution operands for layers 2..8 (index l-1 = 1..7).  For the
+// FP32 kernels, per layer 9*64*64 floats:
+//   fwd[t][ci/4][co][ci%4]   = W[t][ci][co]
+//   bwd[t][co/4][ci][co%4]   = W[8-t][ci][co]     (flipped taps, transposed)
+// For BF16, per layer 9*64*64 bf16:
+//   fwd[t][ci/8][co][ci%8], bwd[t][co/8][ci][co%8].
+constexpr int kPackN = kTaps * kWidth * kWidth;
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).  All return hipError_t of the
+// launch.  `st` may be null for kernels run outside an epoch.
+// ---------------------------------------------------------------------------
+hipError_t launch_minmax(const float* x, long long n, float* part, int nblk, unsigned* counter,
+                         float* lohi, int* nonfinite, hipStream_t s);
+hipError_t launch_prepare(const float* x, int H, int W, int C, const float* lohi,
+                          float* xs, float* ue, float* uo, float* le, float* lo, hipStream_t s);
+hipError_t launch_init_state(DevState* st, int patience, int max_epochs, int fixed_epochs, hipStream_t s);
+hipError_t launch_pack(const float* theta, const ParamTable& pt, float* fwd, float* bwd,
+                       uint16_t* fwd16, uint16_t* bwd16, hipStream_t s);
+hipError_t launch_conv1(const float* in, int C, const float* w1, const float* b1, void* out, int bf16,
+                        int h, int w, const DevState* st, hipStream_t s);
+hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, void* out, int bf16,
+                           int h, int w, const DevState* st, hipStream_t s);
+hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, void* out, int bf16,
+                           int h, int w, const DevState* st, hipStream_t s);
+int wgrad_splits(int h, int w);
+hipError_t launch_wgrad(const void* src, const void* dlt, float* part, int nsplit, int bf16,
+                        int h, int w, const DevState* st, hipStream_t s);
+hipError_t launch_wgrad1(const float* in, int C, const void* dlt, float* part, int nsplit, int bf16,
+                         int h, int w, const DevState* st, hipStream_t s);
+int head_splits(long long npix);
+hipError_t launch_head_train(const void* a8, const float* tgt, int C, int k, const float* w9,
+                             const float* b9, void* d8, float* part, double* lpart, int nsplit,
+                             int bf16, long long npix, DevState* st, hipStream_t s);
+hipError_t launch_head_val(const void* a8, const float* xs, int C, int k, const float* w9,
+                           const float* b9, float* y, double* vpart, int nblk, int bf16,
+                           long long npix, DevState* st, double* vtrace, hipStream_t s);
+hipError_t launch_accumulate(const float* y, float* S, float* ybest, long long npix, DevState* st,
+                             hipStream_t s);
+hipError_t launch_finalize(const float* y, const float* S, const float* ybest, const float* lohi,
+                           float* out, long long npix, const DevState* st, hipStream_t s);
+hipError_t launch_adam(float* theta, float* m, float* v, float* g, const float* part,
+                       const float* ginj, const ParamTable& pt, float lr, double beta1,
+                       double beta2, float eps, float* fwd, float* bwd, uint16_t* fwd16,
+                       uint16_t* bwd16, DevState* st, hipStream_t s);
+hipError_t launch_extract(const float* src, int h, int w, int C, float* out_chw, hipStream_t s);
+
+}  // namespace n2f

@@ -1,0 +1,264 @@
+"""ctypes binding of libn2f.so (include/n2f.h), the Noise2Fast GPU library.
+
+Argument marshalling only: every step of the loop runs in the HIP library.
+PyTorch supplies device memory (images, the workspace) and the stream.
+Importing this module does not load the library; the first call does, and
+raises if it has not been built (``python -m paper_2108_10209_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_float, c_int, c_longlong, c_size_t, c_ulonglong, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libn2f.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
+WCONSTANT, WCAPPED = 1, 2
+FP32, BF16 = 0, 1
+
+SYMBOLS = [
+    "n2f_config_default", "n2f_last_error", "n2f_param_count", "n2f_init_params", "n2f_workspace_bytes",
+    "n2f_run_create", "n2f_run_destroy", "n2f_train_step", "n2f_validate", "n2f_run_epochs", "n2f_result",
+    "n2f_denoise", "n2f_get_state", "n2f_set_state", "n2f_get_grad", "n2f_debug_adam", "n2f_get_progress",
+    "n2f_get_history", "n2f_get_lohi", "n2f_get_image", "n2f_profile_begin", "n2f_profile_read",
+    "n2f_profile_end",
+]
+K_CONV_FWD, K_CONV_BWD, K_WGRAD = 0, 1, 2
+
+
+class N2FError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"n2f error {code}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("n_layers", c_int), ("width", c_int),
+        ("lr", c_float), ("beta1", c_float), ("beta2", c_float), ("eps", c_float),
+        ("patience", c_int), ("max_epochs", c_int), ("fixed_epochs", c_int),
+        ("pair_order", c_int * 4), ("precision", c_int), ("init_seed", c_ulonglong),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2108_10209_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.n2f_config_default.restype = None
+        L.n2f_config_default.argtypes = [POINTER(Config)]
+        L.n2f_last_error.restype = ctypes.c_char_p
+        L.n2f_last_error.argtypes = []
+        sig = {
+            "n2f_param_count": [c_int, POINTER(Config), POINTER(c_size_t)],
+            "n2f_init_params": [c_int, POINTER(Config), c_ulonglong, c_void_p],
+            "n2f_workspace_bytes": [c_int, c_int, c_int, POINTER(Config), POINTER(c_size_t)],
+            "n2f_run_create": [POINTER(c_void_p), c_void_p, c_int, c_int, c_int, POINTER(Config), c_void_p,
+                               c_size_t, c_void_p],
+            "n2f_run_destroy": [c_void_p],
+            "n2f_train_step": [c_void_p, c_int, c_int],
+            "n2f_validate": [c_void_p, c_int, POINTER(c_double), POINTER(c_int), POINTER(c_int)],
+            "n2f_run_epochs": [c_void_p, c_int, c_int, POINTER(c_int)],
+            "n2f_result": [c_void_p, c_void_p],
+            "n2f_denoise": [c_void_p, c_void_p, c_int, c_int, c_int, POINTER(Config), c_void_p, c_size_t,
+                            c_void_p],
+            "n2f_get_state": [c_void_p, c_int, c_void_p, c_void_p, c_void_p, POINTER(c_longlong)],
+            "n2f_set_state": [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_longlong],
+            "n2f_get_grad": [c_void_p, c_int, c_void_p, POINTER(c_double)],
+            "n2f_debug_adam": [c_void_p, c_int, c_void_p],
+            "n2f_get_progress": [c_void_p, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int),
+                                 POINTER(c_double)],
+            "n2f_get_history": [c_void_p, c_int, c_int, c_void_p],
+            "n2f_get_lohi": [c_void_p, POINTER(c_float), POINTER(c_float)],
+            "n2f_get_image": [c_void_p, c_int, c_void_p],
+            "n2f_profile_begin": [],
+            "n2f_profile_read": [c_int, POINTER(c_double), POINTER(c_longlong), POINTER(c_longlong)],
+            "n2f_profile_end": [],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.restype = c_int
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise N2FError(status, lib().n2f_last_error().decode(errors="replace"))
+    return status
+
+
+def default_config(**kw) -> Config:
+    cfg = Config()
+    lib().n2f_config_default(byref(cfg))
+    for k, v in kw.items():
+        if k == "pair_order":
+            cfg.pair_order = (c_int * 4)(*v)
+        else:
+            setattr(cfg, k, v)
+    return cfg
+
+
+def param_count(C: int, cfg: Config | None = None) -> int:
+    cfg = cfg or default_config()
+    n = c_size_t()
+    _check(lib().n2f_param_count(C, byref(cfg), byref(n)))
+    return n.value
+
+
+def init_params(C: int, seed: int, cfg: Config | None = None) -> np.ndarray:
+    cfg = cfg or default_config()
+    n = param_count(C, cfg)
+    out = np.empty((C, n), dtype=np.float32)
+    _check(lib().n2f_init_params(C, byref(cfg), c_ulonglong(seed), out.ctypes.data))
+    return out
+
+
+def workspace_bytes(H: int, W: int, C: int, cfg: Config | None = None) -> int:
+    cfg = cfg or default_config()
+    n = c_size_t()
+    _check(lib().n2f_workspace_bytes(H, W, C, byref(cfg), byref(n)))
+    return n.value
+
+
+def _stream_of(t):
+    import torch
+    return c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+class Run:
+    """One image's run: create, step, validate, read results and state."""
+
+    def __init__(self, x, cfg: Config | None = None, ws=None):
+        import torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.dim() == 3 and x.is_contiguous()
+        self.cfg = cfg or default_config()
+        self.C, self.H, self.W = (int(s) for s in x.shape)
+        self.device = x.device
+        nbytes = workspace_bytes(self.H, self.W, self.C, self.cfg)
+        self.ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        assert self.ws.numel() >= nbytes
+        self.nparams = param_count(self.C, self.cfg)
+        self._ptr = c_void_p()
+        self.status = _check(lib().n2f_run_create(byref(self._ptr), c_void_p(x.data_ptr()), self.H, self.W, self.C,
+                                                  byref(self.cfg), c_void_p(self.ws.data_ptr()), nbytes,
+                                                  _stream_of(x)))
+
+    def close(self):
+        if self._ptr:
+            lib().n2f_run_destroy(self._ptr)
+            self._ptr = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def train_step(self, net: int, pair: int):
+        _check(lib().n2f_train_step(self._ptr, net, pair))
+
+    def validate(self, net: int = 0):
+        v, imp, done = c_double(), c_int(), c_int()
+        _check(lib().n2f_validate(self._ptr, net, byref(v), byref(imp), byref(done)))
+        return v.value, bool(imp.value), bool(done.value)
+
+    def run_epochs(self, net: int, max_now: int):
+        done = c_int()
+        st = _check(lib().n2f_run_epochs(self._ptr, net, max_now, byref(done)))
+        return bool(done.value), st
+
+    def result(self):
+        import torch
+        out = torch.empty((self.C, self.H, self.W), dtype=torch.float32, device=self.device)
+        _check(lib().n2f_result(self._ptr, c_void_p(out.data_ptr())))
+        return out
+
+    def get_state(self, net: int = 0):
+        th = np.empty(self.nparams, np.float32)
+        m = np.empty(self.nparams, np.float32)
+        v = np.empty(self.nparams, np.float32)
+        t = c_longlong()
+        _check(lib().n2f_get_state(self._ptr, net, th.ctypes.data, m.ctypes.data, v.ctypes.data, byref(t)))
+        return th, m, v, t.value
+
+    def set_state(self, net: int, theta, m=None, v=None, t: int = 0):
+        th = np.ascontiguousarray(theta, np.float32)
+        mm = None if m is None else np.ascontiguousarray(m, np.float32)
+        vv = None if v is None else np.ascontiguousarray(v, np.float32)
+        assert th.size == self.nparams
+        _check(lib().n2f_set_state(self._ptr, net, th.ctypes.data, None if mm is None else mm.ctypes.data,
+                                   None if vv is None else vv.ctypes.data, int(t)))
+
+    def get_grad(self, net: int = 0):
+        g = np.empty(self.nparams, np.float32)
+        loss = c_double()
+        _check(lib().n2f_get_grad(self._ptr, net, g.ctypes.data, byref(loss)))
+        return g, loss.value
+
+    def debug_adam(self, net: int, g):
+        gg = np.ascontiguousarray(g, np.float32)
+        _check(lib().n2f_debug_adam(self._ptr, net, gg.ctypes.data))
+
+    def progress(self, net: int = 0):
+        e, be, ns, best = c_int(), c_int(), c_int(), c_double()
+        _check(lib().n2f_get_progress(self._ptr, net, byref(e), byref(be), byref(ns), byref(best)))
+        return e.value, be.value, ns.value, best.value
+
+    def history(self, net: int = 0):
+        e = self.progress(net)[0]
+        out = np.empty(e, np.float64)
+        _check(lib().n2f_get_history(self._ptr, net, e, out.ctypes.data if e else None))
+        return out
+
+    def lohi(self):
+        lo, hi = c_float(), c_float()
+        _check(lib().n2f_get_lohi(self._ptr, byref(lo), byref(hi)))
+        return lo.value, hi.value
+
+    def image(self, which: int):
+        import torch
+        Hc, Wc = self.H - self.H % 2, self.W - self.W % 2
+        shapes = {0: (self.C, Hc, Wc // 2), 1: (self.C, Hc, Wc // 2), 2: (self.C, Hc // 2, Wc),
+                  3: (self.C, Hc // 2, Wc), 4: (self.C, self.H, self.W)}
+        shape = shapes.get(which, (self.H, self.W))
+        out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        _check(lib().n2f_get_image(self._ptr, which, c_void_p(out.data_ptr())))
+        return out
+
+
+def denoise(x, cfg: Config | None = None, ws=None):
+    """One-shot denoise of a (C, H, W) FP32 CUDA tensor; returns (y, status)."""
+    import torch
+    cfg = cfg or default_config()
+    C, H, W = (int(s) for s in x.shape)
+    nbytes = workspace_bytes(H, W, C, cfg)
+    ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    out = torch.empty_like(x)
+    st = _check(lib().n2f_denoise(c_void_p(x.data_ptr()), c_void_p(out.data_ptr()), H, W, C, byref(cfg),
+                                  c_void_p(ws.data_ptr()), nbytes, _stream_of(x)))
+    return out, st
+
+
+def profile_begin():
+    _check(lib().n2f_profile_begin())
+
+
+def profile_read(kernel_class: int):
+    """(total kernel ms, launches, pixels processed) for one kernel class."""
+    ms, n, px = c_double(), c_longlong(), c_longlong()
+    _check(lib().n2f_profile_read(kernel_class, byref(ms), byref(n), byref(px)))
+    return ms.value, n.value, px.value
+
+
+def profile_end():
+    _check(lib().n2f_profile_end())

@@ -1,0 +1,84 @@
+"""The C-ABI library loads, exports every symbol include/n2f.h declares, and
+its host-only entry points behave (no GPU needed for any of these)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2108_10209_amd import n2f, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "n2f.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(n2f.LIB_PATH), reason="libn2f.so not built")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(n2f_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_binding_symbols():
+    assert _declared() == sorted(n2f.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(n2f.LIB_PATH)
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_config_default_is_the_papers():
+    c = n2f.default_config()
+    assert (c.n_layers, c.width, c.patience) == (8, 64, 100)
+    assert abs(c.lr - 1e-3) < 1e-9 and abs(c.beta1 - 0.9) < 1e-7 and abs(c.beta2 - 0.999) < 1e-7
+    assert abs(c.eps - 1e-8) < 1e-15
+    assert list(c.pair_order) == [0, 1, 2, 3] and c.precision == n2f.FP32 and c.fixed_epochs == 0
+
+
+@pytest.mark.parametrize("C", [1, 3])
+def test_param_count(C):
+    assert n2f.param_count(C) == synth.n_params(C)
+
+
+@pytest.mark.parametrize("C,seed", [(1, 0), (3, 12345), (1, 2 ** 63 + 7)])
+def test_library_init_equals_generator(C, seed):
+    """The library's built-in initial weights are the generator's, bit for
+    bit: both implement SplitMix64 from its published definition."""
+    a = n2f.init_params(C, seed)
+    b = synth.init_params(C, seed)
+    assert a.dtype == b.dtype == np.float32
+    np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_workspace_bytes_scales_and_rejects():
+    small = n2f.workspace_bytes(64, 64, 1)
+    big = n2f.workspace_bytes(512, 512, 1)
+    assert 0 < small < big
+    assert n2f.workspace_bytes(512, 512, 3) > big
+    # activation stash of 8 layers x 64 channels x P pixels dominates
+    assert big >= 8 * 64 * (512 * 256) * 4
+    for H, W, C in [(1, 8, 1), (8, 1, 1), (8, 8, 0), (8, 8, 4)]:
+        with pytest.raises(n2f.N2FError) as e:
+            n2f.workspace_bytes(H, W, C)
+        assert e.value.code == n2f.EINVAL
+
+
+def test_config_validation():
+    for kw in [dict(n_layers=7), dict(width=32), dict(lr=0.0), dict(beta1=1.0), dict(patience=0),
+               dict(max_epochs=0), dict(pair_order=(0, 0, 1, 2)), dict(precision=7)]:
+        with pytest.raises(n2f.N2FError) as e:
+            n2f.workspace_bytes(8, 8, 1, n2f.default_config(**kw))
+        assert e.value.code == n2f.EINVAL
+
+
+def test_null_arguments_rejected_without_device():
+    L = n2f.lib()
+    cfg = n2f.default_config()
+    run = ctypes.c_void_p()
+    st = L.n2f_run_create(ctypes.byref(run), None, 8, 8, 1, ctypes.byref(cfg), None, 0, None)
+    assert st == n2f.EINVAL and b"NULL" in L.n2f_last_error()
+    assert L.n2f_train_step(None, 0, 0) == n2f.EINVAL
+    assert L.n2f_result(None, None) == n2f.EINVAL
