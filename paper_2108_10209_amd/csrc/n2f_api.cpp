@@ -144,7 +144,6 @@ n2f_status check_cfg(const n2f_config* cfg) {
     if (cfg->patience < 1 || cfg->max_epochs < 1 || cfg->fixed_epochs < 0)
         return fail(N2F_EINVAL, "patience and max_epochs must be >= 1, fixed_epochs >= 0");
     if (cfg->precision != N2F_FP32 && cfg->precision != N2F_BF16) return fail(N2F_EINVAL, "unknown precision");
-    if (cfg->precision == N2F_BF16) return fail(N2F_EINVAL, "BF16 precision is not built yet");
     int seen[4] = {0, 0, 0, 0};
     for (int i = 0; i < 4; ++i) {
         if (cfg->pair_order[i] < 0 || cfg->pair_order[i] > 3 || seen[cfg->pair_order[i]]++)
@@ -232,7 +231,7 @@ n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
     q.o_part = o;
     o += align_up(sizeof(float) * partial_floats(q.pt));
     q.o_lpart = o;
-    o += align_up(sizeof(double) * kMaxSplit);
+    o += align_up(sizeof(double) * kMaxHeadSplit);
     q.o_vpart = o;
     o += align_up(sizeof(double) * 1024);
     q.bytes = o;

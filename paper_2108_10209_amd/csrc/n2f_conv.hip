@@ -182,12 +182,237 @@ __global__ __launch_bounds__(256) void k_wgrad_f32(const float* __restrict__ src
     if (threadIdx.x < kWidth) pp[kConvW + threadIdx.x] = dbacc;
 }
 
+// ===========================================================================
+// BF16 path: operands in BF16 (round to nearest even), FP32 accumulation on
+// the 16x16x32 BF16 MFMA.  A lane supplies 8 consecutive K values of one row
+// (A) or column (B); the MFMA sums over the 32 K values of the 4 lane groups.
+// ===========================================================================
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kHSb = 72;   // LDS bf16 per staged pixel (144 B: 8 lanes of a 16-byte read hit 32 banks)
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+// MODE 0: forward, bias + ReLU.  MODE 1: data gradient masked by [a > 0].
+// 16x16 pixel tile per 256-thread block, halo staged pixel-major in LDS;
+// wave wv computes tile rows 4wv..4wv+3 x 64 channels (4x4 MFMA tiles).
+// The result goes back through LDS so each pixel's 64 channels leave as
+// one 128-byte row.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv_bf16(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
+                                                   const float* __restrict__ bias, const uint16_t* __restrict__ mask,
+                                                   uint16_t* __restrict__ out, int h, int w, const DevState* st) {
+    if (finished(st)) return;
+    __shared__ __attribute__((aligned(16))) uint16_t halo[kHalo * kHalo * kHSb];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    for (int idx = threadIdx.x; idx < kHalo * kHalo * 8; idx += 256) {
+        const int pix = idx >> 3, q = idx & 7;
+        const int hy = pix / kHalo, hx = pix - hy * kHalo;
+        const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gy >= 0 && gy < h && gx >= 0 && gx < w)
+            v = *reinterpret_cast<const uint4*>(in + ((long long)gy * w + gx) * kWidth + 8 * q);
+        *reinterpret_cast<uint4*>(halo + pix * kHSb + 8 * q) = v;
+    }
+    __syncthreads();
+
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    // iteration it = 2t + kc covers tap t, channels 32kc..32kc+31; B fragment
+    // (8 channels 8(4kc+g).. of output column 16j+n) at wpk8[(4 it + g) * 64 + 16 j + n].
+    const bf16x8* wp = reinterpret_cast<const bf16x8*>(wpk) + g * 64 + n;
+    bf16x8 bn[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bn[j] = wp[16 * j];
+    for (int it = 0; it < 2 * kTaps; ++it) {
+        const int t = it >> 1, kc = it & 1;
+        bf16x8 b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = bn[j];
+        if (it + 1 < 2 * kTaps) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bn[j] = wp[(4 * (it + 1)) * 64 + 16 * j];
+        }
+        const int dy = t / 3, dx = t - 3 * (t / 3);
+        const uint16_t* hrow = halo + ((4 * wv + dy) * kHalo + n + dx) * kHSb + 32 * kc + 8 * g;
+        bf16x8 a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8*>(hrow + i * kHalo * kHSb);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();   // halo no longer read: reuse it for the output tile
+
+    // D row (pixel x) = 4g + r, column (channel) = 16j + n.
+    uint16_t* ot = halo;   // [256 tile pixels][kHSb]
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int co = 16 * j + n;
+            const float bv = (MODE == 0) ? bias[co] : 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = acc[i][j][r];
+                if (MODE == 0) v = fmaxf(v + bv, 0.f);
+                ot[((4 * wv + i) * kTile + 4 * g + r) * kHSb + co] = bf16_rne(v);
+            }
+        }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kTile * kTile * 8; idx += 256) {
+        const int p = idx >> 3, q = idx & 7;
+        const int gy = y0 + (p >> 4), gx = x0 + (p & 15);
+        if (gy >= h || gx >= w) continue;
+        const long long o = ((long long)gy * w + gx) * kWidth + 8 * q;
+        uint4 v = *reinterpret_cast<const uint4*>(ot + p * kHSb + 8 * q);
+        if (MODE == 1) {
+            const uint4 mk = *reinterpret_cast<const uint4*>(mask + o);
+            // keep a 16-bit lane where the mask value is > 0 (sign clear, not zero)
+            auto sel = [](uint32_t val, uint32_t m) {
+                uint32_t keep = 0;
+                if ((m & 0x8000u) == 0 && (m & 0x7fffu) != 0) keep |= 0xffffu;
+                if ((m & 0x80000000u) == 0 && (m & 0x7fff0000u) != 0) keep |= 0xffff0000u;
+                return val & keep;
+            };
+            v.x = sel(v.x, mk.x);
+            v.y = sel(v.y, mk.y);
+            v.z = sel(v.z, mk.z);
+            v.w = sel(v.w, mk.w);
+        }
+        *reinterpret_cast<uint4*>(out + o) = v;
+    }
+}
+
+// BF16 weight gradient of a 64->64 layer.  GEMM view as in the FP32 kernel
+// (M = (t, ci), N = co, K = pixels) but a K group is 8 consecutive pixels,
+// so both operands are staged channel-major: the source halo as three
+// copies shifted by the tap column dx (so every 8-pixel run starts 16-byte
+// aligned), the delta tile transposed.  Channel strides are padded so the 8
+// lanes of a 16-byte LDS read cover all 32 banks.
+constexpr int kSrcCS = 296;   // bf16 per channel of a shifted source copy (18 rows x 16 + pad)
+constexpr int kDltCS = 264;   // bf16 per channel of the transposed delta tile (256 + pad)
+
+__global__ __launch_bounds__(256) void k_wgrad_bf16(const uint16_t* __restrict__ src, const uint16_t* __restrict__ dlt,
+                                                    float* __restrict__ part, int h, int w, const DevState* st) {
+    if (finished(st)) return;
+    __shared__ __attribute__((aligned(16))) uint16_t sx[3 * kWidth * kSrcCS];
+    __shared__ __attribute__((aligned(16))) uint16_t sd[kWidth * kDltCS];
+    __shared__ float dbs[4][kWidth];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    const int tiles_x = (w + kTile - 1) / kTile, tiles_y = (h + kTile - 1) / kTile;
+    const int ntiles = tiles_x * tiles_y;
+
+    floatx4 acc[9][4];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float dbacc = 0.f;
+
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
+        // source halo, 18 x 18 pixels, into the three dx-shifted copies
+        for (int idx = threadIdx.x; idx < kHalo * kHalo * 8; idx += 256) {
+            const int pix = idx >> 3, q = idx & 7;
+            const int hy = pix / kHalo, hx = pix - hy * kHalo;
+            const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (gy >= 0 && gy < h && gx >= 0 && gx < w)
+                v = *reinterpret_cast<const uint4*>(src + ((long long)gy * w + gx) * kWidth + 8 * q);
+            const uint16_t e[8] = {(uint16_t)v.x, (uint16_t)(v.x >> 16), (uint16_t)v.y, (uint16_t)(v.y >> 16),
+                                   (uint16_t)v.z, (uint16_t)(v.z >> 16), (uint16_t)v.w, (uint16_t)(v.w >> 16)};
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int xs = hx - dx;
+                if (xs < 0 || xs >= kTile) continue;
+                uint16_t* d = sx + (dx * kWidth + 8 * q) * kSrcCS + hy * kTile + xs;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) d[c * kSrcCS] = e[c];
+            }
+        }
+        // delta tile, transposed
+        for (int idx = threadIdx.x; idx < kTile * kTile * 8; idx += 256) {
+            const int p = idx >> 3, q = idx & 7;
+            const int gy = y0 + (p >> 4), gx = x0 + (p & 15);
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (gy < h && gx < w) v = *reinterpret_cast<const uint4*>(dlt + ((long long)gy * w + gx) * kWidth + 8 * q);
+            const uint16_t e[8] = {(uint16_t)v.x, (uint16_t)(v.x >> 16), (uint16_t)v.y, (uint16_t)(v.y >> 16),
+                                   (uint16_t)v.z, (uint16_t)(v.z >> 16), (uint16_t)v.w, (uint16_t)(v.w >> 16)};
+            uint16_t* d = sd + (8 * q) * kDltCS + p;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) d[c * kDltCS] = e[c];
+        }
+        __syncthreads();
+        {
+            const int co = threadIdx.x & 63, pg = threadIdx.x >> 6;
+            float s = 0.f;
+            for (int p = pg * 64; p < pg * 64 + 64; ++p) s += bf16_f(sd[co * kDltCS + p]);
+            dbs[pg][co] = s;
+        }
+        for (int kk = 0; kk < 8; ++kk) {
+            // K group of lane group g: pixels 32kk + 8g .. +7 = row 2kk + g/2, columns 8(g%2)..
+            const int py = 2 * kk + (g >> 1), px0 = 8 * (g & 1);
+            bf16x8 b[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(sd + (16 * j + n) * kDltCS + 32 * kk + 8 * g);
+#pragma unroll
+            for (int ib = 0; ib < 9; ++ib) {
+                const int mb = 9 * wv + ib;
+                const int t = mb >> 2, ci0 = (mb & 3) * 16;
+                const int dy = t / 3, dx = t - 3 * (t / 3);
+                const bf16x8 a =
+                    *reinterpret_cast<const bf16x8*>(sx + (dx * kWidth + ci0 + n) * kSrcCS + (py + dy) * kTile + px0);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[ib][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[ib][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < kWidth)
+            dbacc += ((dbs[0][threadIdx.x] + dbs[1][threadIdx.x]) + dbs[2][threadIdx.x]) + dbs[3][threadIdx.x];
+    }
+
+    float* pp = part + (long long)blockIdx.x * kConvN;
+#pragma unroll
+    for (int ib = 0; ib < 9; ++ib) {
+        const int mb = 9 * wv + ib;
+        const int t = mb >> 2, ci0 = (mb & 3) * 16;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pp[(t * 64 + ci0 + 4 * g + r) * 64 + 16 * j + n] = acc[ib][j][r];
+    }
+    if (threadIdx.x < kWidth) pp[kConvW + threadIdx.x] = dbacc;
+}
+
 }  // namespace
 
 hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, void* out, int bf16, int h, int w,
                            const DevState* st, hipStream_t s) {
-    if (bf16) return hipErrorNotSupported;
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
+    if (bf16) {
+        hipLaunchKernelGGL(k_conv_bf16<0>, grid, dim3(256), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
+                           (const uint16_t*)nullptr, (uint16_t*)out, h, w, st);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_conv_f32<0>, grid, dim3(256), 0, s, (const float*)in, (const float*)wpk, bias,
                        (const float*)nullptr, (float*)out, h, w, st);
     return hipGetLastError();
@@ -195,8 +420,12 @@ hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, v
 
 hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, void* out, int bf16, int h, int w,
                            const DevState* st, hipStream_t s) {
-    if (bf16) return hipErrorNotSupported;
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
+    if (bf16) {
+        hipLaunchKernelGGL(k_conv_bf16<1>, grid, dim3(256), 0, s, (const uint16_t*)dlt, (const uint16_t*)wpk,
+                           (const float*)nullptr, (const uint16_t*)mask, (uint16_t*)out, h, w, st);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_conv_f32<1>, grid, dim3(256), 0, s, (const float*)dlt, (const float*)wpk,
                        (const float*)nullptr, (const float*)mask, (float*)out, h, w, st);
     return hipGetLastError();
@@ -209,7 +438,11 @@ int wgrad_splits(int h, int w) {
 
 hipError_t launch_wgrad(const void* src, const void* dlt, float* part, int nsplit, int bf16, int h, int w,
                         const DevState* st, hipStream_t s) {
-    if (bf16) return hipErrorNotSupported;
+    if (bf16) {
+        hipLaunchKernelGGL(k_wgrad_bf16, dim3(nsplit), dim3(256), 0, s, (const uint16_t*)src, (const uint16_t*)dlt,
+                           part, h, w, st);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_wgrad_f32, dim3(nsplit), dim3(256), 0, s, (const float*)src, (const float*)dlt, part, h, w,
                        st);
     return hipGetLastError();

@@ -15,6 +15,7 @@ constexpr int kConvW = kTaps * kWidth * kWidth;   // weights of a 64->64 layer
 constexpr int kConvN = kConvW + kWidth;           // ... plus its bias
 constexpr int kHeadN = kWidth + 1;                // 1x1 head: 64 weights + bias
 constexpr int kMaxSplit = 256;                    // max pixel splits of a weight gradient
+constexpr int kMaxHeadSplit = 1024;               // max blocks of the training head
 
 // Per-network state that lives in device memory.  The stopping rule is
 // decided on the device so that whole epochs can be queued without a host

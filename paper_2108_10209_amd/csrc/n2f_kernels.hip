@@ -498,19 +498,32 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, floa
                                                  float* fwd, float* bwd, uint16_t* fwd16, uint16_t* bwd16,
                                                  DevState* st) {
     if (finished(st)) return;
+    // 32 parameters per block; 8 lanes per parameter each sum every 8th
+    // split, then the 8 lane sums are added in lane order (fixed order,
+    // so the result does not depend on scheduling).
+    __shared__ float red[8][33];
     const long long t_new = st->t + 1;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < pt.total) {
+    const int p = threadIdx.x & 31, j = threadIdx.x >> 5;
+    const int i = blockIdx.x * 32 + p;
+    if (i < pt.total && !ginj) {
+        const int l = layer_of(pt, i);
+        const int il = i - pt.off[l];
+        const float* pp = part + pt.poff[l] + il;
+        float s = 0.f;
+        for (int sp = j; sp < pt.split[l]; sp += 8) s += pp[(long long)sp * pt.n[l]];
+        red[j][p] = s;
+    }
+    __syncthreads();
+    if (j == 0 && i < pt.total) {
         const int l = layer_of(pt, i);
         const int il = i - pt.off[l];
         float gi;
         if (ginj) {
             gi = ginj[i];
         } else {
-            const float* pp = part + pt.poff[l] + il;
-            float s = 0.f;
-            for (int sp = 0; sp < pt.split[l]; ++sp) s += pp[(long long)sp * pt.n[l]];
-            gi = s;
+            gi = red[0][p];
+#pragma unroll
+            for (int k = 1; k < 8; ++k) gi += red[k][p];
         }
         g[i] = gi;
         const float b1 = (float)beta1, b2 = (float)beta2;
@@ -585,8 +598,8 @@ hipError_t launch_wgrad1(const float* in, int C, const void* dlt, float* part, i
 }
 
 int head_splits(long long npix) {
-    long long b = (npix + 1023) / 1024;
-    return (int)std::max(1LL, std::min(b, (long long)kMaxSplit));
+    long long b = (npix + 255) / 256;
+    return (int)std::max(1LL, std::min(b, (long long)kMaxHeadSplit));
 }
 
 hipError_t launch_head_train(const void* a8, const float* tgt, int C, int k, const float* w9, const float* b9,
@@ -622,7 +635,7 @@ hipError_t launch_finalize(const float* y, const float* S, const float* ybest, c
 hipError_t launch_adam(float* theta, float* m, float* v, float* g, const float* part, const float* ginj,
                        const ParamTable& pt, float lr, double beta1, double beta2, float eps, float* fwd,
                        float* bwd, uint16_t* fwd16, uint16_t* bwd16, DevState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_adam, dim3(nblocks(pt.total, kBlock)), dim3(kBlock), 0, s, theta, m, v, g, part, ginj, pt,
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(pt.total, 32)), dim3(kBlock), 0, s, theta, m, v, g, part, ginj, pt,
                        lr, beta1, beta2, eps, fwd, bwd, fwd16, bwd16, st);
     return hipGetLastError();
 }
