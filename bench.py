@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--max-epochs", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-every", type=int, default=8,
+                    help="time one launch in N of each conv kernel class with HIP events")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a plain copy of known size, to scale HBM counters)")
     args = ap.parse_args()
@@ -116,7 +118,7 @@ def main():
         step(i)
         print(f"warmup {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    n2f.profile_begin()
+    n2f.profile_begin(args.profile_every)
     t0 = time.perf_counter()
     outs = []
     for i in range(args.steps):

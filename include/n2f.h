@@ -64,20 +64,22 @@ typedef struct n2f_config {
     int    n_layers;          /* 3x3 conv layers; only 8 is supported */
     int    width;             /* channels per conv layer; only 64 is supported */
     float  lr;                /* Adam step size (Methods: 1e-3) */
-    float  beta1, beta2, eps; /* Adam moments and epsilon (Kingma and Ba defaults) */
+    float  eps;               /* Adam epsilon (Kingma and Ba default 1e-8) */
+    double beta1, beta2;      /* Adam moment decays (0.9, 0.999); double so that 1 - beta is exact to FP32 */
     int    patience;          /* epochs without a new best before stopping (Methods: 100) */
     int    max_epochs;        /* safety cap (not in the paper); >= 1 */
     int    fixed_epochs;      /* > 0: run exactly this many epochs, output the last validation output */
     int    pair_order[4];     /* order of the four training pairs within an epoch */
     int    precision;         /* N2F_FP32 or N2F_BF16 */
     unsigned long long init_seed; /* SplitMix64 seed of the initial weights */
+    int    use_graph;         /* n2f_run_epochs replays one recorded HIP graph per epoch */
 } n2f_config;
 
 typedef struct n2f_run n2f_run;
 
 /* Fill *cfg with the paper's settings: 8 layers of width 64, Adam lr 1e-3,
  * betas 0.9/0.999, eps 1e-8, patience 100, max_epochs 2000, early stopping,
- * pairs in table order, FP32, seed 0. */
+ * pairs in table order, FP32, seed 0, epochs replayed as HIP graphs. */
 void n2f_config_default(n2f_config* cfg);
 
 /* Message describing the calling thread's most recent error ("" if none). */
@@ -186,18 +188,18 @@ n2f_status n2f_get_lohi(n2f_run* run, float* lo, float* hi);
 n2f_status n2f_get_image(n2f_run* run, int which, float* d_out);
 
 /* ---- kernel timing ----
- * While profiling is on, every launch of the instrumented kernel classes is
- * bracketed by HIP events on the stream it runs on.  Classes:
+ * While profiling is on, one launch in `every` of each instrumented kernel
+ * class is bracketed by HIP events on the stream it runs on.  Classes:
  * N2F_K_CONV_FWD (64->64 forward, training and validation), N2F_K_CONV_BWD
  * (64->64 data gradient), N2F_K_WGRAD (64->64 weight gradient).
  * n2f_profile_begin clears earlier records; n2f_profile_read synchronises
  * the recorded events and returns, for one class, the summed kernel time,
- * the number of launches and the pixels those launches processed.
+ * the number of recorded launches and the pixels those launches processed.
  * Process-wide; not thread-safe. */
 #define N2F_K_CONV_FWD 0
 #define N2F_K_CONV_BWD 1
 #define N2F_K_WGRAD    2
-n2f_status n2f_profile_begin(void);
+n2f_status n2f_profile_begin(int every);
 n2f_status n2f_profile_read(int kernel_class, double* total_ms, long long* launches, long long* pixels);
 n2f_status n2f_profile_end(void);
 

@@ -69,6 +69,7 @@ ParamTable make_table(int C, int nsplit, int hsplit) {
         pt.off[l] = off;
         pt.n[l] = (l < kLayers) ? kTaps * cin * kWidth + kWidth : kHeadN;
         pt.split[l] = (l < kLayers) ? nsplit : hsplit;
+        pt.reduced[l] = 0;
         pt.poff[l] = poff;
         off += pt.n[l];
         poff += (long long)pt.split[l] * pt.n[l];
@@ -138,7 +139,7 @@ n2f_status check_cfg(const n2f_config* cfg) {
     if (!cfg) return fail(N2F_EINVAL, "config is NULL");
     if (cfg->n_layers != kLayers || cfg->width != kWidth)
         return fail(N2F_EINVAL, "only 8 layers of width 64 are supported");
-    if (!(cfg->lr > 0.f) || !(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) || !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f) ||
+    if (!(cfg->lr > 0.f) || !(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0) || !(cfg->beta2 >= 0.0 && cfg->beta2 < 1.0) ||
         !(cfg->eps > 0.f))
         return fail(N2F_EINVAL, "bad Adam hyper-parameters");
     if (cfg->patience < 1 || cfg->max_epochs < 1 || cfg->fixed_epochs < 0)
@@ -172,7 +173,7 @@ n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
     q.nsplit = std::max(wgrad_splits(q.hu, q.wu), wgrad_splits(q.hl, q.wl));
     q.hsplit = head_splits(q.P);
     const long long HW = (long long)H * W;
-    q.vblk = (int)std::max(1LL, std::min((HW + 1023) / 1024, 1024LL));
+    q.vblk = (int)std::max(1LL, std::min((HW + 255) / 256, 1024LL));
     q.mmblk = (int)std::max(1LL, std::min((HW * C + 4095) / 4096, 1024LL));
     q.max_trace = std::max(cfg->max_epochs, cfg->fixed_epochs) + 1;
     q.pt = make_table(C, q.nsplit, q.hsplit);
@@ -247,6 +248,9 @@ struct ProfRec {
 };
 struct Profiler {
     bool on = false;
+    bool capturing = false;
+    int every = 1;             // time every launch of one epoch in `every`
+    long long epochs = 0;
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
@@ -263,7 +267,7 @@ hipEvent_t prof_event() {
 
 template <class F>
 hipError_t timed(int cls, long long npix, hipStream_t s, F&& f) {
-    if (!g_prof.on) return f();
+    if (!g_prof.on || g_prof.capturing) return f();
     hipEvent_t a = prof_event(), b = prof_event();
     if (!a || !b) return hipErrorOutOfMemory;
     hipError_t e = hipEventRecord(a, s);
@@ -306,7 +310,9 @@ struct n2f_run {
     double* vpart;
     bool host_done[3];
     int host_epochs[3];
-    std::vector<float> staging;
+    hipStream_t cap_stream;          // private stream used only to record graphs
+    hipGraph_t graph[3];
+    hipGraphExec_t graph_exec[3];    // one captured epoch per network
 };
 
 namespace {
@@ -378,13 +384,15 @@ n2f_status enqueue_train_step(n2f_run* r, int k, int pair) {
                                 N.st, s);
         }));
         N2F_HIP(timed(N2F_K_CONV_BWD, (long long)npix, s, [&] {
-            return launch_conv_bwd(r->dlt[cur], bwdpk(l), act_layer(r, l - 1, npix), r->dlt[1 - cur], bf, h, w, N.st, s);
+            return launch_conv_bwd(r->dlt[cur], bwdpk(l), act_layer(r, l - 1, npix), r->dlt[1 - cur], bf, h, w, N.st,
+                                   nullptr, 0, nullptr, s);
         }));
         cur = 1 - cur;
     }
     N2F_HIP(launch_wgrad1(in, pl.C, r->dlt[cur], r->part + pt.poff[0], pt.split[0], bf, h, w, N.st, s));
-    N2F_HIP(launch_adam(N.theta, N.m, N.v, N.g, r->part, nullptr, pt, r->cfg.lr, (double)r->cfg.beta1,
-                        (double)r->cfg.beta2, r->cfg.eps, N.fwd, N.bwd, N.fwd16, N.bwd16, N.st, s));
+    N2F_HIP(launch_adam(N.theta, N.m, N.v, N.g, r->part, nullptr, pt, r->cfg.lr, r->cfg.beta1,
+                        r->cfg.beta2, r->cfg.eps, N.fwd, N.bwd, N.fwd16, N.bwd16, r->lpart,
+                        pt.split[kLayers], (long long)npix, N.st, s));
     return N2F_OK;
 }
 
@@ -416,6 +424,45 @@ n2f_status read_state(n2f_run* r, int k, DevState* out) {
     return N2F_OK;
 }
 
+n2f_status enqueue_epoch(n2f_run* r, int k) {
+    for (int i = 0; i < 4; ++i) {
+        n2f_status s = enqueue_train_step(r, k, r->cfg.pair_order[i]);
+        if (s != N2F_OK) return s;
+    }
+    return enqueue_validate(r, k);
+}
+
+// Record one epoch of network k (four steps and the validation) as a graph.
+// Every kernel reads its state from device memory and returns at once when
+// the network is finished, so the same graph is replayed every epoch.
+n2f_status capture_epoch(n2f_run* r, int k) {
+    if (!r->cap_stream) N2F_HIP(hipStreamCreateWithFlags(&r->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = r->stream;
+    r->stream = r->cap_stream;
+    g_prof.capturing = true;
+    hipError_t e = hipStreamBeginCapture(r->cap_stream, hipStreamCaptureModeRelaxed);
+    n2f_status s = N2F_OK;
+    if (e == hipSuccess) s = enqueue_epoch(r, k);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = (e == hipSuccess) ? hipStreamEndCapture(r->cap_stream, &g) : e;
+    g_prof.capturing = false;
+    r->stream = user;
+    if (e != hipSuccess || e2 != hipSuccess || s != N2F_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        if (s != N2F_OK) return s;
+        return fail(N2F_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(N2F_EDEVICE, std::string("graph instantiate failed: ") + hipGetErrorString(e));
+    }
+    r->graph[k] = g;
+    r->graph_exec[k] = ex;
+    return N2F_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -426,8 +473,8 @@ void n2f_config_default(n2f_config* cfg) {
     cfg->n_layers = kLayers;
     cfg->width = kWidth;
     cfg->lr = 1e-3f;
-    cfg->beta1 = 0.9f;
-    cfg->beta2 = 0.999f;
+    cfg->beta1 = 0.9;
+    cfg->beta2 = 0.999;
     cfg->eps = 1e-8f;
     cfg->patience = 100;
     cfg->max_epochs = 2000;
@@ -435,6 +482,7 @@ void n2f_config_default(n2f_config* cfg) {
     for (int i = 0; i < 4; ++i) cfg->pair_order[i] = i;
     cfg->precision = N2F_FP32;
     cfg->init_seed = 0;
+    cfg->use_graph = 1;
 }
 
 const char* n2f_last_error(void) { return g_err.c_str(); }
@@ -497,6 +545,11 @@ n2f_status n2f_run_create(n2f_run** out, const float* d_in, int H, int W, int C,
     r->ws = static_cast<char*>(d_ws);
     r->constant = false;
     r->in_keep = nullptr;
+    r->cap_stream = nullptr;
+    for (int k = 0; k < 3; ++k) {
+        r->graph[k] = nullptr;
+        r->graph_exec[k] = nullptr;
+    }
     char* b = r->ws;
     char* misc = b + pl.o_misc;
     r->lohi = at<float>(misc, 0);
@@ -588,6 +641,11 @@ n2f_status n2f_run_create(n2f_run** out, const float* d_in, int H, int W, int C,
 
 n2f_status n2f_run_destroy(n2f_run* r) {
     if (!r) return fail(N2F_EINVAL, "run is NULL");
+    for (int k = 0; k < 3; ++k) {
+        if (r->graph_exec[k]) (void)hipGraphExecDestroy(r->graph_exec[k]);
+        if (r->graph[k]) (void)hipGraphDestroy(r->graph[k]);
+    }
+    if (r->cap_stream) (void)hipStreamDestroy(r->cap_stream);
     delete r;
     return N2F_OK;
 }
@@ -622,18 +680,23 @@ n2f_status n2f_run_epochs(n2f_run* r, int net, int max_now, int* done) {
     n2f_status s = check_run(r, net);
     if (s != N2F_OK) return s;
     if (max_now < 1) return fail(N2F_EINVAL, "max_epochs_now must be >= 1");
+    if (r->cfg.use_graph && !r->graph_exec[net]) {
+        s = capture_epoch(r, net);
+        if (s != N2F_OK) return s;
+    }
     DevState st;
     int ran = 0;
     while (!r->host_done[net] && ran < max_now) {
         // queue a few epochs ahead, then poll the device-side stopping rule
         const int batch = std::min(max_now - ran, 4);
         for (int e = 0; e < batch; ++e) {
-            for (int i = 0; i < 4; ++i) {
-                s = enqueue_train_step(r, net, r->cfg.pair_order[i]);
+            const bool direct = !r->graph_exec[net] || (g_prof.on && (g_prof.epochs++ % g_prof.every) == 0);
+            if (direct) {
+                s = enqueue_epoch(r, net);
                 if (s != N2F_OK) return s;
+            } else {
+                N2F_HIP(hipGraphLaunch(r->graph_exec[net], r->stream));
             }
-            s = enqueue_validate(r, net);
-            if (s != N2F_OK) return s;
         }
         ran += batch;
         s = read_state(r, net, &st);
@@ -770,8 +833,9 @@ n2f_status n2f_debug_adam(n2f_run* r, int net, const float* g) {
     canon_to_internal(g, tmp.data(), r->pl.C, pt);
     // stage the injected gradient in the partial-sum buffer (unused between steps)
     N2F_HIP(hipMemcpyAsync(r->part, tmp.data(), sizeof(float) * pt.total, hipMemcpyHostToDevice, r->stream));
-    N2F_HIP(launch_adam(N.theta, N.m, N.v, N.g, r->part, r->part, pt, r->cfg.lr, (double)r->cfg.beta1,
-                        (double)r->cfg.beta2, r->cfg.eps, N.fwd, N.bwd, N.fwd16, N.bwd16, N.st, r->stream));
+    N2F_HIP(launch_adam(N.theta, N.m, N.v, N.g, r->part, r->part, pt, r->cfg.lr, r->cfg.beta1,
+                        r->cfg.beta2, r->cfg.eps, N.fwd, N.bwd, N.fwd16, N.bwd16, r->lpart, 0, 1, N.st,
+                        r->stream));
     N2F_HIP(hipStreamSynchronize(r->stream));
     return N2F_OK;
 }
@@ -827,9 +891,12 @@ n2f_status n2f_get_image(n2f_run* r, int which, float* d_out) {
     return N2F_OK;
 }
 
-n2f_status n2f_profile_begin(void) {
+n2f_status n2f_profile_begin(int every) {
+    if (every < 1) return fail(N2F_EINVAL, "every must be >= 1");
     g_prof.recs.clear();
     g_prof.used = 0;
+    g_prof.every = every;
+    g_prof.epochs = 0;
     g_prof.on = true;
     return N2F_OK;
 }

@@ -31,6 +31,37 @@ constexpr int kHS = 68;  // LDS floats per staged pixel
 
 __device__ __forceinline__ bool finished(const DevState* st) { return st != nullptr && st->done; }
 
+// Sum the `nsplit` per-split partials of one 64->64 layer's gradient
+// (kConvN values each) for this block's slice of the values, and write the
+// sums to g.  Run at the end of the data-gradient kernel of the same layer
+// (the weight-gradient kernel has completed), spreading the reduction over
+// that kernel's blocks.  Lane group j (of 8) adds splits j, j+8, ...; the 8
+// group sums are then added in group order, so the result is fixed.
+// `red` is LDS scratch of 8 * 33 floats.
+__device__ __forceinline__ void reduce_partials_slice(const float* __restrict__ part, int nsplit,
+                                                      float* __restrict__ g, float* red) {
+    const int nb = gridDim.x * gridDim.y;
+    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+    const int chunk = (kConvN + nb - 1) / nb;
+    const int lo = bid * chunk, hi = min(kConvN, lo + chunk);
+    const int q = threadIdx.x & 31, j = threadIdx.x >> 5;
+    for (int base = lo; base < hi; base += 32) {
+        const int i = base + q;
+        float sum = 0.f;
+        if (i < hi)
+            for (int sp = j; sp < nsplit; sp += 8) sum += part[(long long)sp * kConvN + i];
+        __syncthreads();
+        red[j * 33 + q] = sum;
+        __syncthreads();
+        if (j == 0 && i < hi) {
+            float tot = red[q];
+#pragma unroll
+            for (int k = 1; k < 8; ++k) tot += red[k * 33 + q];
+            g[i] = tot;
+        }
+    }
+}
+
 // Stage the (16+2)^2 x 64 halo around tile (x0, y0) of a channels-last FP32
 // activation into LDS, zero outside the image.
 __device__ __forceinline__ void stage_halo_f32(float* halo, const float* __restrict__ in, int x0, int y0, int h,
@@ -50,7 +81,9 @@ __device__ __forceinline__ void stage_halo_f32(float* halo, const float* __restr
 template <int MODE>
 __global__ __launch_bounds__(256) void k_conv_f32(const float* __restrict__ in, const float* __restrict__ wpk,
                                                   const float* __restrict__ bias, const float* __restrict__ mask,
-                                                  float* __restrict__ out, int h, int w, const DevState* st) {
+                                                  float* __restrict__ out, int h, int w, const DevState* st,
+                                                  const float* __restrict__ gpart, int nsplit,
+                                                  float* __restrict__ gout) {
     if (finished(st)) return;
     __shared__ __attribute__((aligned(16))) float halo[kHalo * kHalo * kHS];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -108,6 +141,7 @@ __global__ __launch_bounds__(256) void k_conv_f32(const float* __restrict__ in, 
             }
         }
     }
+    if (MODE == 1 && gpart) reduce_partials_slice(gpart, nsplit, gout, halo);
 }
 
 // Weight gradient of a 64->64 layer.  Block b accumulates tiles b, b + S,
@@ -208,7 +242,9 @@ __device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float(((u
 template <int MODE>
 __global__ __launch_bounds__(256) void k_conv_bf16(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
                                                    const float* __restrict__ bias, const uint16_t* __restrict__ mask,
-                                                   uint16_t* __restrict__ out, int h, int w, const DevState* st) {
+                                                   uint16_t* __restrict__ out, int h, int w, const DevState* st,
+                                                   const float* __restrict__ gpart, int nsplit,
+                                                   float* __restrict__ gout) {
     if (finished(st)) return;
     __shared__ __attribute__((aligned(16))) uint16_t halo[kHalo * kHalo * kHSb];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -297,27 +333,50 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const uint16_t* __restrict__ 
         }
         *reinterpret_cast<uint4*>(out + o) = v;
     }
+    if (MODE == 1 && gpart) reduce_partials_slice(gpart, nsplit, gout, reinterpret_cast<float*>(halo));
 }
 
 // BF16 weight gradient of a 64->64 layer.  GEMM view as in the FP32 kernel
-// (M = (t, ci), N = co, K = pixels) but a K group is 8 consecutive pixels,
-// so both operands are staged channel-major: the source halo as three
-// copies shifted by the tap column dx (so every 8-pixel run starts 16-byte
-// aligned), the delta tile transposed.  Channel strides are padded so the 8
-// lanes of a 16-byte LDS read cover all 32 banks.
-constexpr int kSrcCS = 296;   // bf16 per channel of a shifted source copy (18 rows x 16 + pad)
-constexpr int kDltCS = 264;   // bf16 per channel of the transposed delta tile (256 + pad)
+// (M = (t, ci) = 576, N = co = 64, K = pixels); a K group is 8 consecutive
+// tile pixels.  Both operands stay pixel-major in LDS (pixel stride 68 bf16,
+// 8-byte aligned rows) and are read with the gfx950 16-bit transpose load:
+// within a group of 16 lanes, row-lane r addresses pixel p0 + r/4 and
+// channels c0 + 4(r%4).., and lane L then holds channel c0 + L of pixels
+// p0..p0+3; two such loads give the 8 K values of an MFMA fragment.  A tap
+// shift is only a different row address.
+// The block has 8 waves in two groups of 4; each group stages and reduces
+// its own tiles in its own LDS buffers, and at the end the two groups'
+// sums are added (group 0 + group 1), so a block still writes one partial.
+constexpr int kPS = 68;                          // bf16 per staged pixel
+constexpr int kHaloB = kHalo * kHalo * kPS;      // bf16 per staged halo
+constexpr int kTileB = kTile * kTile * kPS;      // bf16 per staged delta tile
+constexpr int kGroupB = kHaloB + kTileB;         // bf16 per group buffer
 
-__global__ __launch_bounds__(256) void k_wgrad_bf16(const uint16_t* __restrict__ src, const uint16_t* __restrict__ dlt,
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+
+__device__ __forceinline__ bf16x8 tr16_frag(const uint16_t* p0, const uint16_t* p1) {
+    const bf16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
+        (lds_bf16x4*)((__attribute__((address_space(3))) uint16_t*)p0));
+    const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
+        (lds_bf16x4*)((__attribute__((address_space(3))) uint16_t*)p1));
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+__global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__ src, const uint16_t* __restrict__ dlt,
                                                     float* __restrict__ part, int h, int w, const DevState* st) {
     if (finished(st)) return;
-    __shared__ __attribute__((aligned(16))) uint16_t sx[3 * kWidth * kSrcCS];
-    __shared__ __attribute__((aligned(16))) uint16_t sd[kWidth * kDltCS];
-    __shared__ float dbs[4][kWidth];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int g = lane >> 4, n = lane & 15;
+    __shared__ __attribute__((aligned(16))) uint16_t buf[2 * kGroupB];
+    __shared__ float dbs[2][4][kWidth];
+    const int tid = threadIdx.x & 255, grp = threadIdx.x >> 8;
+    const int lane = threadIdx.x & 63, wq = tid >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    uint16_t* halo = buf + grp * kGroupB;
+    uint16_t* dt = halo + kHaloB;
     const int tiles_x = (w + kTile - 1) / kTile, tiles_y = (h + kTile - 1) / kTile;
     const int ntiles = tiles_x * tiles_y;
+    const int stride = 2 * gridDim.x;
+    const int iters = (ntiles - 2 * (int)blockIdx.x + stride - 1) / stride;   // same for both groups' loop
 
     floatx4 acc[9][4];
 #pragma unroll
@@ -326,81 +385,89 @@ __global__ __launch_bounds__(256) void k_wgrad_bf16(const uint16_t* __restrict__
         for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     float dbacc = 0.f;
 
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
-        // source halo, 18 x 18 pixels, into the three dx-shifted copies
-        for (int idx = threadIdx.x; idx < kHalo * kHalo * 8; idx += 256) {
+    for (int it = 0; it < iters; ++it) {
+        const int tile = 2 * blockIdx.x + grp + it * stride;
+        const bool have = tile < ntiles;
+        const int x0 = have ? (tile % tiles_x) * kTile : 0, y0 = have ? (tile / tiles_x) * kTile : 0;
+        for (int idx = tid; idx < kHalo * kHalo * 8; idx += 256) {
             const int pix = idx >> 3, q = idx & 7;
             const int hy = pix / kHalo, hx = pix - hy * kHalo;
             const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (gy >= 0 && gy < h && gx >= 0 && gx < w)
+            if (have && gy >= 0 && gy < h && gx >= 0 && gx < w)
                 v = *reinterpret_cast<const uint4*>(src + ((long long)gy * w + gx) * kWidth + 8 * q);
-            const uint16_t e[8] = {(uint16_t)v.x, (uint16_t)(v.x >> 16), (uint16_t)v.y, (uint16_t)(v.y >> 16),
-                                   (uint16_t)v.z, (uint16_t)(v.z >> 16), (uint16_t)v.w, (uint16_t)(v.w >> 16)};
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const int xs = hx - dx;
-                if (xs < 0 || xs >= kTile) continue;
-                uint16_t* d = sx + (dx * kWidth + 8 * q) * kSrcCS + hy * kTile + xs;
-#pragma unroll
-                for (int c = 0; c < 8; ++c) d[c * kSrcCS] = e[c];
-            }
+            uint2* d = reinterpret_cast<uint2*>(halo + pix * kPS + 8 * q);
+            d[0] = make_uint2(v.x, v.y);
+            d[1] = make_uint2(v.z, v.w);
         }
-        // delta tile, transposed
-        for (int idx = threadIdx.x; idx < kTile * kTile * 8; idx += 256) {
+        for (int idx = tid; idx < kTile * kTile * 8; idx += 256) {
             const int p = idx >> 3, q = idx & 7;
             const int gy = y0 + (p >> 4), gx = x0 + (p & 15);
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (gy < h && gx < w) v = *reinterpret_cast<const uint4*>(dlt + ((long long)gy * w + gx) * kWidth + 8 * q);
-            const uint16_t e[8] = {(uint16_t)v.x, (uint16_t)(v.x >> 16), (uint16_t)v.y, (uint16_t)(v.y >> 16),
-                                   (uint16_t)v.z, (uint16_t)(v.z >> 16), (uint16_t)v.w, (uint16_t)(v.w >> 16)};
-            uint16_t* d = sd + (8 * q) * kDltCS + p;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) d[c * kDltCS] = e[c];
+            if (have && gy < h && gx < w) v = *reinterpret_cast<const uint4*>(dlt + ((long long)gy * w + gx) * kWidth + 8 * q);
+            uint2* d = reinterpret_cast<uint2*>(dt + p * kPS + 8 * q);
+            d[0] = make_uint2(v.x, v.y);
+            d[1] = make_uint2(v.z, v.w);
         }
         __syncthreads();
         {
-            const int co = threadIdx.x & 63, pg = threadIdx.x >> 6;
-            float s = 0.f;
-            for (int p = pg * 64; p < pg * 64 + 64; ++p) s += bf16_f(sd[co * kDltCS + p]);
-            dbs[pg][co] = s;
+            const int co = tid & 63, pg = tid >> 6;
+            float sacc = 0.f;
+            for (int p = pg * 64; p < pg * 64 + 64; ++p) sacc += bf16_f(dt[p * kPS + co]);
+            dbs[grp][pg][co] = sacc;
         }
+        const int rp = r >> 2, rc = 4 * (r & 3);
         for (int kk = 0; kk < 8; ++kk) {
-            // K group of lane group g: pixels 32kk + 8g .. +7 = row 2kk + g/2, columns 8(g%2)..
-            const int py = 2 * kk + (g >> 1), px0 = 8 * (g & 1);
+            // row-lane pixels of the two halves: kappa = 32kk + 8g + 4h + rp
+            const int k0 = 32 * kk + 8 * g + rp, k1 = k0 + 4;
             bf16x8 b[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                b[j] = *reinterpret_cast<const bf16x8*>(sd + (16 * j + n) * kDltCS + 32 * kk + 8 * g);
+            for (int j = 0; j < 4; ++j) b[j] = tr16_frag(dt + k0 * kPS + 16 * j + rc, dt + k1 * kPS + 16 * j + rc);
+            const int py0 = k0 >> 4, px0 = k0 & 15, py1 = k1 >> 4, px1 = k1 & 15;
 #pragma unroll
             for (int ib = 0; ib < 9; ++ib) {
-                const int mb = 9 * wv + ib;
+                const int mb = 9 * wq + ib;
                 const int t = mb >> 2, ci0 = (mb & 3) * 16;
                 const int dy = t / 3, dx = t - 3 * (t / 3);
-                const bf16x8 a =
-                    *reinterpret_cast<const bf16x8*>(sx + (dx * kWidth + ci0 + n) * kSrcCS + (py + dy) * kTile + px0);
+                const bf16x8 a = tr16_frag(halo + ((py0 + dy) * kHalo + px0 + dx) * kPS + ci0 + rc,
+                                           halo + ((py1 + dy) * kHalo + px1 + dx) * kPS + ci0 + rc);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     acc[ib][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[ib][j], 0, 0, 0);
             }
         }
         __syncthreads();
-        if (threadIdx.x < kWidth)
-            dbacc += ((dbs[0][threadIdx.x] + dbs[1][threadIdx.x]) + dbs[2][threadIdx.x]) + dbs[3][threadIdx.x];
+        if (tid < kWidth)
+            dbacc += ((dbs[grp][0][tid] + dbs[grp][1][tid]) + dbs[grp][2][tid]) + dbs[grp][3][tid];
     }
 
-    float* pp = part + (long long)blockIdx.x * kConvN;
+    // group 1 hands its sums to group 0 through LDS; group 0 adds and writes
+    float* xch = reinterpret_cast<float*>(buf);          // 4 waves x 144 values x 64 lanes
+    if (grp == 1) {
 #pragma unroll
-    for (int ib = 0; ib < 9; ++ib) {
-        const int mb = 9 * wv + ib;
-        const int t = mb >> 2, ci0 = (mb & 3) * 16;
+        for (int ib = 0; ib < 9; ++ib)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) pp[(t * 64 + ci0 + 4 * g + r) * 64 + 16 * j + n] = acc[ib][j][r];
+                for (int e = 0; e < 4; ++e) xch[((wq * 9 + ib) * 16 + j * 4 + e) * 64 + lane] = acc[ib][j][e];
+        if (tid < kWidth) dbs[1][0][tid] = dbacc;
     }
-    if (threadIdx.x < kWidth) pp[kConvW + threadIdx.x] = dbacc;
+    __syncthreads();
+    if (grp == 0) {
+        float* pp = part + (long long)blockIdx.x * kConvN;
+#pragma unroll
+        for (int ib = 0; ib < 9; ++ib) {
+            const int mb = 9 * wq + ib;
+            const int t = mb >> 2, ci0 = (mb & 3) * 16;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    pp[(t * 64 + ci0 + 4 * g + e) * 64 + 16 * j + r] =
+                        acc[ib][j][e] + xch[((wq * 9 + ib) * 16 + j * 4 + e) * 64 + lane];
+        }
+        if (tid < kWidth) pp[kConvW + tid] = dbacc + dbs[1][0][tid];
+    }
 }
 
 }  // namespace
@@ -410,24 +477,26 @@ hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, v
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
     if (bf16) {
         hipLaunchKernelGGL(k_conv_bf16<0>, grid, dim3(256), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
-                           (const uint16_t*)nullptr, (uint16_t*)out, h, w, st);
+                           (const uint16_t*)nullptr, (uint16_t*)out, h, w, st, (const float*)nullptr, 0,
+                           (float*)nullptr);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_conv_f32<0>, grid, dim3(256), 0, s, (const float*)in, (const float*)wpk, bias,
-                       (const float*)nullptr, (float*)out, h, w, st);
+                       (const float*)nullptr, (float*)out, h, w, st, (const float*)nullptr, 0, (float*)nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, void* out, int bf16, int h, int w,
-                           const DevState* st, hipStream_t s) {
+                           const DevState* st, const float* gpart, int nsplit, float* gout, hipStream_t s) {
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
     if (bf16) {
         hipLaunchKernelGGL(k_conv_bf16<1>, grid, dim3(256), 0, s, (const uint16_t*)dlt, (const uint16_t*)wpk,
-                           (const float*)nullptr, (const uint16_t*)mask, (uint16_t*)out, h, w, st);
+                           (const float*)nullptr, (const uint16_t*)mask, (uint16_t*)out, h, w, st, gpart, nsplit,
+                           gout);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_conv_f32<1>, grid, dim3(256), 0, s, (const float*)dlt, (const float*)wpk,
-                       (const float*)nullptr, (const float*)mask, (float*)out, h, w, st);
+                       (const float*)nullptr, (const float*)mask, (float*)out, h, w, st, gpart, nsplit, gout);
     return hipGetLastError();
 }
 
@@ -439,7 +508,7 @@ int wgrad_splits(int h, int w) {
 hipError_t launch_wgrad(const void* src, const void* dlt, float* part, int nsplit, int bf16, int h, int w,
                         const DevState* st, hipStream_t s) {
     if (bf16) {
-        hipLaunchKernelGGL(k_wgrad_bf16, dim3(nsplit), dim3(256), 0, s, (const uint16_t*)src, (const uint16_t*)dlt,
+        hipLaunchKernelGGL(k_wgrad_bf16, dim3(nsplit), dim3(512), 0, s, (const uint16_t*)src, (const uint16_t*)dlt,
                            part, h, w, st);
         return hipGetLastError();
     }

@@ -31,11 +31,9 @@ struct DevState {
     int improved;         // last validation improved on the best
     int done;             // network finished (rule fired, cap hit, or numeric failure)
     int capped;           // finished by max_epochs
-    int pending;          // a validation output waits to be folded into the running sum
+    int acc;              // the last validation produced an output to fold into the running sum
     int nonfinite;        // a non-finite score was seen
     int patience, max_epochs, fixed_epochs;
-    unsigned cnt_val, cnt_adam, cnt_acc, cnt_loss;   // last-block counters
-    int pad_;
 };
 
 // Where each trainable tensor of one network sits.  The internal ("tap
@@ -48,6 +46,7 @@ struct ParamTable {
     int cin[kLayers + 1];     // input channels of layer l
     int split[kLayers + 1];   // number of partial copies of layer l
     long long poff[kLayers + 1];  // offset of layer l's partials in the partial buffer
+    int reduced[kLayers + 1];     // 1: layer l's gradient is already summed into g before Adam
     int total;                // parameters of one network
 };
 
@@ -74,8 +73,11 @@ hipError_t launch_conv1(const float* in, int C, const float* w1, const float* b1
                         int h, int w, const DevState* st, hipStream_t s);
 hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, void* out, int bf16,
                            int h, int w, const DevState* st, hipStream_t s);
+// The data-gradient launch also sums the weight-gradient partials `gpart`
+// (nsplit copies of one 64->64 layer) into gout, when gpart is not null.
 hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, void* out, int bf16,
-                           int h, int w, const DevState* st, hipStream_t s);
+                           int h, int w, const DevState* st, const float* gpart, int nsplit,
+                           float* gout, hipStream_t s);
 int wgrad_splits(int h, int w);
 hipError_t launch_wgrad(const void* src, const void* dlt, float* part, int nsplit, int bf16,
                         int h, int w, const DevState* st, hipStream_t s);
@@ -95,7 +97,8 @@ hipError_t launch_finalize(const float* y, const float* S, const float* ybest, c
 hipError_t launch_adam(float* theta, float* m, float* v, float* g, const float* part,
                        const float* ginj, const ParamTable& pt, float lr, double beta1,
                        double beta2, float eps, float* fwd, float* bwd, uint16_t* fwd16,
-                       uint16_t* bwd16, DevState* st, hipStream_t s);
+                       uint16_t* bwd16, const double* lpart, int nloss, long long loss_npix,
+                       DevState* st, hipStream_t s);
 hipError_t launch_extract(const float* src, int h, int w, int C, float* out_chw, hipStream_t s);
 
 }  // namespace n2f

@@ -192,60 +192,79 @@ __global__ __launch_bounds__(kBlock) void k_pack(const float* __restrict__ theta
 
 // ---------------------------------------------------------------------------
 // First 3x3 conv (C <= 3 input channels, K = 9C is too short for MFMA) with
-// bias and ReLU.  16 threads per pixel, 4 output channels each.
+// bias and ReLU.  Thread = (pixel, group of 16 output channels): four
+// consecutive lanes write one pixel's 64 channels contiguously.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_conv1(const float* __restrict__ in, int C,
                                                   const float* __restrict__ w1, const float* __restrict__ b1,
                                                   void* __restrict__ out, int bf, int h, int w,
                                                   const DevState* st) {
     if (finished(st)) return;
-    __shared__ float sw[kTaps * 3 * kWidth + kWidth];
+    __shared__ __attribute__((aligned(16))) float sw[kTaps * 3 * kWidth + kWidth];
     for (int i = threadIdx.x; i < kTaps * C * kWidth; i += kBlock) sw[i] = w1[i];
     for (int i = threadIdx.x; i < kWidth; i += kBlock) sw[kTaps * 3 * kWidth + i] = b1[i];
     __syncthreads();
-    const int q = threadIdx.x & 15;
-    const long long npix = (long long)h * w;
-    for (int it = 0; it < 4; ++it) {
-        const long long p = ((long long)blockIdx.x * 4 + it) * 16 + (threadIdx.x >> 4);
-        if (p >= npix) break;
-        const int y = (int)(p / w), x = (int)(p - (long long)y * w);
-        float a0 = sw[kTaps * 3 * kWidth + 4 * q + 0], a1 = sw[kTaps * 3 * kWidth + 4 * q + 1];
-        float a2 = sw[kTaps * 3 * kWidth + 4 * q + 2], a3 = sw[kTaps * 3 * kWidth + 4 * q + 3];
-        for (int t = 0; t < kTaps; ++t) {
-            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-            if (yy < 0 || yy >= h || xx < 0 || xx >= w) continue;
-            const float* src = in + ((long long)yy * w + xx) * C;
-            for (int c = 0; c < C; ++c) {
-                const float v = src[c];
-                const float* ww = sw + (t * C + c) * kWidth + 4 * q;
-                a0 = fmaf(v, ww[0], a0);
-                a1 = fmaf(v, ww[1], a1);
-                a2 = fmaf(v, ww[2], a2);
-                a3 = fmaf(v, ww[3], a3);
+    const long long p = (long long)blockIdx.x * (kBlock / 4) + (threadIdx.x >> 2);
+    const int cg = threadIdx.x & 3;
+    if (p >= (long long)h * w) return;
+    const int y = (int)(p / w), x = (int)(p - (long long)y * w);
+    float acc[16];
+    const float4* bb = reinterpret_cast<const float4*>(sw + kTaps * 3 * kWidth + 16 * cg);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float4 v = bb[r];
+        acc[4 * r] = v.x;
+        acc[4 * r + 1] = v.y;
+        acc[4 * r + 2] = v.z;
+        acc[4 * r + 3] = v.w;
+    }
+    for (int t = 0; t < kTaps; ++t) {
+        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+        if (yy < 0 || yy >= h || xx < 0 || xx >= w) continue;
+        const float* src = in + ((long long)yy * w + xx) * C;
+        for (int c = 0; c < C; ++c) {
+            const float v = src[c];
+            const float4* ww = reinterpret_cast<const float4*>(sw + (t * C + c) * kWidth + 16 * cg);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float4 wv = ww[r];
+                acc[4 * r] = fmaf(v, wv.x, acc[4 * r]);
+                acc[4 * r + 1] = fmaf(v, wv.y, acc[4 * r + 1]);
+                acc[4 * r + 2] = fmaf(v, wv.z, acc[4 * r + 2]);
+                acc[4 * r + 3] = fmaf(v, wv.w, acc[4 * r + 3]);
             }
         }
-        store4(out, p * kWidth + 4 * q, make_float4(fmaxf(a0, 0.f), fmaxf(a1, 0.f), fmaxf(a2, 0.f), fmaxf(a3, 0.f)),
-               bf != 0);
     }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        store4(out, p * kWidth + 16 * cg + 4 * r,
+               make_float4(fmaxf(acc[4 * r], 0.f), fmaxf(acc[4 * r + 1], 0.f), fmaxf(acc[4 * r + 2], 0.f),
+                           fmaxf(acc[4 * r + 3], 0.f)),
+               bf != 0);
 }
 
 // ---------------------------------------------------------------------------
 // Weight gradient of the first layer: dW1[t][c][co] = sum_p x[p + off(t)][c]
 // * d1[p][co] and db1[co] = sum_p d1[p][co], one partial sum per split of
-// 16x16 pixel tiles.
+// 16x16 pixel tiles.  Thread = (output channel, quarter of the tile's
+// pixels): the delta read is one distinct word per lane, the input reads
+// are wave-wide broadcasts; quarters are added in a fixed order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_wgrad1(const float* __restrict__ in, int C,
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_wgrad1(const float* __restrict__ in,
                                                    const void* __restrict__ dlt, int bf,
                                                    float* __restrict__ part, int h, int w,
                                                    const DevState* st) {
     if (finished(st)) return;
-    __shared__ float sx[18 * 18 * 3];
+    constexpr int nW = kTaps * C * kWidth;
+    constexpr int n1 = nW + kWidth;
+    constexpr int nacc = kTaps * C + 1;          // weights (t, c) then the bias
+    __shared__ float sx[18 * 18 * C];
     __shared__ float sd[256 * kWidth];
-    const int nW = kTaps * C * kWidth;
-    const int n1 = nW + kWidth;
-    float acc[7];
+    const int co = threadIdx.x & 63, pg = threadIdx.x >> 6;
+    float acc[nacc];
 #pragma unroll
-    for (int r = 0; r < 7; ++r) acc[r] = 0.f;
+    for (int r = 0; r < nacc; ++r) acc[r] = 0.f;
     const int tiles_x = (w + 15) >> 4, tiles_y = (h + 15) >> 4;
     const int ntiles = tiles_x * tiles_y;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -263,29 +282,28 @@ __global__ __launch_bounds__(kBlock) void k_wgrad1(const float* __restrict__ in,
             *reinterpret_cast<float4*>(sd + p * kWidth + 4 * q) = v;
         }
         __syncthreads();
+        for (int p = pg * 64; p < pg * 64 + 64; ++p) {
+            const float d = sd[p * kWidth + co];
+            const int py = p >> 4, px = p & 15;
 #pragma unroll
-        for (int r = 0; r < 7; ++r) {
-            const int o = threadIdx.x + r * kBlock;
-            if (o < nW) {
-                const int t = o / (C * kWidth), c = (o / kWidth) % C, co = o & 63;
-                const int dy = t / 3, dx = t % 3;
-                float s = 0.f;
-                for (int p = 0; p < 256; ++p)
-                    s = fmaf(sx[(((p >> 4) + dy) * 18 + (p & 15) + dx) * C + c], sd[p * kWidth + co], s);
-                acc[r] += s;
-            } else if (o < n1) {
-                const int co = o - nW;
-                float s = 0.f;
-                for (int p = 0; p < 256; ++p) s += sd[p * kWidth + co];
-                acc[r] += s;
-            }
+            for (int t = 0; t < kTaps; ++t)
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    acc[t * C + c] = fmaf(sx[((py + t / 3) * 18 + px + t % 3) * C + c], d, acc[t * C + c]);
+            acc[kTaps * C] += d;
         }
         __syncthreads();
     }
+    // add the four pixel quarters in order through LDS (reusing sd)
 #pragma unroll
-    for (int r = 0; r < 7; ++r) {
-        const int o = threadIdx.x + r * kBlock;
-        if (o < n1) part[(long long)blockIdx.x * n1 + o] = acc[r];
+    for (int r = 0; r < nacc; ++r) sd[(pg * nacc + r) * kWidth + co] = acc[r];
+    __syncthreads();
+    for (int o = threadIdx.x; o < n1; o += kBlock) {
+        const int r = (o < nW) ? (o >> 6) : kTaps * C;    // (t * C + c), or the bias slot
+        const int c2 = o & 63;
+        float s = 0.f;
+        for (int q = 0; q < 4; ++q) s += sd[(q * nacc + r) * kWidth + c2];
+        part[(long long)blockIdx.x * n1 + o] = s;
     }
 }
 
@@ -332,8 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_head_train(const void* __restrict__ 
         g3 = fmaf(d, a.w, g3);
         if (q == 0) {
             gb += d;
-            const double zd = (double)z;
-            lacc += (zd > 0.0 ? zd : 0.0) + log1p(exp(-fabs(zd))) - (double)t * zd;
+            lacc += (double)(fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - t * z);
         }
     }
     sacc[pg][4 * q + 0] = g0;
@@ -354,14 +371,8 @@ __global__ __launch_bounds__(kBlock) void k_head_train(const void* __restrict__ 
         double s = 0.0;
         for (int i = 0; i < 16; ++i) s += sl[i];
         lpart[blockIdx.x] = s;
-    }
-    if (last_block(&st->cnt_loss)) {
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (unsigned i = 0; i < gridDim.x; ++i) s += lpart[i];
-            st->loss = s / (double)npix;
-            st->cnt_loss = 0;
-        }
+        // one Adam step follows this head: count it (no other block reads t)
+        if (blockIdx.x == 0) st->t += 1;
     }
 }
 
@@ -407,51 +418,68 @@ __global__ __launch_bounds__(kBlock) void k_head_val(const void* __restrict__ a8
         for (int i = 0; i < 16; ++i) s += sl[i];
         vpart[blockIdx.x] = s;
     }
-    if (last_block(&st->cnt_val)) {
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (unsigned i = 0; i < gridDim.x; ++i) s += vpart[i];
-            const double v = s / (double)npix;
-            DevState S = *st;
-            S.epoch += 1;
-            S.last_v = v;
-            vtrace[S.epoch - 1] = v;
-            if (!isfinite(v)) {
-                S.nonfinite = 1;
-                S.done = 1;
-                S.improved = 0;
-                S.pending = 0;
-            } else {
-                if (v < S.best) {
-                    S.best = v;
-                    S.best_epoch = S.epoch;
-                    S.n_since = 0;
-                    S.improved = 1;
-                } else {
-                    S.n_since += 1;
-                    S.improved = 0;
-                }
-                S.pending = 1;
-                if (S.fixed_epochs > 0) {
-                    if (S.epoch >= S.fixed_epochs) S.done = 1;
-                } else if (S.n_since >= S.patience) {
-                    S.done = 1;
-                } else if (S.epoch >= S.max_epochs) {
-                    S.done = 1;
-                    S.capped = 1;
-                }
-            }
-            S.cnt_val = 0;
-            *st = S;
+}
+
+// Score of the last validation (fixed-order FP64 sum of the block partials)
+// and the stopping rule: a strict improvement records the epoch; `patience`
+// epochs in a row without one end the run; fixed-epoch mode ends after
+// `fixed_epochs`.  One block.  `acc` tells the next kernel whether there is
+// an output to fold in.
+__global__ __launch_bounds__(kBlock) void k_decide(const double* __restrict__ vpart, int nblk, long long npix,
+                                                   DevState* st, double* __restrict__ vtrace) {
+    __shared__ double sv[kBlock];
+    if (st->done) {
+        if (threadIdx.x == 0) st->acc = 0;
+        return;
+    }
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += kBlock) s += vpart[i];
+    sv[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = kBlock / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sv[threadIdx.x] += sv[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double v = sv[0] / (double)npix;
+    DevState S = *st;
+    S.epoch += 1;
+    S.last_v = v;
+    vtrace[S.epoch - 1] = v;
+    if (!isfinite(v)) {
+        S.nonfinite = 1;
+        S.done = 1;
+        S.improved = 0;
+        S.acc = 0;
+    } else {
+        if (v < S.best) {
+            S.best = v;
+            S.best_epoch = S.epoch;
+            S.n_since = 0;
+            S.improved = 1;
+        } else {
+            S.n_since += 1;
+            S.improved = 0;
+        }
+        S.acc = 1;
+        if (S.fixed_epochs > 0) {
+            if (S.epoch >= S.fixed_epochs) S.done = 1;
+        } else if (S.n_since >= S.patience) {
+            S.done = 1;
+        } else if (S.epoch >= S.max_epochs) {
+            S.done = 1;
+            S.capped = 1;
         }
     }
+    *st = S;
 }
 
 // Fold the last validation output into the running sum: a new best empties
 // the sum and becomes the best output; otherwise the output is added.
 __global__ __launch_bounds__(kBlock) void k_accumulate(const float* __restrict__ y, float* __restrict__ S,
-                                                       float* __restrict__ ybest, long long npix, DevState* st) {
-    if (!st->pending) return;
+                                                       float* __restrict__ ybest, long long npix,
+                                                       const DevState* st) {
+    if (!st->acc) return;
     const int improved = st->improved;
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < npix; i += (long long)gridDim.x * kBlock) {
         const float v = y[i];
@@ -460,12 +488,6 @@ __global__ __launch_bounds__(kBlock) void k_accumulate(const float* __restrict__
             ybest[i] = v;
         } else {
             S[i] += v;
-        }
-    }
-    if (last_block(&st->cnt_acc)) {
-        if (threadIdx.x == 0) {
-            st->pending = 0;
-            st->cnt_acc = 0;
         }
     }
 }
@@ -496,21 +518,29 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, floa
                                                  const float* __restrict__ part, const float* __restrict__ ginj,
                                                  ParamTable pt, float lr, double beta1, double beta2, float eps,
                                                  float* fwd, float* bwd, uint16_t* fwd16, uint16_t* bwd16,
+                                                 const double* __restrict__ lpart, int nloss, long long loss_npix,
                                                  DevState* st) {
     if (finished(st)) return;
     // 32 parameters per block; 8 lanes per parameter each sum every 8th
     // split, then the 8 lane sums are added in lane order (fixed order,
     // so the result does not depend on scheduling).
     __shared__ float red[8][33];
-    const long long t_new = st->t + 1;
+    const long long t_new = st->t;   // this step, already counted by the head kernel (or the bump)
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !ginj) {
+        double l = 0.0;
+        for (int b = 0; b < nloss; ++b) l += lpart[b];
+        st->loss = l / (double)loss_npix;
+    }
     const int p = threadIdx.x & 31, j = threadIdx.x >> 5;
     const int i = blockIdx.x * 32 + p;
     if (i < pt.total && !ginj) {
         const int l = layer_of(pt, i);
         const int il = i - pt.off[l];
-        const float* pp = part + pt.poff[l] + il;
         float s = 0.f;
-        for (int sp = j; sp < pt.split[l]; sp += 8) s += pp[(long long)sp * pt.n[l]];
+        if (!pt.reduced[l]) {
+            const float* pp = part + pt.poff[l] + il;
+            for (int sp = j; sp < pt.split[l]; sp += 8) s += pp[(long long)sp * pt.n[l]];
+        }
         red[j][p] = s;
     }
     __syncthreads();
@@ -520,29 +550,33 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, floa
         float gi;
         if (ginj) {
             gi = ginj[i];
+        } else if (pt.reduced[l]) {
+            gi = g[i];                // summed by the data-gradient kernel of layer l
         } else {
             gi = red[0][p];
 #pragma unroll
             for (int k = 1; k < 8; ++k) gi += red[k][p];
         }
         g[i] = gi;
+        // decay factors and their complements formed in FP64, each rounded
+        // once: 1 - (float)0.999 would be off by 1e-5 relative
         const float b1 = (float)beta1, b2 = (float)beta2;
+        const float omb1 = (float)(1.0 - beta1), omb2 = (float)(1.0 - beta2);
         const float bc1 = (float)(1.0 - pow(beta1, (double)t_new));
         const float bc2 = (float)(1.0 - pow(beta2, (double)t_new));
-        const float mi = b1 * m[i] + (1.0f - b1) * gi;
-        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        const float mi = b1 * m[i] + omb1 * gi;
+        const float vi = b2 * v[i] + omb2 * gi * gi;
         const float th = theta[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
         m[i] = mi;
         v[i] = vi;
         theta[i] = th;
         if (l >= 1 && l < kLayers && il < kConvW) pack_one(l, il, th, fwd, bwd, fwd16, bwd16);
     }
-    if (last_block(&st->cnt_adam)) {
-        if (threadIdx.x == 0) {
-            st->t = t_new;
-            st->cnt_adam = 0;
-        }
-    }
+}
+
+// Count one Adam step (for steps whose gradient does not come from the head).
+__global__ void k_bump_step(DevState* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && !st->done) st->t += 1;
 }
 
 // Channels-last image (h*w pixels x C) to planar CHW.
@@ -586,19 +620,21 @@ hipError_t launch_pack(const float* theta, const ParamTable& pt, float* fwd, flo
 
 hipError_t launch_conv1(const float* in, int C, const float* w1, const float* b1, void* out, int bf16, int h,
                         int w, const DevState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_conv1, dim3(nblocks((long long)h * w, 64)), dim3(kBlock), 0, s, in, C, w1, b1, out, bf16,
+    hipLaunchKernelGGL(k_conv1, dim3(nblocks((long long)h * w, kBlock / 4)), dim3(kBlock), 0, s, in, C, w1, b1, out, bf16,
                        h, w, st);
     return hipGetLastError();
 }
 
 hipError_t launch_wgrad1(const float* in, int C, const void* dlt, float* part, int nsplit, int bf16, int h, int w,
                          const DevState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_wgrad1, dim3(nsplit), dim3(kBlock), 0, s, in, C, dlt, bf16, part, h, w, st);
+    if (C == 1) hipLaunchKernelGGL(k_wgrad1<1>, dim3(nsplit), dim3(kBlock), 0, s, in, dlt, bf16, part, h, w, st);
+    else if (C == 2) hipLaunchKernelGGL(k_wgrad1<2>, dim3(nsplit), dim3(kBlock), 0, s, in, dlt, bf16, part, h, w, st);
+    else hipLaunchKernelGGL(k_wgrad1<3>, dim3(nsplit), dim3(kBlock), 0, s, in, dlt, bf16, part, h, w, st);
     return hipGetLastError();
 }
 
 int head_splits(long long npix) {
-    long long b = (npix + 255) / 256;
+    long long b = (npix + 127) / 128;
     return (int)std::max(1LL, std::min(b, (long long)kMaxHeadSplit));
 }
 
@@ -615,13 +651,16 @@ hipError_t launch_head_val(const void* a8, const float* xs, int C, int k, const 
                            double* vtrace, hipStream_t s) {
     hipLaunchKernelGGL(k_head_val, dim3(nblk), dim3(kBlock), 0, s, a8, xs, C, k, w9, b9, y, vpart, bf16, npix, st,
                        vtrace);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kBlock), 0, s, (const double*)vpart, nblk, npix, st, vtrace);
     return hipGetLastError();
 }
 
 hipError_t launch_accumulate(const float* y, float* S, float* ybest, long long npix, DevState* st,
                              hipStream_t s) {
     const unsigned nb = std::min<unsigned>(nblocks(npix, kBlock * 4), 2048u);
-    hipLaunchKernelGGL(k_accumulate, dim3(nb), dim3(kBlock), 0, s, y, S, ybest, npix, st);
+    hipLaunchKernelGGL(k_accumulate, dim3(nb), dim3(kBlock), 0, s, y, S, ybest, npix, (const DevState*)st);
     return hipGetLastError();
 }
 
@@ -634,9 +673,15 @@ hipError_t launch_finalize(const float* y, const float* S, const float* ybest, c
 
 hipError_t launch_adam(float* theta, float* m, float* v, float* g, const float* part, const float* ginj,
                        const ParamTable& pt, float lr, double beta1, double beta2, float eps, float* fwd,
-                       float* bwd, uint16_t* fwd16, uint16_t* bwd16, DevState* st, hipStream_t s) {
+                       float* bwd, uint16_t* fwd16, uint16_t* bwd16, const double* lpart, int nloss,
+                       long long loss_npix, DevState* st, hipStream_t s) {
+    if (ginj) {
+        hipLaunchKernelGGL(k_bump_step, dim3(1), dim3(64), 0, s, st);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_adam, dim3(nblocks(pt.total, 32)), dim3(kBlock), 0, s, theta, m, v, g, part, ginj, pt,
-                       lr, beta1, beta2, eps, fwd, bwd, fwd16, bwd16, st);
+                       lr, beta1, beta2, eps, fwd, bwd, fwd16, bwd16, lpart, nloss, loss_npix, st);
     return hipGetLastError();
 }
 

@@ -38,9 +38,10 @@ class N2FError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [
         ("n_layers", c_int), ("width", c_int),
-        ("lr", c_float), ("beta1", c_float), ("beta2", c_float), ("eps", c_float),
+        ("lr", c_float), ("eps", c_float), ("beta1", c_double), ("beta2", c_double),
         ("patience", c_int), ("max_epochs", c_int), ("fixed_epochs", c_int),
         ("pair_order", c_int * 4), ("precision", c_int), ("init_seed", c_ulonglong),
+        ("use_graph", c_int),
     ]
 
 
@@ -79,7 +80,7 @@ def lib():
             "n2f_get_history": [c_void_p, c_int, c_int, c_void_p],
             "n2f_get_lohi": [c_void_p, POINTER(c_float), POINTER(c_float)],
             "n2f_get_image": [c_void_p, c_int, c_void_p],
-            "n2f_profile_begin": [],
+            "n2f_profile_begin": [c_int],
             "n2f_profile_read": [c_int, POINTER(c_double), POINTER(c_longlong), POINTER(c_longlong)],
             "n2f_profile_end": [],
         }
@@ -249,8 +250,8 @@ def denoise(x, cfg: Config | None = None, ws=None):
     return out, st
 
 
-def profile_begin():
-    _check(lib().n2f_profile_begin())
+def profile_begin(every: int = 1):
+    _check(lib().n2f_profile_begin(every))
 
 
 def profile_read(kernel_class: int):

@@ -299,3 +299,42 @@ def test_deterministic():
     a, _ = n2f.denoise(dev(noisy), cfg)
     b, _ = n2f.denoise(dev(noisy), cfg)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [n2f.FP32, n2f.BF16])
+def test_graph_replay_equals_direct_launches(prec):
+    """Epochs replayed from one recorded HIP graph (host polling between
+    replays) give the same bits as epochs launched kernel by kernel, with
+    a fixed epoch count and with the stopping rule firing mid-batch."""
+    _, noisy = noisy_image(1, 52, 44, 9)
+    for kw in [dict(fixed_epochs=5), dict(patience=5, max_epochs=80)]:
+        outs = []
+        for g in (1, 0):
+            r = n2f.Run(dev(noisy), n2f.default_config(precision=prec, use_graph=g, **kw))
+            done, status = r.run_epochs(0, 200)
+            assert done and status == n2f.OK
+            outs.append((r.result().cpu(), r.history(0), r.progress(0)))
+        assert torch.equal(outs[0][0], outs[1][0])
+        np.testing.assert_array_equal(outs[0][1], outs[1][1])
+        assert outs[0][2] == outs[1][2]
+
+
+def test_free_running_steps_track_oracle():
+    """Eight steps with the state kept on the device (no teacher forcing):
+    the accumulated parameter change stays within 1e-4 (norm-wise) of the
+    oracle's.  This guards the step counter, Adam's constants (1 - beta2
+    must be exact to FP32) and the weight repacking between steps."""
+    _, noisy = synth.small_64(0)
+    th0 = synth.init_params(1, 0)[0]
+    r = n2f.Run(dev(noisy), n2f.default_config(fixed_epochs=8))
+    xs = r.image(4).cpu().numpy().astype(np.float64)
+    pairs = O.training_pairs(xs)
+    st = O.new_state(th0)
+    for step in range(8):
+        r.train_step(0, step % 4)
+        st = O.train_step(st, 1, pairs[step % 4][0], pairs[step % 4][1][0], H0)[0]
+    th, m, v, t = r.get_state(0)
+    say("free-run dtheta err", rel(th - th0, st.theta - th0), "v err", rel(v, st.v))
+    assert t == 8
+    assert rel(th - th0, st.theta - th0) < 1e-4
+    assert rel(v, st.v) < 1e-4
