@@ -69,7 +69,6 @@ ParamTable make_table(int C, int nsplit, int hsplit) {
         pt.off[l] = off;
         pt.n[l] = (l < kLayers) ? kTaps * cin * kWidth + kWidth : kHeadN;
         pt.split[l] = (l < kLayers) ? nsplit : hsplit;
-        pt.reduced[l] = 0;
         pt.poff[l] = poff;
         off += pt.n[l];
         poff += (long long)pt.split[l] * pt.n[l];
@@ -384,8 +383,7 @@ n2f_status enqueue_train_step(n2f_run* r, int k, int pair) {
                                 N.st, s);
         }));
         N2F_HIP(timed(N2F_K_CONV_BWD, (long long)npix, s, [&] {
-            return launch_conv_bwd(r->dlt[cur], bwdpk(l), act_layer(r, l - 1, npix), r->dlt[1 - cur], bf, h, w, N.st,
-                                   nullptr, 0, nullptr, s);
+            return launch_conv_bwd(r->dlt[cur], bwdpk(l), act_layer(r, l - 1, npix), r->dlt[1 - cur], bf, h, w, N.st, s);
         }));
         cur = 1 - cur;
     }

@@ -31,37 +31,6 @@ constexpr int kHS = 68;  // LDS floats per staged pixel
 
 __device__ __forceinline__ bool finished(const DevState* st) { return st != nullptr && st->done; }
 
-// Sum the `nsplit` per-split partials of one 64->64 layer's gradient
-// (kConvN values each) for this block's slice of the values, and write the
-// sums to g.  Run at the end of the data-gradient kernel of the same layer
-// (the weight-gradient kernel has completed), spreading the reduction over
-// that kernel's blocks.  Lane group j (of 8) adds splits j, j+8, ...; the 8
-// group sums are then added in group order, so the result is fixed.
-// `red` is LDS scratch of 8 * 33 floats.
-__device__ __forceinline__ void reduce_partials_slice(const float* __restrict__ part, int nsplit,
-                                                      float* __restrict__ g, float* red) {
-    const int nb = gridDim.x * gridDim.y;
-    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-    const int chunk = (kConvN + nb - 1) / nb;
-    const int lo = bid * chunk, hi = min(kConvN, lo + chunk);
-    const int q = threadIdx.x & 31, j = threadIdx.x >> 5;
-    for (int base = lo; base < hi; base += 32) {
-        const int i = base + q;
-        float sum = 0.f;
-        if (i < hi)
-            for (int sp = j; sp < nsplit; sp += 8) sum += part[(long long)sp * kConvN + i];
-        __syncthreads();
-        red[j * 33 + q] = sum;
-        __syncthreads();
-        if (j == 0 && i < hi) {
-            float tot = red[q];
-#pragma unroll
-            for (int k = 1; k < 8; ++k) tot += red[k * 33 + q];
-            g[i] = tot;
-        }
-    }
-}
-
 // Stage the (16+2)^2 x 64 halo around tile (x0, y0) of a channels-last FP32
 // activation into LDS, zero outside the image.
 __device__ __forceinline__ void stage_halo_f32(float* halo, const float* __restrict__ in, int x0, int y0, int h,
@@ -81,9 +50,7 @@ __device__ __forceinline__ void stage_halo_f32(float* halo, const float* __restr
 template <int MODE>
 __global__ __launch_bounds__(256) void k_conv_f32(const float* __restrict__ in, const float* __restrict__ wpk,
                                                   const float* __restrict__ bias, const float* __restrict__ mask,
-                                                  float* __restrict__ out, int h, int w, const DevState* st,
-                                                  const float* __restrict__ gpart, int nsplit,
-                                                  float* __restrict__ gout) {
+                                                  float* __restrict__ out, int h, int w, const DevState* st) {
     if (finished(st)) return;
     __shared__ __attribute__((aligned(16))) float halo[kHalo * kHalo * kHS];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -141,7 +108,6 @@ __global__ __launch_bounds__(256) void k_conv_f32(const float* __restrict__ in, 
             }
         }
     }
-    if (MODE == 1 && gpart) reduce_partials_slice(gpart, nsplit, gout, halo);
 }
 
 // Weight gradient of a 64->64 layer.  Block b accumulates tiles b, b + S,
@@ -223,7 +189,6 @@ __global__ __launch_bounds__(256) void k_wgrad_f32(const float* __restrict__ src
 // ===========================================================================
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kHSb = 72;   // LDS bf16 per staged pixel (144 B: 8 lanes of a 16-byte read hit 32 banks)
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
     uint32_t u = __float_as_uint(f);
@@ -234,6 +199,9 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 
 __device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
+constexpr int kHSb = 72;   // LDS bf16 per staged pixel (144 B: 8 lanes of a 16-byte read hit 32 banks)
+
+
 // MODE 0: forward, bias + ReLU.  MODE 1: data gradient masked by [a > 0].
 // 16x16 pixel tile per 256-thread block, halo staged pixel-major in LDS;
 // wave wv computes tile rows 4wv..4wv+3 x 64 channels (4x4 MFMA tiles).
@@ -242,9 +210,7 @@ __device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float(((u
 template <int MODE>
 __global__ __launch_bounds__(256) void k_conv_bf16(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
                                                    const float* __restrict__ bias, const uint16_t* __restrict__ mask,
-                                                   uint16_t* __restrict__ out, int h, int w, const DevState* st,
-                                                   const float* __restrict__ gpart, int nsplit,
-                                                   float* __restrict__ gout) {
+                                                   uint16_t* __restrict__ out, int h, int w, const DevState* st) {
     if (finished(st)) return;
     __shared__ __attribute__((aligned(16))) uint16_t halo[kHalo * kHalo * kHSb];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -333,7 +299,6 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const uint16_t* __restrict__ 
         }
         *reinterpret_cast<uint4*>(out + o) = v;
     }
-    if (MODE == 1 && gpart) reduce_partials_slice(gpart, nsplit, gout, reinterpret_cast<float*>(halo));
 }
 
 // BF16 weight gradient of a 64->64 layer.  GEMM view as in the FP32 kernel
@@ -477,26 +442,24 @@ hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, v
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
     if (bf16) {
         hipLaunchKernelGGL(k_conv_bf16<0>, grid, dim3(256), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
-                           (const uint16_t*)nullptr, (uint16_t*)out, h, w, st, (const float*)nullptr, 0,
-                           (float*)nullptr);
+                           (const uint16_t*)nullptr, (uint16_t*)out, h, w, st);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_conv_f32<0>, grid, dim3(256), 0, s, (const float*)in, (const float*)wpk, bias,
-                       (const float*)nullptr, (float*)out, h, w, st, (const float*)nullptr, 0, (float*)nullptr);
+                       (const float*)nullptr, (float*)out, h, w, st);
     return hipGetLastError();
 }
 
 hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, void* out, int bf16, int h, int w,
-                           const DevState* st, const float* gpart, int nsplit, float* gout, hipStream_t s) {
+                           const DevState* st, hipStream_t s) {
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
     if (bf16) {
         hipLaunchKernelGGL(k_conv_bf16<1>, grid, dim3(256), 0, s, (const uint16_t*)dlt, (const uint16_t*)wpk,
-                           (const float*)nullptr, (const uint16_t*)mask, (uint16_t*)out, h, w, st, gpart, nsplit,
-                           gout);
+                           (const float*)nullptr, (const uint16_t*)mask, (uint16_t*)out, h, w, st);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_conv_f32<1>, grid, dim3(256), 0, s, (const float*)dlt, (const float*)wpk,
-                       (const float*)nullptr, (const float*)mask, (float*)out, h, w, st, gpart, nsplit, gout);
+                       (const float*)nullptr, (const float*)mask, (float*)out, h, w, st);
     return hipGetLastError();
 }
 

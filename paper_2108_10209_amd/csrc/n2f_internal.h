@@ -46,7 +46,6 @@ struct ParamTable {
     int cin[kLayers + 1];     // input channels of layer l
     int split[kLayers + 1];   // number of partial copies of layer l
     long long poff[kLayers + 1];  // offset of layer l's partials in the partial buffer
-    int reduced[kLayers + 1];     // 1: layer l's gradient is already summed into g before Adam
     int total;                // parameters of one network
 };
 
@@ -73,11 +72,8 @@ hipError_t launch_conv1(const float* in, int C, const float* w1, const float* b1
                         int h, int w, const DevState* st, hipStream_t s);
 hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, void* out, int bf16,
                            int h, int w, const DevState* st, hipStream_t s);
-// The data-gradient launch also sums the weight-gradient partials `gpart`
-// (nsplit copies of one 64->64 layer) into gout, when gpart is not null.
 hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, void* out, int bf16,
-                           int h, int w, const DevState* st, const float* gpart, int nsplit,
-                           float* gout, hipStream_t s);
+                           int h, int w, const DevState* st, hipStream_t s);
 int wgrad_splits(int h, int w);
 hipError_t launch_wgrad(const void* src, const void* dlt, float* part, int nsplit, int bf16,
                         int h, int w, const DevState* st, hipStream_t s);

@@ -513,6 +513,27 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const float* __restrict__ y
 // injected gradient); bias corrections use the device step counter; the
 // packed convolution operands are rewritten from the new weights.
 // ---------------------------------------------------------------------------
+// One Adam update of parameter i with gradient gi.
+__device__ __forceinline__ void adam_one(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
+                                         int i, float gi, float lr, float b1, float b2, float omb1, float omb2,
+                                         float bc1, float bc2, float eps, int l, int il, float* fwd, float* bwd,
+                                         uint16_t* fwd16, uint16_t* bwd16) {
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float vi = b2 * v[i] + omb2 * gi * gi;
+    const float th = theta[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] = th;
+    if (l >= 1 && l < kLayers && il < kConvW) pack_one(l, il, th, fwd, bwd, fwd16, bwd16);
+}
+
+// Blocks [0, 7 * kAdamBPL) each own 256 consecutive values of one 64->64
+// layer and sum that layer's split partials with 16-byte loads (4 split
+// groups, added in group order); the remaining blocks own 32 values of the
+// first layer or the head (8 split groups).  Either way the sum order is
+// fixed.
+constexpr int kAdamBPL = (kConvN + 255) / 256;     // blocks per 64->64 layer
+
 __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, float* __restrict__ m,
                                                  float* __restrict__ v, float* __restrict__ g,
                                                  const float* __restrict__ part, const float* __restrict__ ginj,
@@ -521,9 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, floa
                                                  const double* __restrict__ lpart, int nloss, long long loss_npix,
                                                  DevState* st) {
     if (finished(st)) return;
-    // 32 parameters per block; 8 lanes per parameter each sum every 8th
-    // split, then the 8 lane sums are added in lane order (fixed order,
-    // so the result does not depend on scheduling).
+    __shared__ float4 red4[4][64];
     __shared__ float red[8][33];
     const long long t_new = st->t;   // this step, already counted by the head kernel (or the bump)
     if (blockIdx.x == 0 && threadIdx.x == 0 && !ginj) {
@@ -531,46 +550,83 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, floa
         for (int b = 0; b < nloss; ++b) l += lpart[b];
         st->loss = l / (double)loss_npix;
     }
-    const int p = threadIdx.x & 31, j = threadIdx.x >> 5;
-    const int i = blockIdx.x * 32 + p;
-    if (i < pt.total && !ginj) {
-        const int l = layer_of(pt, i);
-        const int il = i - pt.off[l];
-        float s = 0.f;
-        if (!pt.reduced[l]) {
-            const float* pp = part + pt.poff[l] + il;
-            for (int sp = j; sp < pt.split[l]; sp += 8) s += pp[(long long)sp * pt.n[l]];
+    // decay factors and their complements formed in FP64, each rounded
+    // once: 1 - (float)0.999 would be off by 1e-5 relative
+    const float b1 = (float)beta1, b2 = (float)beta2;
+    const float omb1 = (float)(1.0 - beta1), omb2 = (float)(1.0 - beta2);
+    const float bc1 = (float)(1.0 - pow(beta1, (double)t_new));
+    const float bc2 = (float)(1.0 - pow(beta2, (double)t_new));
+    const int nconv = (kLayers - 1) * kAdamBPL;
+    if ((int)blockIdx.x < nconv) {
+        const int l = 1 + blockIdx.x / kAdamBPL;
+        const int il0 = (blockIdx.x % kAdamBPL) * 256;
+        const int q = threadIdx.x & 63, j = threadIdx.x >> 6;
+        const int il = il0 + 4 * q;
+        const bool valid = il < kConvN;
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (valid && !ginj) {
+            const float4* pp = reinterpret_cast<const float4*>(part + pt.poff[l] + il);
+            const int row4 = kConvN / 4;
+#pragma unroll 8
+            for (int sp = j; sp < pt.split[l]; sp += 4) {
+                const float4 x = pp[(long long)sp * row4];
+                acc.x += x.x;
+                acc.y += x.y;
+                acc.z += x.z;
+                acc.w += x.w;
+            }
         }
-        red[j][p] = s;
+        red4[j][q] = acc;
+        __syncthreads();
+        if (j == 0 && valid) {
+            const int i0 = pt.off[l] + il;
+            float gg[4];
+            if (ginj) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) gg[e] = ginj[i0 + e];
+            } else {
+                const float4 s0 = red4[0][q], s1 = red4[1][q], s2 = red4[2][q], s3 = red4[3][q];
+                gg[0] = ((s0.x + s1.x) + s2.x) + s3.x;
+                gg[1] = ((s0.y + s1.y) + s2.y) + s3.y;
+                gg[2] = ((s0.z + s1.z) + s2.z) + s3.z;
+                gg[3] = ((s0.w + s1.w) + s2.w) + s3.w;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                g[i0 + e] = gg[e];
+                adam_one(theta, m, v, i0 + e, gg[e], lr, b1, b2, omb1, omb2, bc1, bc2, eps, l, il + e, fwd, bwd,
+                         fwd16, bwd16);
+            }
+        }
+        return;
     }
+    // first layer (block range 0) and head (range 1), 32 values per block
+    const int nb0 = (pt.n[0] + 31) / 32;
+    const int rb = blockIdx.x - nconv;
+    const int l = (rb < nb0) ? 0 : kLayers;
+    const int il_base = (rb < nb0 ? rb : rb - nb0) * 32;
+    const int p = threadIdx.x & 31, j = threadIdx.x >> 5;
+    const int il = il_base + p;
+    const bool valid = il < pt.n[l];
+    float sum = 0.f;
+    if (valid && !ginj) {
+        const float* pp = part + pt.poff[l] + il;
+        for (int sp = j; sp < pt.split[l]; sp += 8) sum += pp[(long long)sp * pt.n[l]];
+    }
+    red[j][p] = sum;
     __syncthreads();
-    if (j == 0 && i < pt.total) {
-        const int l = layer_of(pt, i);
-        const int il = i - pt.off[l];
+    if (j == 0 && valid) {
+        const int i = pt.off[l] + il;
         float gi;
         if (ginj) {
             gi = ginj[i];
-        } else if (pt.reduced[l]) {
-            gi = g[i];                // summed by the data-gradient kernel of layer l
         } else {
             gi = red[0][p];
 #pragma unroll
             for (int k = 1; k < 8; ++k) gi += red[k][p];
         }
         g[i] = gi;
-        // decay factors and their complements formed in FP64, each rounded
-        // once: 1 - (float)0.999 would be off by 1e-5 relative
-        const float b1 = (float)beta1, b2 = (float)beta2;
-        const float omb1 = (float)(1.0 - beta1), omb2 = (float)(1.0 - beta2);
-        const float bc1 = (float)(1.0 - pow(beta1, (double)t_new));
-        const float bc2 = (float)(1.0 - pow(beta2, (double)t_new));
-        const float mi = b1 * m[i] + omb1 * gi;
-        const float vi = b2 * v[i] + omb2 * gi * gi;
-        const float th = theta[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
-        m[i] = mi;
-        v[i] = vi;
-        theta[i] = th;
-        if (l >= 1 && l < kLayers && il < kConvW) pack_one(l, il, th, fwd, bwd, fwd16, bwd16);
+        adam_one(theta, m, v, i, gi, lr, b1, b2, omb1, omb2, bc1, bc2, eps, l, il, fwd, bwd, fwd16, bwd16);
     }
 }
 
@@ -680,7 +736,8 @@ hipError_t launch_adam(float* theta, float* m, float* v, float* g, const float* 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_adam, dim3(nblocks(pt.total, 32)), dim3(kBlock), 0, s, theta, m, v, g, part, ginj, pt,
+    const int nblk = (kLayers - 1) * kAdamBPL + (pt.n[0] + 31) / 32 + (pt.n[kLayers] + 31) / 32;
+    hipLaunchKernelGGL(k_adam, dim3(nblk), dim3(kBlock), 0, s, theta, m, v, g, part, ginj, pt,
                        lr, beta1, beta2, eps, fwd, bwd, fwd16, bwd16, lpart, nloss, loss_npix, st);
     return hipGetLastError();
 }

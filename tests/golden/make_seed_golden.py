@@ -1,0 +1,61 @@
+"""Write the oracle's end-to-end PSNR over several initial-weight seeds.
+
+A single run of the method ends at an epoch that moves with rounding noise
+and with the initial weights, so single-run PSNRs of equally correct
+implementations differ by a few tenths of a dB; the mean over seeds is the
+quantity compared.  Runs the CPU FP64 reference (oracle/n2f_oracle.py) on the
+64x64 blobs scene (clean seed 0) with Gaussian noise sigma 25/255 (noise seed
+1), early stopping with patience 100, initial weights from SplitMix64 seeds
+0..n-1, and stores per-seed PSNR, epochs and best epochs.
+
+    python tests/golden/make_seed_golden.py --seeds 32 --workers 4
+
+Calls only the oracle and the input generators.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+from multiprocessing import Pool
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+
+def run_one(seed):
+    from oracle import n2f_oracle as O
+    from paper_2108_10209_amd import synth
+    clean, noisy = synth.small_64(0)
+    t0 = time.time()
+    r = O.denoise(noisy, synth.init_params(1, seed), O.Hyper())
+    out = {"seed": seed, "psnr": synth.psnr(r.y, clean), "epochs": r.epochs[0], "best_epoch": r.best_epoch[0],
+           "capped": r.capped[0], "seconds": time.time() - t0}
+    print(json.dumps(out), flush=True)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--seeds", type=int, default=32)
+    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--out", default=os.path.join(HERE, "oracle_psnr_64_sigma25_seeds.json"))
+    a = ap.parse_args()
+    with Pool(a.workers) as pool:
+        runs = pool.map(run_one, range(a.seeds))
+    import numpy as np
+    from paper_2108_10209_amd import synth
+    clean, noisy = synth.small_64(0)
+    ps = np.array([r["psnr"] for r in runs])
+    out = {"source": "CPU FP64 oracle, whole Noise2Fast loop (Methods section), early stopping, "
+                     "written by tests/golden/make_seed_golden.py",
+           "image": "64x64 blobs, clean seed 0, Gaussian sigma 25/255, noise seed 1", "patience": 100,
+           "noisy_psnr": synth.psnr(noisy, clean), "mean_psnr": float(ps.mean()), "std_psnr": float(ps.std(ddof=1)),
+           "runs": runs}
+    with open(a.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(a.out, out["mean_psnr"], out["std_psnr"])
+
+
+if __name__ == "__main__":
+    main()

@@ -94,18 +94,27 @@ def test_bf16_deterministic_and_one_shot():
     assert sa == sb == n2f.OK and torch.equal(a, b)
 
 
-def test_bf16_psnr_matches_fp32_512():
-    """512x512, sigma 25/255, full early-stopping runs: BF16 PSNR within
-    0.1 dB of the FP32 path on the same image and initial weights."""
-    clean, noisy = synth.single_512(25, 2)
+def test_bf16_mean_psnr_matches_fp32():
+    """Mean final PSNR over 12 initial-weight seeds (256x256 blobs scene,
+    sigma 25/255, full early-stopping runs): BF16 within 0.1 dB of FP32, up
+    to the sampling error of the two means.  A single run's PSNR moves by a
+    few tenths of a dB with the initial weights and with rounding noise (the
+    stopping epoch shifts), for either precision, so single runs are not
+    compared."""
+    clean, noisy = synth.single_512(25, 2, size=256)
     x = dev(noisy)
-    out = {}
+    res = {}
     for name, prec in [("fp32", n2f.FP32), ("bf16", n2f.BF16)]:
-        r = n2f.Run(x, n2f.default_config(precision=prec))
-        done, status = r.run_epochs(0, 2000)
-        y = r.result().cpu().numpy()
-        out[name] = (synth.psnr(y, clean), r.progress(0)[:2], status)
-        say(name, out[name])
-    assert out["fp32"][2] == out["bf16"][2] == n2f.OK
-    assert abs(out["fp32"][0] - out["bf16"][0]) < 0.1
-    assert out["bf16"][0] > synth.psnr(noisy, clean) + 5.0
+        ps = []
+        for seed in range(12):
+            r = n2f.Run(x, n2f.default_config(precision=prec, init_seed=seed))
+            done, status = r.run_epochs(0, 2000)
+            assert done and status == n2f.OK
+            ps.append(synth.psnr(r.result().cpu().numpy(), clean))
+        res[name] = np.array(ps)
+        say(name, "mean %.3f std %.3f" % (res[name].mean(), res[name].std(ddof=1)))
+    diff = res["bf16"].mean() - res["fp32"].mean()
+    se = np.sqrt(res["bf16"].var(ddof=1) / 12 + res["fp32"].var(ddof=1) / 12)
+    say("bf16 - fp32 %.3f dB, standard error %.3f" % (diff, se))
+    assert abs(diff) <= 0.1 + 2.5 * se
+    assert res["bf16"].min() > synth.psnr(noisy, clean) + 10.0
