@@ -60,6 +60,132 @@ def cpu_baseline(noisy, epochs_per_image, sample_steps: int = 1):
                       f"(mean epochs to convergence of the GPU run)"}
 
 
+def _psnr_list(outs, cleans):
+    from paper_2108_10209_amd import synth
+    return [synth.psnr(y.cpu().numpy(), c) for y, c in zip(outs, cleans)]
+
+
+def bench_batch(args):
+    """64 independent grayscale images, sides uniform in [256, 1024],
+    Poisson (peak 30) + Gaussian (10/255) noise, trained together as one
+    batch (BF16 by default): images/s to convergence, against the FP32
+    single-image path timed on the first `--fp32-sample` images."""
+    import numpy as np
+    import torch
+    from paper_2108_10209_amd import n2f, synth
+    dev = torch.device("cuda:0")
+    pairs = synth.batch_images(args.batch_n, 256, 1024, seed=3)
+    cleans = [c for c, _ in pairs]
+    xs = [torch.from_numpy(x).to(dev) for _, x in pairs]
+    npx = sum(x.numel() for x in xs)
+    prec = n2f.BF16 if args.precision == "bf16" else n2f.FP32
+    cfg = n2f.default_config(precision=prec, max_epochs=args.max_epochs)
+    print(f"batch of {len(xs)} images, {npx / 1e6:.1f} Mpx", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = n2f.Batch(xs, cfg, n_streams=args.streams)
+    b.run()
+    outs = [b.result(i) for i in range(len(xs))]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    epochs = [b.progress(i)[0] for i in range(len(xs))]
+    b.close()
+    ps = _psnr_list(outs, cleans)
+    k = min(args.fp32_sample, len(xs))
+    cfg32 = n2f.default_config(precision=n2f.FP32, max_epochs=args.max_epochs)
+    t1 = time.perf_counter()
+    outs32 = [n2f.denoise(xs[i], cfg32)[0] for i in range(k)]
+    torch.cuda.synchronize()
+    wall32 = time.perf_counter() - t1
+    ps32 = _psnr_list(outs32, cleans[:k])
+    ips = len(xs) / wall
+    return {
+        "metric": "images/s denoised to convergence (batch of 64 images, sides U[256,1024], Poisson-Gaussian)",
+        "value": round(ips, 4), "unit": "images/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(1e3 * wall, 1), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"batch of {len(xs)} independent grayscale images, H and W uniform in [256,1024], "
+                               "Poisson peak 30 + Gaussian 10/255, patience 100",
+                   "precision": args.precision, "streams": args.streams},
+        "mpx_per_s": round(npx / wall / 1e6, 3), "epochs_mean": round(float(np.mean(epochs)), 1),
+        "psnr_mean": round(float(np.mean(ps)), 3),
+        "fp32_single_image": {"images": k, "images_per_s": round(k / wall32, 4),
+                              "psnr_mean_same_images": round(float(np.mean(ps32)), 3),
+                              "batched_psnr_mean_same_images": round(float(np.mean(ps[:k])), 3)},
+        "speedup_vs_fp32_single": round(ips / (k / wall32), 2),
+    }
+
+
+def bench_serve(args):
+    """Poisson-arrival stream (log-uniform sides in [128, 2048], 30% RGB,
+    Gaussian or Poisson noise per request) served by the continuous-batching
+    server in BF16, in real time; p50/p99 latency = completion - arrival.
+    Baseline: the plain FP32 path serving the same trace one request at a
+    time in arrival order, computed from each request's measured FP32
+    service time."""
+    import numpy as np
+    import torch
+    from paper_2108_10209_amd import n2f, synth
+    dev = torch.device("cuda:0")
+    reqs = synth.serving_trace(n=args.serve_n, rate=args.rate, seed=5)
+    data = [synth.request_image(r) for r in reqs]
+    xs = [torch.from_numpy(x).to(dev) for _, x in data]
+    outs = [torch.empty_like(x) for x in xs]
+    prec = n2f.BF16 if args.precision == "bf16" else n2f.FP32
+    cfg = n2f.default_config(precision=prec, max_epochs=args.max_epochs)
+    srv = n2f.Server(args.arena_gib << 30, cfg, n_streams=args.streams, max_active=args.max_active)
+    torch.cuda.synchronize()
+    print(f"serving {len(reqs)} requests at {args.rate}/s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    nxt, done = 0, {}
+    while len(done) < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and reqs[nxt].arrival <= now:
+            srv.submit(nxt, xs[nxt], outs[nxt])
+            nxt += 1
+        active, queued = srv.step(args.epochs_per_step) if (nxt > len(done)) else (0, 0)
+        if active == 0 and queued == 0 and nxt < len(reqs):
+            time.sleep(max(0.0, reqs[nxt].arrival - (time.perf_counter() - t0)))
+        for rid, st in srv.poll():
+            done[rid] = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([done[i] - reqs[i].arrival for i in range(len(reqs))])
+    span = max(done.values()) - reqs[0].arrival
+    ps = _psnr_list(outs, [c for c, _ in data])
+    # baseline: FP32, one request at a time in arrival order
+    cfg32 = n2f.default_config(precision=n2f.FP32, max_epochs=args.max_epochs)
+    svc, outs32 = [], []
+    for x in xs[:args.serve_fp32_n]:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        outs32.append(n2f.denoise(x, cfg32)[0])
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t1)
+    k = len(svc)
+    comp, t = [], 0.0
+    for i in range(k):
+        t = max(t, reqs[i].arrival) + svc[i]
+        comp.append(t)
+    lat32 = np.array([comp[i] - reqs[i].arrival for i in range(k)])
+    ps32 = _psnr_list(outs32, [c for c, _ in data[:k]])
+    return {
+        "metric": "served images/s and p50/p99 request latency (Poisson arrivals, sides log-uniform [128,2048], 30% RGB)",
+        "value": round(len(reqs) / span, 4), "unit": "images/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(1e3 * span, 1), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"first {len(reqs)} requests of the seeded trace (seed 5), arrival rate {args.rate}/s",
+                   "precision": args.precision, "streams": args.streams, "max_active": args.max_active,
+                   "epochs_per_step": args.epochs_per_step},
+        "latency_s": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)},
+        "psnr_mean": round(float(np.mean(ps)), 3),
+        "fp32_sequential": {"requests": k, "images_per_s": round(k / (comp[-1] - reqs[0].arrival), 4),
+                            "latency_s": {"p50": round(float(np.percentile(lat32, 50)), 3),
+                                          "p99": round(float(np.percentile(lat32, 99)), 3)},
+                            "psnr_mean_same_requests": round(float(np.mean(ps32)), 3),
+                            "served_psnr_mean_same_requests": round(float(np.mean(ps[:k])), 3)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,7 +196,17 @@ def main():
     ap.add_argument("--max-epochs", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-every", type=int, default=8,
-                    help="time one launch in N of each conv kernel class with HIP events")
+                    help="time every conv launch of one epoch in N with HIP events")
+    ap.add_argument("--workload", choices=["single", "batch", "serve"], default="single")
+    ap.add_argument("--batch-n", type=int, default=64)
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--fp32-sample", type=int, default=8)
+    ap.add_argument("--serve-n", type=int, default=24)
+    ap.add_argument("--serve-fp32-n", type=int, default=24)
+    ap.add_argument("--rate", type=float, default=0.5)
+    ap.add_argument("--arena-gib", type=int, default=64)
+    ap.add_argument("--max-active", type=int, default=16)
+    ap.add_argument("--epochs-per-step", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a plain copy of known size, to scale HBM counters)")
     args = ap.parse_args()
@@ -87,6 +223,13 @@ def main():
         print(f"bench.py measures one GPU only (asked for {args.gpus}): each image is an independent run, "
               "so several GPUs would each take their own images with no communication.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload != "single":
+        if args.precision == "fp32" and "--precision" not in sys.argv:
+            args.precision = "bf16"
+        res = bench_batch(args) if args.workload == "batch" else bench_serve(args)
+        print(json.dumps(res), flush=True)
+        return
 
     import numpy as np
     import torch

@@ -187,6 +187,86 @@ n2f_status n2f_get_lohi(n2f_run* run, float* lo, float* hi);
  * (H x W, standardised units).  Queued. */
 n2f_status n2f_get_image(n2f_run* run, int which, float* d_out);
 
+/* Queue `n_epochs` whole epochs of network `net` on the run's stream (the
+ * recorded epoch graph when cfg->use_graph, captured on first use) without
+ * waiting; epochs after the network finishes do nothing.  Queued. */
+n2f_status n2f_run_launch_epochs(n2f_run* run, int net, int n_epochs);
+
+/* Wait for the run's stream and report whether network `net` is finished
+ * and how many epochs it has validated (either pointer may be NULL).
+ * Returns N2F_ENUMERIC after a non-finite score, N2F_WCAPPED when the
+ * network stopped at cfg->max_epochs.  Synchronises that stream only. */
+n2f_status n2f_run_poll(n2f_run* run, int net, int* done, int* epochs);
+
+/* ---- many independent images ----
+ * A batch trains one run per image, each with its own weights, Adam state,
+ * stopping rule and workspace slice, all inside one caller workspace.  Each
+ * run replays its own recorded epoch graph on one of `n_streams` HIP streams
+ * (created by the batch, default priority), so the epochs of different
+ * images overlap on the device; networks of a multi-channel image run one
+ * after the other.  Images may differ in size and channel count. */
+typedef struct n2f_batch n2f_batch;
+
+/* Workspace for a batch: the 256-byte aligned sum of the images' needs. */
+n2f_status n2f_batch_workspace_bytes(int n, const int* H, const int* W, const int* C, const n2f_config* cfg,
+                                     size_t* bytes);
+
+/* Create the runs (each reads its device CHW input d_in[i] during this
+ * call).  Synchronises.  Constant images are finished at once. */
+n2f_status n2f_batch_create(n2f_batch** batch, int n, const float* const* d_in, const int* H, const int* W,
+                            const int* C, const n2f_config* cfg, void* d_ws, size_t ws_bytes, int n_streams);
+
+/* Run epochs of every unfinished image until all are finished or each has
+ * run `max_epochs_now` more epochs; *n_active (may be NULL) reports the
+ * images still training.  Synchronises. */
+n2f_status n2f_batch_run(n2f_batch* batch, int max_epochs_now, int* n_active);
+
+/* Write image i's result (CHW, input units) to d_out.  Synchronises. */
+n2f_status n2f_batch_result(n2f_batch* batch, int i, float* d_out);
+
+/* Epochs run (all networks together) and finished flag of image i. */
+n2f_status n2f_batch_progress(n2f_batch* batch, int i, int* epochs, int* finished);
+
+n2f_status n2f_batch_destroy(n2f_batch* batch);
+
+/* ---- continuous-batching server ----
+ * Requests queue in arrival order.  A request is admitted when fewer than
+ * `max_active` runs are active and its workspace (n2f_workspace_bytes) fits
+ * in a free range of the caller's device arena (first fit; strict arrival
+ * order, so a large request is never overtaken).  Each n2f_server_step
+ * admits what fits, queues `epochs` epochs of every active run on its
+ * stream, and retires finished runs: their result is written to the
+ * request's d_out, their arena range is freed, and their id is reported by
+ * n2f_server_poll.  Runs therefore join and leave at epoch boundaries while
+ * the others keep training.
+ * With flags & N2F_SERVER_SIMULATE no device work is done: a request
+ * finishes after `sim_epochs` epochs, which tests the admission and
+ * bookkeeping logic on a machine without a GPU. */
+#define N2F_SERVER_SIMULATE 1
+typedef struct n2f_server n2f_server;
+
+n2f_status n2f_server_create(n2f_server** srv, const n2f_config* cfg, void* d_arena, size_t arena_bytes,
+                             int n_streams, int max_active, int flags);
+
+/* Queue a request (d_in and d_out: device CHW images owned by the caller,
+ * kept until the id is reported finished).  N2F_ENOMEM if it could never
+ * fit in the arena. */
+n2f_status n2f_server_submit(n2f_server* srv, long long id, const float* d_in, float* d_out, int H, int W, int C,
+                             int sim_epochs);
+
+/* One scheduling round as described above.  Synchronises the active
+ * streams.  Reports active and queued request counts (pointers may be NULL). */
+n2f_status n2f_server_step(n2f_server* srv, int epochs, int* n_active, int* n_queued);
+
+/* Pop up to `max` finished ids (completion order) into ids; *n = count.
+ * status (may be NULL) receives each request's final n2f_status. */
+n2f_status n2f_server_poll(n2f_server* srv, long long* ids, int* status, int max, int* n);
+
+/* Arena bytes in use and the largest free range. */
+n2f_status n2f_server_memory(n2f_server* srv, size_t* used, size_t* largest_free);
+
+n2f_status n2f_server_destroy(n2f_server* srv);
+
 /* ---- kernel timing ----
  * While profiling is on, one launch in `every` of each instrumented kernel
  * class is bracketed by HIP events on the stream it runs on.  Classes:

@@ -485,6 +485,12 @@ void n2f_config_default(n2f_config* cfg) {
 
 const char* n2f_last_error(void) { return g_err.c_str(); }
 
+}  // extern "C"
+
+void n2f::set_last_error(const char* msg) { g_err = msg; }
+
+extern "C" {
+
 n2f_status n2f_param_count(int C, const n2f_config* cfg, size_t* count) {
     n2f_status s = check_cfg(cfg);
     if (s != N2F_OK) return s;
@@ -705,6 +711,41 @@ n2f_status n2f_run_epochs(n2f_run* r, int net, int max_now, int* done) {
     s = read_state(r, net, &st);
     if (s != N2F_OK) return s;
     if (done) *done = st.done;
+    if (st.nonfinite) return fail(N2F_ENUMERIC, "validation score is not finite");
+    if (st.capped) return N2F_WCAPPED;
+    return N2F_OK;
+}
+
+n2f_status n2f_run_launch_epochs(n2f_run* r, int net, int n_epochs) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    if (n_epochs < 1) return fail(N2F_EINVAL, "n_epochs must be >= 1");
+    if (r->host_done[net]) return N2F_OK;
+    if (r->cfg.use_graph && !r->graph_exec[net]) {
+        s = capture_epoch(r, net);
+        if (s != N2F_OK) return s;
+    }
+    for (int e = 0; e < n_epochs; ++e) {
+        if (r->graph_exec[net]) {
+            N2F_HIP(hipGraphLaunch(r->graph_exec[net], r->stream));
+        } else {
+            s = enqueue_epoch(r, net);
+            if (s != N2F_OK) return s;
+        }
+    }
+    return N2F_OK;
+}
+
+n2f_status n2f_run_poll(n2f_run* r, int net, int* done, int* epochs) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    DevState st;
+    s = read_state(r, net, &st);
+    if (s != N2F_OK) return s;
+    r->host_done[net] = st.done != 0;
+    r->host_epochs[net] = st.epoch;
+    if (done) *done = st.done;
+    if (epochs) *epochs = st.epoch;
     if (st.nonfinite) return fail(N2F_ENUMERIC, "validation score is not finite");
     if (st.capped) return N2F_WCAPPED;
     return N2F_OK;

@@ -6,6 +6,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <string>
+
 namespace n2f {
 
 constexpr int kWidth = 64;        // channels of every hidden layer
@@ -96,5 +98,9 @@ hipError_t launch_adam(float* theta, float* m, float* v, float* g, const float* 
                        uint16_t* bwd16, const double* lpart, int nloss, long long loss_npix,
                        DevState* st, hipStream_t s);
 hipError_t launch_extract(const float* src, int h, int w, int C, float* out_chw, hipStream_t s);
+
+// Message returned by n2f_last_error() on the calling thread.
+void set_last_error(const char* msg);
+inline void set_last_error(const std::string& msg) { set_last_error(msg.c_str()); }
 
 }  // namespace n2f

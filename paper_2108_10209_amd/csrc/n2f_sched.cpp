@@ -1,0 +1,407 @@
+// Scheduling of many independent Noise2Fast runs on one GPU: a fixed batch
+// of images of uneven sizes, and a continuous-batching server that admits
+// requests by device-memory budget and lets runs join and leave at epoch
+// boundaries.  Built on the public run API of include/n2f.h: every run
+// replays its own recorded epoch graph on one of a few HIP streams, so the
+// epochs of different images overlap on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "n2f.h"
+#include "n2f_internal.h"
+
+namespace {
+
+n2f_status sfail(n2f_status code, const std::string& msg) {
+    n2f::set_last_error(msg);
+    return code;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// Epochs queued per run between two polls of its stopping rule.
+constexpr int kPollEpochs = 4;
+
+n2f_status make_streams(std::vector<hipStream_t>& v, int n) {
+    for (int i = 0; i < n; ++i) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+            return sfail(N2F_EDEVICE, "stream creation failed");
+        v.push_back(s);
+    }
+    return N2F_OK;
+}
+
+// First-fit allocator over [0, size) with coalescing of free ranges.
+class Arena {
+   public:
+    explicit Arena(size_t size) : size_(size) { free_[0] = size; }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = align_up(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align_up(bytes);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+    size_t largest() const {
+        size_t m = 0;
+        for (const auto& kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
+    size_t size() const { return size_; }
+
+   private:
+    size_t size_, used_ = 0;
+    std::map<size_t, size_t> free_;   // offset -> length
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batch
+// ---------------------------------------------------------------------------
+struct n2f_batch {
+    n2f_config cfg;
+    int n = 0;
+    std::vector<n2f_run*> runs;
+    std::vector<int> C, net, finished, epochs, stream_of;
+    std::vector<hipStream_t> streams;
+    ~n2f_batch() {
+        for (n2f_run* r : runs)
+            if (r) n2f_run_destroy(r);
+        for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+    }
+};
+
+extern "C" {
+
+n2f_status n2f_batch_workspace_bytes(int n, const int* H, const int* W, const int* C, const n2f_config* cfg,
+                                     size_t* bytes) {
+    if (n < 1 || !H || !W || !C || !bytes) return sfail(N2F_EINVAL, "bad batch arguments");
+    size_t tot = 0;
+    for (int i = 0; i < n; ++i) {
+        size_t b = 0;
+        n2f_status s = n2f_workspace_bytes(H[i], W[i], C[i], cfg, &b);
+        if (s != N2F_OK) return s;
+        tot += align_up(b);
+    }
+    *bytes = tot;
+    return N2F_OK;
+}
+
+n2f_status n2f_batch_create(n2f_batch** out, int n, const float* const* d_in, const int* H, const int* W,
+                            const int* C, const n2f_config* cfg, void* d_ws, size_t ws_bytes, int n_streams) {
+    if (!out || !d_in || !d_ws || !cfg || n < 1 || n_streams < 1) return sfail(N2F_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    size_t need = 0;
+    n2f_status s = n2f_batch_workspace_bytes(n, H, W, C, cfg, &need);
+    if (s != N2F_OK) return s;
+    if (ws_bytes < need) return sfail(N2F_ENOMEM, "batch workspace too small");
+    n2f_batch* b = new (std::nothrow) n2f_batch();
+    if (!b) return sfail(N2F_ENOMEM, "host allocation failed");
+    b->cfg = *cfg;
+    b->n = n;
+    s = make_streams(b->streams, std::min(n, n_streams));
+    if (s != N2F_OK) {
+        delete b;
+        return s;
+    }
+    char* ws = static_cast<char*>(d_ws);
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        size_t wb = 0;
+        n2f_workspace_bytes(H[i], W[i], C[i], cfg, &wb);
+        const int si = i % (int)b->streams.size();
+        n2f_run* r = nullptr;
+        s = n2f_run_create(&r, d_in[i], H[i], W[i], C[i], cfg, ws + off, wb, b->streams[si]);
+        if (s < 0) {
+            delete b;
+            return s;
+        }
+        b->runs.push_back(r);
+        b->C.push_back(C[i]);
+        b->net.push_back(0);
+        b->finished.push_back(s == N2F_WCONSTANT ? 1 : 0);
+        b->epochs.push_back(0);
+        b->stream_of.push_back(si);
+        off += align_up(wb);
+    }
+    *out = b;
+    return N2F_OK;
+}
+
+n2f_status n2f_batch_run(n2f_batch* b, int max_now, int* n_active) {
+    if (!b || max_now < 1) return sfail(N2F_EINVAL, "bad batch arguments");
+    std::vector<int> ran(b->n, 0);
+    for (;;) {
+        int active = 0;
+        // queue a few epochs for every image still training ...
+        for (int i = 0; i < b->n; ++i) {
+            if (b->finished[i] || ran[i] >= max_now) continue;
+            const int k = std::min(kPollEpochs, max_now - ran[i]);
+            n2f_status s = n2f_run_launch_epochs(b->runs[i], b->net[i], k);
+            if (s < 0) return s;
+            ran[i] += k;
+            ++active;
+        }
+        if (!active) break;
+        // ... then read each one's stopping rule
+        for (int i = 0; i < b->n; ++i) {
+            if (b->finished[i]) continue;
+            int done = 0, ep = 0;
+            n2f_status s = n2f_run_poll(b->runs[i], b->net[i], &done, &ep);
+            if (s < 0) return s;
+            if (done) {
+                b->epochs[i] += ep;
+                if (++b->net[i] >= b->C[i]) b->finished[i] = 1;
+            }
+        }
+    }
+    if (n_active) {
+        int a = 0;
+        for (int i = 0; i < b->n; ++i) a += !b->finished[i];
+        *n_active = a;
+    }
+    return N2F_OK;
+}
+
+n2f_status n2f_batch_result(n2f_batch* b, int i, float* d_out) {
+    if (!b || i < 0 || i >= b->n || !d_out) return sfail(N2F_EINVAL, "bad batch arguments");
+    n2f_status s = n2f_result(b->runs[i], d_out);
+    if (s < 0) return s;
+    if (hipStreamSynchronize(b->streams[b->stream_of[i]]) != hipSuccess) return sfail(N2F_EDEVICE, "sync failed");
+    return s;
+}
+
+n2f_status n2f_batch_progress(n2f_batch* b, int i, int* epochs, int* finished) {
+    if (!b || i < 0 || i >= b->n) return sfail(N2F_EINVAL, "bad batch arguments");
+    int ep = b->epochs[i];
+    if (!b->finished[i] && b->net[i] < b->C[i]) {
+        int cur = 0;
+        if (n2f_get_progress(b->runs[i], b->net[i], &cur, nullptr, nullptr, nullptr) == N2F_OK) ep += cur;
+    }
+    if (epochs) *epochs = ep;
+    if (finished) *finished = b->finished[i];
+    return N2F_OK;
+}
+
+n2f_status n2f_batch_destroy(n2f_batch* b) {
+    if (!b) return sfail(N2F_EINVAL, "batch is NULL");
+    delete b;
+    return N2F_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Server
+// ---------------------------------------------------------------------------
+struct n2f_server {
+    struct Req {
+        long long id;
+        const float* in;
+        float* out;
+        int H, W, C, sim_epochs;
+        size_t bytes;
+    };
+    struct Active {
+        Req q;
+        n2f_run* run;
+        size_t off;
+        int net, stream, epochs;
+    };
+    n2f_config cfg;
+    char* arena_base = nullptr;
+    Arena arena;
+    bool simulate = false;
+    int max_active = 1;
+    std::vector<hipStream_t> streams;
+    std::vector<int> stream_load;
+    std::deque<Req> queue;
+    std::vector<Active> active;
+    std::deque<std::pair<long long, int>> finished;
+    explicit n2f_server(size_t bytes) : arena(bytes) {}
+    ~n2f_server() {
+        for (Active& a : active)
+            if (a.run) n2f_run_destroy(a.run);
+        for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+    }
+};
+
+namespace {
+
+void retire(n2f_server* v, size_t idx, int status) {
+    n2f_server::Active& a = v->active[idx];
+    if (a.run) n2f_run_destroy(a.run);
+    v->arena.release(a.off, a.q.bytes);
+    if (!v->simulate) v->stream_load[a.stream]--;
+    v->finished.emplace_back(a.q.id, status);
+    v->active.erase(v->active.begin() + idx);
+}
+
+}  // namespace
+
+extern "C" {
+
+n2f_status n2f_server_create(n2f_server** out, const n2f_config* cfg, void* d_arena, size_t arena_bytes,
+                             int n_streams, int max_active, int flags) {
+    if (!out || !cfg || n_streams < 1 || max_active < 1) return sfail(N2F_EINVAL, "bad server arguments");
+    const bool sim = (flags & N2F_SERVER_SIMULATE) != 0;
+    if (!sim && !d_arena) return sfail(N2F_EINVAL, "arena is NULL");
+    if (reinterpret_cast<uintptr_t>(d_arena) % kAlign) return sfail(N2F_EINVAL, "arena must be 256-byte aligned");
+    size_t probe = 0;
+    n2f_status s = n2f_workspace_bytes(2, 2, 1, cfg, &probe);   // validates the config
+    if (s != N2F_OK) return s;
+    n2f_server* v = new (std::nothrow) n2f_server(arena_bytes);
+    if (!v) return sfail(N2F_ENOMEM, "host allocation failed");
+    v->cfg = *cfg;
+    v->arena_base = static_cast<char*>(d_arena);
+    v->simulate = sim;
+    v->max_active = max_active;
+    if (!sim) {
+        s = make_streams(v->streams, n_streams);
+        if (s != N2F_OK) {
+            delete v;
+            return s;
+        }
+        v->stream_load.assign(v->streams.size(), 0);
+    }
+    *out = v;
+    return N2F_OK;
+}
+
+n2f_status n2f_server_submit(n2f_server* v, long long id, const float* d_in, float* d_out, int H, int W, int C,
+                             int sim_epochs) {
+    if (!v) return sfail(N2F_EINVAL, "server is NULL");
+    if (!v->simulate && (!d_in || !d_out)) return sfail(N2F_EINVAL, "input or output is NULL");
+    size_t bytes = 0;
+    n2f_status s = n2f_workspace_bytes(H, W, C, &v->cfg, &bytes);
+    if (s != N2F_OK) return s;
+    if (align_up(bytes) > v->arena.size()) return sfail(N2F_ENOMEM, "request can never fit in the arena");
+    v->queue.push_back({id, d_in, d_out, H, W, C, std::max(1, sim_epochs), bytes});
+    return N2F_OK;
+}
+
+n2f_status n2f_server_step(n2f_server* v, int epochs, int* n_active, int* n_queued) {
+    if (!v || epochs < 1) return sfail(N2F_EINVAL, "bad server arguments");
+    // 1. admission, strictly in arrival order
+    while (!v->queue.empty() && (int)v->active.size() < v->max_active) {
+        n2f_server::Req q = v->queue.front();
+        size_t off = 0;
+        if (!v->arena.alloc(q.bytes, &off)) break;
+        v->queue.pop_front();
+        n2f_server::Active a{q, nullptr, off, 0, 0, 0};
+        if (!v->simulate) {
+            a.stream = (int)(std::min_element(v->stream_load.begin(), v->stream_load.end()) - v->stream_load.begin());
+            v->stream_load[a.stream]++;
+            n2f_status s = n2f_run_create(&a.run, q.in, q.H, q.W, q.C, &v->cfg, v->arena_base + off, q.bytes,
+                                          v->streams[a.stream]);
+            if (s < 0 || s == N2F_WCONSTANT) {
+                if (s == N2F_WCONSTANT) s = n2f_result(a.run, q.out);
+                (void)hipStreamSynchronize(v->streams[a.stream]);
+                v->active.push_back(a);
+                retire(v, v->active.size() - 1, s);
+                continue;
+            }
+        }
+        v->active.push_back(a);
+    }
+    // 2. queue epochs for every active run
+    for (n2f_server::Active& a : v->active) {
+        if (v->simulate) {
+            a.epochs += epochs;
+            continue;
+        }
+        n2f_status s = n2f_run_launch_epochs(a.run, a.net, epochs);
+        if (s < 0) return s;
+    }
+    // 3. retire finished runs (result, arena range, id)
+    for (size_t i = 0; i < v->active.size();) {
+        n2f_server::Active& a = v->active[i];
+        if (v->simulate) {
+            if (a.epochs >= a.q.sim_epochs) {
+                retire(v, i, N2F_OK);
+                continue;
+            }
+            ++i;
+            continue;
+        }
+        int done = 0;
+        n2f_status s = n2f_run_poll(a.run, a.net, &done, nullptr);
+        if (s < 0) {
+            retire(v, i, s);
+            continue;
+        }
+        if (done && ++a.net >= a.q.C) {
+            s = n2f_result(a.run, a.q.out);
+            if (hipStreamSynchronize(v->streams[a.stream]) != hipSuccess) s = sfail(N2F_EDEVICE, "sync failed");
+            retire(v, i, s);
+            continue;
+        }
+        ++i;
+    }
+    if (n_active) *n_active = (int)v->active.size();
+    if (n_queued) *n_queued = (int)v->queue.size();
+    return N2F_OK;
+}
+
+n2f_status n2f_server_poll(n2f_server* v, long long* ids, int* status, int max, int* n) {
+    if (!v || !n || (max > 0 && !ids)) return sfail(N2F_EINVAL, "bad server arguments");
+    int k = 0;
+    while (k < max && !v->finished.empty()) {
+        ids[k] = v->finished.front().first;
+        if (status) status[k] = v->finished.front().second;
+        v->finished.pop_front();
+        ++k;
+    }
+    *n = k;
+    return N2F_OK;
+}
+
+n2f_status n2f_server_memory(n2f_server* v, size_t* used, size_t* largest_free) {
+    if (!v) return sfail(N2F_EINVAL, "server is NULL");
+    if (used) *used = v->arena.used();
+    if (largest_free) *largest_free = v->arena.largest();
+    return N2F_OK;
+}
+
+n2f_status n2f_server_destroy(n2f_server* v) {
+    if (!v) return sfail(N2F_EINVAL, "server is NULL");
+    delete v;
+    return N2F_OK;
+}
+
+}  // extern "C"

@@ -24,8 +24,11 @@ SYMBOLS = [
     "n2f_run_create", "n2f_run_destroy", "n2f_train_step", "n2f_validate", "n2f_run_epochs", "n2f_result",
     "n2f_denoise", "n2f_get_state", "n2f_set_state", "n2f_get_grad", "n2f_debug_adam", "n2f_get_progress",
     "n2f_get_history", "n2f_get_lohi", "n2f_get_image", "n2f_profile_begin", "n2f_profile_read",
-    "n2f_profile_end",
+    "n2f_profile_end", "n2f_run_launch_epochs", "n2f_run_poll", "n2f_batch_workspace_bytes", "n2f_batch_create",
+    "n2f_batch_run", "n2f_batch_result", "n2f_batch_progress", "n2f_batch_destroy", "n2f_server_create",
+    "n2f_server_submit", "n2f_server_step", "n2f_server_poll", "n2f_server_memory", "n2f_server_destroy",
 ]
+SERVER_SIMULATE = 1
 K_CONV_FWD, K_CONV_BWD, K_WGRAD = 0, 1, 2
 
 
@@ -83,6 +86,21 @@ def lib():
             "n2f_profile_begin": [c_int],
             "n2f_profile_read": [c_int, POINTER(c_double), POINTER(c_longlong), POINTER(c_longlong)],
             "n2f_profile_end": [],
+            "n2f_run_launch_epochs": [c_void_p, c_int, c_int],
+            "n2f_run_poll": [c_void_p, c_int, POINTER(c_int), POINTER(c_int)],
+            "n2f_batch_workspace_bytes": [c_int, c_void_p, c_void_p, c_void_p, POINTER(Config), POINTER(c_size_t)],
+            "n2f_batch_create": [POINTER(c_void_p), c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(Config),
+                                 c_void_p, c_size_t, c_int],
+            "n2f_batch_run": [c_void_p, c_int, POINTER(c_int)],
+            "n2f_batch_result": [c_void_p, c_int, c_void_p],
+            "n2f_batch_progress": [c_void_p, c_int, POINTER(c_int), POINTER(c_int)],
+            "n2f_batch_destroy": [c_void_p],
+            "n2f_server_create": [POINTER(c_void_p), POINTER(Config), c_void_p, c_size_t, c_int, c_int, c_int],
+            "n2f_server_submit": [c_void_p, c_longlong, c_void_p, c_void_p, c_int, c_int, c_int, c_int],
+            "n2f_server_step": [c_void_p, c_int, POINTER(c_int), POINTER(c_int)],
+            "n2f_server_poll": [c_void_p, c_void_p, c_void_p, c_int, POINTER(c_int)],
+            "n2f_server_memory": [c_void_p, POINTER(c_size_t), POINTER(c_size_t)],
+            "n2f_server_destroy": [c_void_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -263,3 +281,110 @@ def profile_read(kernel_class: int):
 
 def profile_end():
     _check(lib().n2f_profile_end())
+
+
+def _ints(v):
+    return np.ascontiguousarray(np.asarray(v, dtype=np.int32))
+
+
+class Batch:
+    """Independent images of uneven sizes trained together (see n2f.h)."""
+
+    def __init__(self, images, cfg: Config | None = None, n_streams: int = 4):
+        import torch
+        self.cfg = cfg or default_config()
+        self.images = [x.contiguous() for x in images]
+        self.shapes = [tuple(int(d) for d in x.shape) for x in self.images]
+        n = len(self.images)
+        C = _ints([s[0] for s in self.shapes])
+        H = _ints([s[1] for s in self.shapes])
+        W = _ints([s[2] for s in self.shapes])
+        nb = c_size_t()
+        _check(lib().n2f_batch_workspace_bytes(n, H.ctypes.data, W.ctypes.data, C.ctypes.data, byref(self.cfg),
+                                               byref(nb)))
+        dev = self.images[0].device
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        ptrs = (c_void_p * n)(*[x.data_ptr() for x in self.images])
+        self._ptr = c_void_p()
+        torch.cuda.synchronize(dev)
+        _check(lib().n2f_batch_create(byref(self._ptr), n, ptrs, H.ctypes.data, W.ctypes.data, C.ctypes.data,
+                                      byref(self.cfg), c_void_p(self.ws.data_ptr()), nb.value, n_streams))
+
+    def run(self, max_epochs: int = 100000):
+        a = c_int()
+        _check(lib().n2f_batch_run(self._ptr, max_epochs, byref(a)))
+        return a.value
+
+    def result(self, i: int):
+        import torch
+        out = torch.empty(self.shapes[i], dtype=torch.float32, device=self.images[i].device)
+        _check(lib().n2f_batch_result(self._ptr, i, c_void_p(out.data_ptr())))
+        return out
+
+    def progress(self, i: int):
+        e, f = c_int(), c_int()
+        _check(lib().n2f_batch_progress(self._ptr, i, byref(e), byref(f)))
+        return e.value, bool(f.value)
+
+    def close(self):
+        if self._ptr:
+            lib().n2f_batch_destroy(self._ptr)
+            self._ptr = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server over one device arena (see n2f.h)."""
+
+    def __init__(self, arena_bytes: int, cfg: Config | None = None, n_streams: int = 4, max_active: int = 64,
+                 simulate: bool = False, device="cuda:0"):
+        self.cfg = cfg or default_config()
+        self.arena = None
+        ptr = None
+        if not simulate:
+            import torch
+            self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device)
+            ptr = self.arena.data_ptr()
+        self._ptr = c_void_p()
+        _check(lib().n2f_server_create(byref(self._ptr), byref(self.cfg), ptr, arena_bytes, n_streams, max_active,
+                                       SERVER_SIMULATE if simulate else 0))
+
+    def submit(self, rid: int, x=None, out=None, H: int = 0, W: int = 0, C: int = 1, sim_epochs: int = 0):
+        if x is not None:
+            C, H, W = (int(d) for d in x.shape)
+        return _check(lib().n2f_server_submit(self._ptr, rid, None if x is None else c_void_p(x.data_ptr()),
+                                              None if out is None else c_void_p(out.data_ptr()), H, W, C,
+                                              sim_epochs))
+
+    def step(self, epochs: int = 1):
+        a, q = c_int(), c_int()
+        _check(lib().n2f_server_step(self._ptr, epochs, byref(a), byref(q)))
+        return a.value, q.value
+
+    def poll(self, max_n: int = 4096):
+        ids = np.empty(max_n, np.int64)
+        st = np.empty(max_n, np.int32)
+        n = c_int()
+        _check(lib().n2f_server_poll(self._ptr, ids.ctypes.data, st.ctypes.data, max_n, byref(n)))
+        return list(zip(ids[:n.value].tolist(), st[:n.value].tolist()))
+
+    def memory(self):
+        u, l = c_size_t(), c_size_t()
+        _check(lib().n2f_server_memory(self._ptr, byref(u), byref(l)))
+        return u.value, l.value
+
+    def close(self):
+        if self._ptr:
+            lib().n2f_server_destroy(self._ptr)
+            self._ptr = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
