@@ -191,7 +191,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="bf16")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison run")
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--max-epochs", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -225,8 +226,6 @@ def main():
         sys.exit(2)
 
     if args.workload != "single":
-        if args.precision == "fp32" and "--precision" not in sys.argv:
-            args.precision = "bf16"
         res = bench_batch(args) if args.workload == "batch" else bench_serve(args)
         print(json.dumps(res), flush=True)
         return
@@ -238,15 +237,70 @@ def main():
     dev = torch.device("cuda:0")
     sigmas = [15, 25, 50]
     imgs = []
-    for i, s in enumerate(sigmas):
-        clean, noisy = synth.single_512(s, noise_seed=i + 1, size=args.size)
-        imgs.append((s, clean, noisy, torch.from_numpy(noisy).to(dev)))
-    prec = n2f.BF16 if args.precision == "bf16" else n2f.FP32
+    for i, sg in enumerate(sigmas):
+        clean, noisy = synth.single_512(sg, noise_seed=i + 1, size=args.size)
+        imgs.append((sg, clean, noisy, torch.from_numpy(noisy).to(dev)))
+    head = args.precision
+    runs = {head: run_single(args, imgs, head, profile=True)}
+    if not args.no_fp32 and head != "fp32":
+        runs["fp32"] = run_single(args, imgs, "fp32", profile=False)
+    r = runs[head]
+    prof = r["prof"]
+    dom = max(prof, key=lambda c: prof[c][0])
+    ms, nl, px = prof[dom]
+    achieved = px * CONV_FLOP_PER_PX / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    kern = {KNAMES[c]: {"total_ms_sampled": round(prof[c][0], 3), "launches_sampled": prof[c][1],
+                        "avg_us": round(1e3 * prof[c][0] / max(prof[c][1], 1), 2),
+                        "tflops": round(prof[c][2] * CONV_FLOP_PER_PX / max(prof[c][0], 1e-9) / 1e9, 2)}
+            for c in KNAMES}
+    npx = args.size * args.size
+    result = {
+        "metric": "images/s denoised to convergence (512x512 grayscale, sigma 15/25/50, early stopping)",
+        "value": round(r["ips"], 4),
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * r["wall"] / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": round(r["ips"] / (1.0 / 45.0), 2),
+        "baseline_note": "paper: under 45 s per 512x512 image on an RTX 5000 mobile (context only)",
+        "dtype": head,
+        "data": "synthetic",
+        "config": {"workload": f"single {args.size}x{args.size} grayscale, Gaussian sigma 15/25/50 per 255, "
+                               "patience 100, one image per step",
+                   "precision": head, "global_batch": 1, "image": f"{args.size}x{args.size}x1"},
+        "mpx_per_s": round(r["ips"] * npx / 1e6, 4),
+        "latency_s": r["latency"],
+        "epochs_mean": r["epochs_mean"],
+        "per_image": r["per_image"],
+        "kernels": kern,
+        "roofline": {"bound": "mfma", "kernel": KNAMES[dom], "achieved": round(achieved, 2),
+                     "peak": PEAK[head], "unit": "TFLOP/s", "frac": round(achieved / PEAK[head], 4),
+                     "traffic": measured_traffic(KERNEL_SYMBOL[(head, dom)])},
+    }
+    for k, v in runs.items():
+        if k != head:
+            result[k] = {"value": round(v["ips"], 4), "unit": "images/s", "epochs_mean": v["epochs_mean"],
+                         "per_image": v["per_image"], "ms_per_step": round(1e3 * v["wall"] / args.steps, 2)}
+    if not args.no_cpu_baseline:
+        print("cpu baseline ...", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(imgs[1][2], float(r["epochs_mean"]))
+    print(json.dumps(result), flush=True)
+
+
+def run_single(args, imgs, precision, profile):
+    """Time args.steps whole-image denoises (after args.warmup untimed ones)."""
+    import numpy as np
+    import torch
+    from paper_2108_10209_amd import n2f, synth
+    prec = n2f.BF16 if precision == "bf16" else n2f.FP32
     cfg = n2f.default_config(precision=prec, max_epochs=args.max_epochs)
-    ws = torch.empty(n2f.workspace_bytes(args.size, args.size, 1, cfg), dtype=torch.uint8, device=dev)
+    ws = torch.empty(n2f.workspace_bytes(args.size, args.size, 1, cfg), dtype=torch.uint8, device="cuda:0")
 
     def step(i):
-        s, clean, noisy, x = imgs[i % len(imgs)]
+        sg, clean, noisy, x = imgs[i % len(imgs)]
         t0 = time.perf_counter()
         run = n2f.Run(x, cfg, ws=ws)
         _, status = run.run_epochs(0, args.max_epochs)
@@ -259,68 +313,59 @@ def main():
 
     for i in range(args.warmup):
         step(i)
-        print(f"warmup {i} done", file=sys.stderr, flush=True)
+        print(f"{precision} warmup {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    n2f.profile_begin(args.profile_every)
+    if profile:
+        n2f.profile_begin(args.profile_every)
     t0 = time.perf_counter()
     outs = []
     for i in range(args.steps):
         outs.append(step(i))
-        print(f"step {i} done: {outs[-1][1]} epochs, {outs[-1][3]:.2f} s", file=sys.stderr, flush=True)
+        print(f"{precision} step {i} done: {outs[-1][1]} epochs, {outs[-1][3]:.2f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    n2f.profile_end()
-
-    psnrs, epochs, lats = [], [], []
+    prof = None
+    if profile:
+        n2f.profile_end()
+        prof = {c: n2f.profile_read(c) for c in KNAMES}
+    per, epochs, lats = [], [], []
     for i, (y, e, be, lat, status) in enumerate(outs):
-        s, clean, noisy, _ = imgs[i % len(imgs)]
-        psnrs.append({"sigma": s, "psnr": round(synth.psnr(y.cpu().numpy(), clean), 3),
-                      "noisy_psnr": round(synth.psnr(noisy, clean), 3), "epochs": e, "best_epoch": be,
-                      "capped": status == n2f.WCAPPED})
+        sg, clean, noisy, _ = imgs[i % len(imgs)]
+        per.append({"sigma": sg, "psnr": round(synth.psnr(y.cpu().numpy(), clean), 3),
+                    "noisy_psnr": round(synth.psnr(noisy, clean), 3), "epochs": e, "best_epoch": be,
+                    "capped": status == n2f.WCAPPED})
         epochs.append(e)
         lats.append(lat)
+    return {"ips": args.steps / wall, "wall": wall, "prof": prof, "per_image": per,
+            "epochs_mean": round(float(np.mean(epochs)), 1),
+            "latency": {"p50": round(float(np.percentile(lats, 50)), 3),
+                        "p99": round(float(np.percentile(lats, 99)), 3)}}
 
-    prof = {c: n2f.profile_read(c) for c in KNAMES}
-    dom = max(prof, key=lambda c: prof[c][0])
-    ms, nl, px = prof[dom]
-    achieved = px * CONV_FLOP_PER_PX / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-    kern = {KNAMES[c]: {"total_ms": round(prof[c][0], 3), "launches": prof[c][1],
-                        "avg_us": round(1e3 * prof[c][0] / max(prof[c][1], 1), 2),
-                        "tflops": round(prof[c][2] * CONV_FLOP_PER_PX / max(prof[c][0], 1e-9) / 1e9, 2)}
-            for c in KNAMES}
 
-    ips = args.steps / wall
-    npx = args.size * args.size
-    result = {
-        "metric": "images/s denoised to convergence (512x512 grayscale, sigma 15/25/50, early stopping)",
-        "value": round(ips, 4),
-        "unit": "images/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * wall / args.steps, 2),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": round(ips / (1.0 / 45.0), 2),
-        "baseline_note": "paper: under 45 s per 512x512 image on an RTX 5000 mobile (context only)",
-        "dtype": "f32" if prec == n2f.FP32 else "bf16",
-        "data": "synthetic",
-        "config": {"workload": f"single {args.size}x{args.size} grayscale, Gaussian sigma 15/25/50 per 255, "
-                               "patience 100, one image per step",
-                   "precision": args.precision, "global_batch": 1, "image": f"{args.size}x{args.size}x1"},
-        "mpx_per_s": round(ips * npx / 1e6, 4),
-        "latency_s": {"p50": round(float(np.percentile(lats, 50)), 3), "p99": round(float(np.percentile(lats, 99)), 3)},
-        "epochs_mean": round(float(np.mean(epochs)), 1),
-        "per_image": psnrs,
-        "kernels": kern,
-        "roofline": {"bound": "mfma", "kernel": KNAMES[dom], "achieved": round(achieved, 2),
-                     "peak": PEAK[args.precision], "unit": "TFLOP/s", "frac": round(achieved / PEAK[args.precision], 4),
-                     "traffic": None},
-    }
-    if not args.no_cpu_baseline:
-        print("cpu baseline ...", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(imgs[1][2], float(np.mean(epochs)))
-    print(json.dumps(result), flush=True)
+# kernel symbol prefix of each (precision, class), as rocprofv3 names them
+KERNEL_SYMBOL = {("bf16", 0): "k_conv_bf16<0>", ("bf16", 1): "k_conv_bf16<1>", ("bf16", 2): "k_wgrad_bf16",
+                 ("fp32", 0): "k_conv_f32<0>", ("fp32", 1): "k_conv_f32<1>", ("fp32", 2): "k_wgrad_f32"}
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic.md")
+CONV_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2108_10209_amd", "csrc", "n2f_conv.hip")
+
+
+def measured_traffic(symbol):
+    """HBM bytes per launch of `symbol` from the committed rocprofv3 counter
+    summary, or None when it is missing or was taken on other kernel source."""
+    import hashlib
+    try:
+        src = hashlib.sha256(open(CONV_SRC, "rb").read()).hexdigest()[:16]
+        for line in open(TRAFFIC_FILE):
+            if line.startswith("traffic:"):
+                kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+                if kv.get("kernel") == symbol and kv.get("src_sha256_16") == src:
+                    return {"fetch_bytes_per_launch": float(kv["fetch_bytes"]),
+                            "write_bytes_per_launch": float(kv["write_bytes"]),
+                            "bytes_per_launch": float(kv["fetch_bytes"]) + float(kv["write_bytes"]),
+                            "algorithmic_bytes_per_launch": float(kv["algorithmic_bytes"])}
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
 
 
 if __name__ == "__main__":

@@ -199,106 +199,176 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 
 __device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
-constexpr int kHSb = 72;   // LDS bf16 per staged pixel (144 B: 8 lanes of a 16-byte read hit 32 banks)
 
 
 // MODE 0: forward, bias + ReLU.  MODE 1: data gradient masked by [a > 0].
-// 16x16 pixel tile per 256-thread block, halo staged pixel-major in LDS;
-// wave wv computes tile rows 4wv..4wv+3 x 64 channels (4x4 MFMA tiles).
-// The result goes back through LDS so each pixel's 64 channels leave as
-// one 128-byte row.
+// One persistent 512-thread block per CU.  The layer's packed weights (9 x
+// 64 x 64 BF16, 72 KiB) stay in LDS for all the block's tiles.  The 8 waves
+// form two groups; each group computes its own 16x16 tile from its own halo
+// buffer (18 x 18 pixels x 64 BF16, the 16-byte chunks of each pixel
+// XOR-swizzled by the pixel index: no padding, and the 8 lanes of a 128-bit
+// read land on 32 distinct banks), so two waves share each SIMD.  While a
+// group computes, the halo of its next tile is already loading into
+// registers.
+// The MFMA takes the weights as its first operand (rows = output channels)
+// and the activations as its second (columns = pixels), so a lane's four
+// accumulators are four consecutive channels of one pixel and leave as one
+// 8-byte store.  The activation fragment of a tile row is read once per
+// (dy, channel half): the dx = 1 and dx = 2 fragments are the same data
+// moved one lane down each 16-lane DPP row, with the one pixel that enters
+// at the row end taken from a broadcast LDS read.
+constexpr int kHaloPix = kHalo * kHalo;               // 324 staged pixels
+constexpr int kHaloChunks = kHaloPix * 8;             // 16-byte chunks per halo
+constexpr int kPf = (kHaloChunks + 255) / 256;        // chunks each thread prefetches
+constexpr int kDppRowShl1 = 0x101;                    // DPP control: lane n takes lane n+1 of its row
+
+__device__ __forceinline__ int swz(int pix, int q) { return pix * 64 + ((q ^ (pix & 7)) << 3); }
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// dst[n] = src[n + 1] inside each 16-lane row; the last lane of a row takes `last`.
+__device__ __forceinline__ bf16x8 shift_in_row(bf16x8 src, bf16x8 last) {
+    const u32x4 s = __builtin_bit_cast(u32x4, src), t = __builtin_bit_cast(u32x4, last);
+    u32x4 d;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) d[v] = (uint32_t)__builtin_amdgcn_update_dpp((int)t[v], (int)s[v], kDppRowShl1, 0xf, 0xf, false);
+    return __builtin_bit_cast(bf16x8, d);
+}
+
+// a > 0 for a BF16 value: sign clear and not zero.
+__device__ __forceinline__ uint32_t keep_positive(uint32_t val, uint32_t mm) {
+    uint32_t keep = 0;
+    if ((mm & 0x8000u) == 0 && (mm & 0x7fffu) != 0) keep |= 0xffffu;
+    if ((mm & 0x80000000u) == 0 && (mm & 0x7fff0000u) != 0) keep |= 0xffff0000u;
+    return val & keep;
+}
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_conv_bf16(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
+__global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
                                                    const float* __restrict__ bias, const uint16_t* __restrict__ mask,
                                                    uint16_t* __restrict__ out, int h, int w, const DevState* st) {
     if (finished(st)) return;
-    __shared__ __attribute__((aligned(16))) uint16_t halo[kHalo * kHalo * kHSb];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ __attribute__((aligned(16))) uint16_t sw[kTaps * kWidth * kWidth];
+    __shared__ __attribute__((aligned(16))) uint16_t hb[2][kHaloPix * kWidth];
+    const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
+    const int lane = tid & 63, wq = gt >> 6;
     const int g = lane >> 4, n = lane & 15;
-    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
-    for (int idx = threadIdx.x; idx < kHalo * kHalo * 8; idx += 256) {
-        const int pix = idx >> 3, q = idx & 7;
-        const int hy = pix / kHalo, hx = pix - hy * kHalo;
-        const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (gy >= 0 && gy < h && gx >= 0 && gx < w)
-            v = *reinterpret_cast<const uint4*>(in + ((long long)gy * w + gx) * kWidth + 8 * q);
-        *reinterpret_cast<uint4*>(halo + pix * kHSb + 8 * q) = v;
-    }
-    __syncthreads();
+    uint16_t* halo = hb[grp];
+    for (int i = tid; i < kTaps * kWidth * kWidth / 8; i += 512)
+        reinterpret_cast<uint4*>(sw)[i] = reinterpret_cast<const uint4*>(wpk)[i];
+    const int tiles_x = (w + kTile - 1) / kTile, tiles_y = (h + kTile - 1) / kTile;
+    const int ntiles = tiles_x * tiles_y;
+    const int stride = 2 * gridDim.x;
+    const int iters = (ntiles - 2 * (int)blockIdx.x + stride - 1) / stride;
 
-    floatx4 acc[4][4];
+    uint4 pf[kPf];
+    auto fetch = [&](int tile) {
+        const bool have = tile < ntiles;
+        const int x0 = have ? (tile % tiles_x) * kTile : 0, y0 = have ? (tile / tiles_x) * kTile : 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    // iteration it = 2t + kc covers tap t, channels 32kc..32kc+31; B fragment
-    // (8 channels 8(4kc+g).. of output column 16j+n) at wpk8[(4 it + g) * 64 + 16 j + n].
-    const bf16x8* wp = reinterpret_cast<const bf16x8*>(wpk) + g * 64 + n;
-    bf16x8 bn[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) bn[j] = wp[16 * j];
-    for (int it = 0; it < 2 * kTaps; ++it) {
-        const int t = it >> 1, kc = it & 1;
-        bf16x8 b[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = bn[j];
-        if (it + 1 < 2 * kTaps) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bn[j] = wp[(4 * (it + 1)) * 64 + 16 * j];
+        for (int u = 0; u < kPf; ++u) {
+            const int idx = gt + 256 * u;
+            const int pix = idx >> 3, q = idx & 7;
+            const int hy = pix / kHalo, hx = pix - hy * kHalo;
+            const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+            pf[u] = make_uint4(0u, 0u, 0u, 0u);
+            if (have && idx < kHaloChunks && gy >= 0 && gy < h && gx >= 0 && gx < w)
+                pf[u] = *reinterpret_cast<const uint4*>(in + ((long long)gy * w + gx) * kWidth + 8 * q);
         }
-        const int dy = t / 3, dx = t - 3 * (t / 3);
-        const uint16_t* hrow = halo + ((4 * wv + dy) * kHalo + n + dx) * kHSb + 32 * kc + 8 * g;
-        bf16x8 a[4];
+    };
+    if (iters > 0) fetch(2 * blockIdx.x + grp);
+
+    for (int k = 0; k < iters; ++k) {
+        const int tile = 2 * blockIdx.x + grp + k * stride;
+        const bool have = tile < ntiles;
+        const int x0 = have ? (tile % tiles_x) * kTile : 0, y0 = have ? (tile / tiles_x) * kTile : 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8*>(hrow + i * kHalo * kHSb);
+        for (int u = 0; u < kPf; ++u) {
+            const int idx = gt + 256 * u;
+            if (idx < kHaloChunks) *reinterpret_cast<uint4*>(halo + swz(idx >> 3, idx & 7)) = pf[u];
+        }
+        __syncthreads();
+        if (k + 1 < iters) fetch(tile + stride);   // in flight during the MFMA loop
+
+        floatx4 acc[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();   // halo no longer read: reuse it for the output tile
-
-    // D row (pixel x) = 4g + r, column (channel) = 16j + n.
-    uint16_t* ot = halo;   // [256 tile pixels][kHSb]
+            for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int dy = 0; dy < 3; ++dy) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+            for (int kc = 0; kc < 2; ++kc) {
+                // activation fragments of tile rows 4wq+i at dx = 0 (lane n: pixel n),
+                // and the pixels 16, 17 that enter at the row end for dx = 1, 2
+                bf16x8 a0[4], e1[4], e2[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int co = 16 * j + n;
-            const float bv = (MODE == 0) ? bias[co] : 0.f;
+                for (int i = 0; i < 4; ++i) {
+                    const int prow = (4 * wq + i + dy) * kHalo;
+                    a0[i] = *reinterpret_cast<const bf16x8*>(halo + swz(prow + n, 4 * kc + g));
+                    e1[i] = *reinterpret_cast<const bf16x8*>(halo + swz(prow + 16, 4 * kc + g));
+                    e2[i] = *reinterpret_cast<const bf16x8*>(halo + swz(prow + 17, 4 * kc + g));
+                }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float v = acc[i][j][r];
-                if (MODE == 0) v = fmaxf(v + bv, 0.f);
-                ot[((4 * wv + i) * kTile + 4 * g + r) * kHSb + co] = bf16_rne(v);
+                for (int dx = 0; dx < 3; ++dx) {
+                    if (dx > 0) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) a0[i] = shift_in_row(a0[i], dx == 1 ? e1[i] : e2[i]);
+                    }
+                    // B fragment of tap t, channels 8(4kc+g).. of output column 16j+n
+                    const int it = 2 * (3 * dy + dx) + kc;
+                    bf16x8 wb[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        wb[j] = *reinterpret_cast<const bf16x8*>(sw + ((4 * it + g) * 64 + 16 * j + n) * 8);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[j], a0[i], acc[i][j], 0, 0, 0);
+                }
             }
         }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < kTile * kTile * 8; idx += 256) {
-        const int p = idx >> 3, q = idx & 7;
-        const int gy = y0 + (p >> 4), gx = x0 + (p & 15);
-        if (gy >= h || gx >= w) continue;
-        const long long o = ((long long)gy * w + gx) * kWidth + 8 * q;
-        uint4 v = *reinterpret_cast<const uint4*>(ot + p * kHSb + 8 * q);
-        if (MODE == 1) {
-            const uint4 mk = *reinterpret_cast<const uint4*>(mask + o);
-            // keep a 16-bit lane where the mask value is > 0 (sign clear, not zero)
-            auto sel = [](uint32_t val, uint32_t m) {
-                uint32_t keep = 0;
-                if ((m & 0x8000u) == 0 && (m & 0x7fffu) != 0) keep |= 0xffffu;
-                if ((m & 0x80000000u) == 0 && (m & 0x7fff0000u) != 0) keep |= 0xffff0000u;
-                return val & keep;
-            };
-            v.x = sel(v.x, mk.x);
-            v.y = sel(v.y, mk.y);
-            v.z = sel(v.z, mk.z);
-            v.w = sel(v.w, mk.w);
+
+        // D row = channel 16j + 4g + r, column = pixel x = n of tile row 4wq + i.
+        if (have) {
+            float bv[4][4];
+            if (MODE == 0) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) bv[j][r] = bias[16 * j + 4 * g + r];
+            }
+            const int gx = x0 + n;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int gy = y0 + 4 * wq + i;
+                if (gy >= h || gx >= w) continue;
+                const long long base = ((long long)gy * w + gx) * kWidth + 4 * g;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float v[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] = (MODE == 0) ? fmaxf(acc[i][j][r] + bv[j][r], 0.f) : acc[i][j][r];
+                    uint2 o = make_uint2((uint32_t)bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[1]) << 16),
+                                         (uint32_t)bf16_rne(v[2]) | ((uint32_t)bf16_rne(v[3]) << 16));
+                    if (MODE == 1) {
+                        const uint2 mk = *reinterpret_cast<const uint2*>(mask + base + 16 * j);
+                        o.x = keep_positive(o.x, mk.x);
+                        o.y = keep_positive(o.y, mk.y);
+                    }
+                    *reinterpret_cast<uint2*>(out + base + 16 * j) = o;
+                }
+            }
         }
-        *reinterpret_cast<uint4*>(out + o) = v;
+        __syncthreads();   // the next tile's halo overwrites this buffer
     }
+}
+
+// Grid of the BF16 convolution: one block (two tiles in flight) per CU at most.
+int conv_bf16_blocks(int h, int w) {
+    const int tiles = ((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile);
+    const int b = (tiles + 1) / 2;
+    return b < 256 ? b : 256;
 }
 
 // BF16 weight gradient of a 64->64 layer.  GEMM view as in the FP32 kernel
@@ -441,7 +511,7 @@ hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, v
                            const DevState* st, hipStream_t s) {
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
     if (bf16) {
-        hipLaunchKernelGGL(k_conv_bf16<0>, grid, dim3(256), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
+        hipLaunchKernelGGL(k_conv_bf16<0>, dim3(conv_bf16_blocks(h, w)), dim3(512), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
                            (const uint16_t*)nullptr, (uint16_t*)out, h, w, st);
         return hipGetLastError();
     }
@@ -454,7 +524,7 @@ hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, v
                            const DevState* st, hipStream_t s) {
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
     if (bf16) {
-        hipLaunchKernelGGL(k_conv_bf16<1>, grid, dim3(256), 0, s, (const uint16_t*)dlt, (const uint16_t*)wpk,
+        hipLaunchKernelGGL(k_conv_bf16<1>, dim3(conv_bf16_blocks(h, w)), dim3(512), 0, s, (const uint16_t*)dlt, (const uint16_t*)wpk,
                            (const float*)nullptr, (const uint16_t*)mask, (uint16_t*)out, h, w, st);
         return hipGetLastError();
     }

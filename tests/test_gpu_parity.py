@@ -5,7 +5,9 @@ FP32 ulp of the oracle's FP64 value; a teacher-forced training step (GPU
 loaded with the oracle's state) within norm-wise relative error 1e-5 per
 parameter tensor (FP32); final PSNR within 0.1 dB.
 """
+import json
 import math
+import os
 import sys
 
 import numpy as np
@@ -338,3 +340,51 @@ def test_free_running_steps_track_oracle():
     assert t == 8
     assert rel(th - th0, st.theta - th0) < 1e-4
     assert rel(v, st.v) < 1e-4
+
+
+SEED_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_psnr_64_sigma25_seeds.json")
+
+
+@pytest.mark.skipif(not os.path.exists(SEED_GOLDEN), reason="oracle seed golden not generated")
+@pytest.mark.parametrize("prec", [n2f.FP32, n2f.BF16])
+def test_mean_psnr_matches_oracle_over_seeds(prec):
+    """Whole loop with early stopping (64x64, sigma 25/255): the mean final
+    PSNR over the same initial-weight seeds as the oracle's stored runs is
+    within 0.1 dB of the oracle's mean, up to the sampling error of the two
+    means (single runs differ by a few tenths of a dB with rounding noise)."""
+    gold = json.load(open(SEED_GOLDEN))
+    clean, noisy = synth.small_64(0)
+    x = dev(noisy)
+    ps, eps = [], []
+    for run in gold["runs"]:
+        r = n2f.Run(x, n2f.default_config(precision=prec, init_seed=run["seed"]))
+        done, status = r.run_epochs(0, 2000)
+        assert done and status == n2f.OK
+        ps.append(synth.psnr(r.result().cpu().numpy(), clean))
+        eps.append(r.progress(0)[0])
+    ps = np.array(ps)
+    po = np.array([run["psnr"] for run in gold["runs"]])
+    n = len(ps)
+    se = np.sqrt(ps.var(ddof=1) / n + po.var(ddof=1) / n)
+    say("gpu mean %.3f std %.3f | oracle mean %.3f std %.3f | se %.3f | epochs %.1f vs %.1f" %
+        (ps.mean(), ps.std(ddof=1), po.mean(), po.std(ddof=1), se, np.mean(eps),
+         np.mean([run["epochs"] for run in gold["runs"]])))
+    assert abs(ps.mean() - po.mean()) <= 0.1 + 2.5 * se
+    assert ps.min() > gold["noisy_psnr"] + 5.0
+
+
+GOLD_256 = os.path.join(os.path.dirname(__file__), "golden", "oracle_psnr_256_sigma25.json")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLD_256), reason="oracle 256 golden not generated")
+def test_single_run_256_within_run_to_run_spread():
+    """One full early-stopping run at 256x256 (sigma 25/255, seed 0) against
+    the oracle's run on the same inputs.  Single runs scatter with a measured
+    standard deviation of about 0.4 dB, so the bound is 2.5 of those."""
+    gold = json.load(open(GOLD_256))
+    clean, noisy = synth.single_512(25, 2, size=256)
+    r = n2f.Run(dev(noisy), n2f.default_config())
+    r.run_epochs(0, 2000)
+    p = synth.psnr(r.result().cpu().numpy(), clean)
+    say("256 gpu", p, r.progress(0)[:2], "oracle", gold["psnr"], gold["epochs"], gold["best_epoch"])
+    assert abs(p - gold["psnr"]) < 1.0
