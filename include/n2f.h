@@ -268,17 +268,23 @@ n2f_status n2f_server_memory(n2f_server* srv, size_t* used, size_t* largest_free
 n2f_status n2f_server_destroy(n2f_server* srv);
 
 /* ---- kernel timing ----
- * While profiling is on, one launch in `every` of each instrumented kernel
- * class is bracketed by HIP events on the stream it runs on.  Classes:
- * N2F_K_CONV_FWD (64->64 forward, training and validation), N2F_K_CONV_BWD
- * (64->64 data gradient), N2F_K_WGRAD (64->64 weight gradient).
+ * While profiling is on, the launches of one epoch in `every` are issued
+ * directly (not from the epoch's graph) and each run of consecutive launches
+ * of an instrumented class is bracketed by two HIP events on the stream it
+ * runs on.  Classes:
+ *   N2F_K_CONV_FWD  64->64 forward convolution; a run is the 7 launches of
+ *                   one forward pass (training or validation);
+ *   N2F_K_BACKWARD  one 64->64 layer's backward, i.e. its weight-gradient
+ *                   launch plus its data-gradient launch; a run is the 7
+ *                   layers of one backward pass;
+ *   N2F_K_ADAM      the fused gradient reduction + Adam launch.
  * n2f_profile_begin clears earlier records; n2f_profile_read synchronises
- * the recorded events and returns, for one class, the summed kernel time,
- * the number of recorded launches and the pixels those launches processed.
- * Process-wide; not thread-safe. */
+ * the recorded events and returns, for one class, the summed time of its
+ * runs, the number of launches (pairs for N2F_K_BACKWARD) in them and the
+ * pixels those launches processed.  Process-wide; not thread-safe. */
 #define N2F_K_CONV_FWD 0
-#define N2F_K_CONV_BWD 1
-#define N2F_K_WGRAD    2
+#define N2F_K_BACKWARD 1
+#define N2F_K_ADAM     2
 n2f_status n2f_profile_begin(int every);
 n2f_status n2f_profile_read(int kernel_class, double* total_ms, long long* launches, long long* pixels);
 n2f_status n2f_profile_end(void);

@@ -59,7 +59,7 @@ std::vector<CanonLayer> canon_layers(int C) {
     return v;
 }
 
-ParamTable make_table(int C, int nsplit, int hsplit) {
+ParamTable make_table(int C, int n1split, int nsplit, int hsplit) {
     ParamTable pt{};
     int off = 0;
     long long poff = 0;
@@ -68,7 +68,7 @@ ParamTable make_table(int C, int nsplit, int hsplit) {
         pt.cin[l] = cin;
         pt.off[l] = off;
         pt.n[l] = (l < kLayers) ? kTaps * cin * kWidth + kWidth : kHeadN;
-        pt.split[l] = (l < kLayers) ? nsplit : hsplit;
+        pt.split[l] = (l == 0) ? n1split : (l < kLayers) ? nsplit : hsplit;
         pt.poff[l] = poff;
         off += pt.n[l];
         poff += (long long)pt.split[l] * pt.n[l];
@@ -124,7 +124,7 @@ void internal_to_canon(const float* src, float* dst, int C, const ParamTable& pt
 struct Plan {
     int H, W, C, Hc, Wc, P, bf;
     int hu, wu, hl, wl;       // up and left training image shapes
-    int nsplit, hsplit, vblk, mmblk, max_trace;
+    int n1split, nsplit, hsplit, vblk, mmblk, max_trace;
     ParamTable pt;
     size_t o_misc, o_xs, o_ds[4], o_net[3], net_bytes;
     size_t n_state, n_theta, n_pack32, n_pack16, n_trace, n_img;
@@ -169,13 +169,14 @@ n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
     q.hl = q.Hc / 2;
     q.wl = q.Wc;
     q.P = q.Hc * q.Wc / 2;
-    q.nsplit = std::max(wgrad_splits(q.hu, q.wu), wgrad_splits(q.hl, q.wl));
+    q.nsplit = std::max(wgrad_splits(q.hu, q.wu, q.bf), wgrad_splits(q.hl, q.wl, q.bf));
+    q.n1split = (int)std::max(1LL, std::min((long long)kMaxSplit, ((long long)q.P + 511) / 512));
     q.hsplit = head_splits(q.P);
     const long long HW = (long long)H * W;
     q.vblk = (int)std::max(1LL, std::min((HW + 255) / 256, 1024LL));
     q.mmblk = (int)std::max(1LL, std::min((HW * C + 4095) / 4096, 1024LL));
     q.max_trace = std::max(cfg->max_epochs, cfg->fixed_epochs) + 1;
-    q.pt = make_table(C, q.nsplit, q.hsplit);
+    q.pt = make_table(C, q.n1split, q.nsplit, q.hsplit);
 
     size_t o = 0;
     q.o_misc = o;
@@ -239,16 +240,18 @@ n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
     return N2F_OK;
 }
 
-// Kernel-class timing with HIP events on the launch stream (see n2f.h).
+// Kernel-class timing with HIP events on the launch stream (see n2f.h).  A
+// record brackets a run of consecutive launches of one class, so the two
+// event markers cost once per run rather than once per kernel.
 struct ProfRec {
     int cls;
-    long long npix;
+    long long launches, npix;
     hipEvent_t a, b;
 };
 struct Profiler {
     bool on = false;
     bool capturing = false;
-    int every = 1;             // time every launch of one epoch in `every`
+    int every = 1;             // time the launches of one epoch in `every`
     long long epochs = 0;
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
@@ -264,8 +267,9 @@ hipEvent_t prof_event() {
     return e;
 }
 
+// f() enqueues `launches` kernels of class cls, each over npix pixels.
 template <class F>
-hipError_t timed(int cls, long long npix, hipStream_t s, F&& f) {
+hipError_t timed(int cls, int launches, long long npix, hipStream_t s, F&& f) {
     if (!g_prof.on || g_prof.capturing) return f();
     hipEvent_t a = prof_event(), b = prof_event();
     if (!a || !b) return hipErrorOutOfMemory;
@@ -274,7 +278,7 @@ hipError_t timed(int cls, long long npix, hipStream_t s, F&& f) {
     e = f();
     if (e != hipSuccess) return e;
     e = hipEventRecord(b, s);
-    g_prof.recs.push_back({cls, npix, a, b});
+    g_prof.recs.push_back({cls, launches, (long long)launches * npix, a, b});
     return e;
 }
 
@@ -367,30 +371,37 @@ n2f_status enqueue_train_step(n2f_run* r, int k, int pair) {
     };
     // forward with stash: act layer i holds a_{i+1}
     N2F_HIP(launch_conv1(in, pl.C, Wl(0), Bl(0), act_layer(r, 0, npix), bf, h, w, N.st, s));
-    for (int l = 1; l < kLayers; ++l)
-        N2F_HIP(timed(N2F_K_CONV_FWD, (long long)npix, s, [&] {
-            return launch_conv_fwd(act_layer(r, l - 1, npix), fwdpk(l), Bl(l), act_layer(r, l, npix), bf, h, w, N.st, s);
-        }));
+    N2F_HIP(timed(N2F_K_CONV_FWD, kLayers - 1, (long long)npix, s, [&]() -> hipError_t {
+        for (int l = 1; l < kLayers; ++l) {
+            hipError_t e = launch_conv_fwd(act_layer(r, l - 1, npix), fwdpk(l), Bl(l), act_layer(r, l, npix), bf, h, w,
+                                           N.st, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }));
     // head, BCE gradient
     const float* w9 = N.theta + pt.off[kLayers];
     N2F_HIP(launch_head_train(act_layer(r, kLayers - 1, npix), tgt, pl.C, k, w9, w9 + kWidth, r->dlt[0],
                               r->part + pt.poff[kLayers], r->lpart, pt.split[kLayers], bf, (long long)npix, N.st, s));
     // backward: layer l (0-based 7..1) takes delta of its output
     int cur = 0;
-    for (int l = kLayers - 1; l >= 1; --l) {
-        N2F_HIP(timed(N2F_K_WGRAD, (long long)npix, s, [&] {
-            return launch_wgrad(act_layer(r, l - 1, npix), r->dlt[cur], r->part + pt.poff[l], pt.split[l], bf, h, w,
-                                N.st, s);
-        }));
-        N2F_HIP(timed(N2F_K_CONV_BWD, (long long)npix, s, [&] {
-            return launch_conv_bwd(r->dlt[cur], bwdpk(l), act_layer(r, l - 1, npix), r->dlt[1 - cur], bf, h, w, N.st, s);
-        }));
-        cur = 1 - cur;
-    }
+    N2F_HIP(timed(N2F_K_BACKWARD, kLayers - 1, (long long)npix, s, [&]() -> hipError_t {
+        for (int l = kLayers - 1; l >= 1; --l) {
+            hipError_t e = launch_wgrad(act_layer(r, l - 1, npix), r->dlt[cur], r->part + pt.poff[l], pt.split[l], bf,
+                                        h, w, N.st, s);
+            if (e != hipSuccess) return e;
+            e = launch_conv_bwd(r->dlt[cur], bwdpk(l), act_layer(r, l - 1, npix), r->dlt[1 - cur], bf, h, w, N.st, s);
+            if (e != hipSuccess) return e;
+            cur = 1 - cur;
+        }
+        return hipSuccess;
+    }));
     N2F_HIP(launch_wgrad1(in, pl.C, r->dlt[cur], r->part + pt.poff[0], pt.split[0], bf, h, w, N.st, s));
-    N2F_HIP(launch_adam(N.theta, N.m, N.v, N.g, r->part, nullptr, pt, r->cfg.lr, r->cfg.beta1,
-                        r->cfg.beta2, r->cfg.eps, N.fwd, N.bwd, N.fwd16, N.bwd16, r->lpart,
-                        pt.split[kLayers], (long long)npix, N.st, s));
+    N2F_HIP(timed(N2F_K_ADAM, 1, (long long)npix, s, [&] {
+        return launch_adam(N.theta, N.m, N.v, N.g, r->part, nullptr, pt, r->cfg.lr, r->cfg.beta1, r->cfg.beta2,
+                           r->cfg.eps, N.fwd, N.bwd, N.fwd16, N.bwd16, r->lpart, pt.split[kLayers], (long long)npix,
+                           N.st, s);
+    }));
     return N2F_OK;
 }
 
@@ -404,11 +415,15 @@ n2f_status enqueue_validate(n2f_run* r, int k) {
     auto buf = [&](int i) { return act_layer(r, i & 1, npix); };
     auto Bl = [&](int l) { return N.theta + pt.off[l] + kTaps * pt.cin[l] * kWidth; };
     N2F_HIP(launch_conv1(r->xs, pl.C, N.theta + pt.off[0], Bl(0), buf(0), bf, pl.H, pl.W, N.st, s));
-    for (int l = 1; l < kLayers; ++l) {
-        const void* pk = bf ? (const void*)(N.fwd16 + (size_t)(l - 1) * kPackN) : (const void*)(N.fwd + (size_t)(l - 1) * kPackN);
-        N2F_HIP(timed(N2F_K_CONV_FWD, (long long)npix, s,
-                      [&] { return launch_conv_fwd(buf(l - 1), pk, Bl(l), buf(l), bf, pl.H, pl.W, N.st, s); }));
-    }
+    N2F_HIP(timed(N2F_K_CONV_FWD, kLayers - 1, (long long)npix, s, [&]() -> hipError_t {
+        for (int l = 1; l < kLayers; ++l) {
+            const void* pk = bf ? (const void*)(N.fwd16 + (size_t)(l - 1) * kPackN)
+                                : (const void*)(N.fwd + (size_t)(l - 1) * kPackN);
+            hipError_t e = launch_conv_fwd(buf(l - 1), pk, Bl(l), buf(l), bf, pl.H, pl.W, N.st, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }));
     const float* w9 = N.theta + pt.off[kLayers];
     N2F_HIP(launch_head_val(buf(kLayers - 1), r->xs, pl.C, k, w9, w9 + kWidth, N.y, r->vpart, pl.vblk, bf,
                             (long long)npix, N.st, N.trace, s));
@@ -495,7 +510,7 @@ n2f_status n2f_param_count(int C, const n2f_config* cfg, size_t* count) {
     n2f_status s = check_cfg(cfg);
     if (s != N2F_OK) return s;
     if (C < 1 || C > 3 || !count) return fail(N2F_EINVAL, "need 1 <= C <= 3 and a non-NULL count");
-    *count = (size_t)make_table(C, 1, 1).total;
+    *count = (size_t)make_table(C, 1, 1, 1).total;
     return N2F_OK;
 }
 
@@ -941,7 +956,7 @@ n2f_status n2f_profile_begin(int every) {
 }
 
 n2f_status n2f_profile_read(int cls, double* total_ms, long long* launches, long long* pixels) {
-    if (cls < N2F_K_CONV_FWD || cls > N2F_K_WGRAD) return fail(N2F_EINVAL, "unknown kernel class");
+    if (cls < N2F_K_CONV_FWD || cls > N2F_K_ADAM) return fail(N2F_EINVAL, "unknown kernel class");
     double ms = 0.0;
     long long n = 0, px = 0;
     for (const ProfRec& rec : g_prof.recs) {
@@ -950,7 +965,7 @@ n2f_status n2f_profile_read(int cls, double* total_ms, long long* launches, long
         float t = 0.f;
         N2F_HIP(hipEventElapsedTime(&t, rec.a, rec.b));
         ms += t;
-        n += 1;
+        n += rec.launches;
         px += rec.npix;
     }
     if (total_ms) *total_ms = ms;

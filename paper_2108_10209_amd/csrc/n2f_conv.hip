@@ -216,7 +216,7 @@ __device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float(((u
 // 8-byte store.  The activation fragment of a tile row is read once per
 // (dy, channel half): the dx = 1 and dx = 2 fragments are the same data
 // moved one lane down each 16-lane DPP row, with the one pixel that enters
-// at the row end taken from a broadcast LDS read.
+// at the row end read from LDS by the row's last lane alone.
 constexpr int kHaloPix = kHalo * kHalo;               // 324 staged pixels
 constexpr int kHaloChunks = kHaloPix * 8;             // 16-byte chunks per halo
 constexpr int kPf = (kHaloChunks + 255) / 256;        // chunks each thread prefetches
@@ -300,13 +300,18 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
             for (int kc = 0; kc < 2; ++kc) {
                 // activation fragments of tile rows 4wq+i at dx = 0 (lane n: pixel n),
                 // and the pixels 16, 17 that enter at the row end for dx = 1, 2
+                // (only the last lane of each row reads the entering pixels)
                 bf16x8 a0[4], e1[4], e2[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int prow = (4 * wq + i + dy) * kHalo;
                     a0[i] = *reinterpret_cast<const bf16x8*>(halo + swz(prow + n, 4 * kc + g));
-                    e1[i] = *reinterpret_cast<const bf16x8*>(halo + swz(prow + 16, 4 * kc + g));
-                    e2[i] = *reinterpret_cast<const bf16x8*>(halo + swz(prow + 17, 4 * kc + g));
+                    e1[i] = bf16x8{};
+                    e2[i] = bf16x8{};
+                    if (n == 15) {
+                        e1[i] = *reinterpret_cast<const bf16x8*>(halo + swz(prow + 16, 4 * kc + g));
+                        e2[i] = *reinterpret_cast<const bf16x8*>(halo + swz(prow + 17, 4 * kc + g));
+                    }
                 }
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) {
@@ -372,20 +377,34 @@ int conv_bf16_blocks(int h, int w) {
 }
 
 // BF16 weight gradient of a 64->64 layer.  GEMM view as in the FP32 kernel
-// (M = (t, ci) = 576, N = co = 64, K = pixels); a K group is 8 consecutive
-// tile pixels.  Both operands stay pixel-major in LDS (pixel stride 68 bf16,
-// 8-byte aligned rows) and are read with the gfx950 16-bit transpose load:
-// within a group of 16 lanes, row-lane r addresses pixel p0 + r/4 and
-// channels c0 + 4(r%4).., and lane L then holds channel c0 + L of pixels
-// p0..p0+3; two such loads give the 8 K values of an MFMA fragment.  A tap
-// shift is only a different row address.
-// The block has 8 waves in two groups of 4; each group stages and reduces
-// its own tiles in its own LDS buffers, and at the end the two groups'
-// sums are added (group 0 + group 1), so a block still writes one partial.
-constexpr int kPS = 68;                          // bf16 per staged pixel
-constexpr int kHaloB = kHalo * kHalo * kPS;      // bf16 per staged halo
-constexpr int kTileB = kTile * kTile * kPS;      // bf16 per staged delta tile
-constexpr int kGroupB = kHaloB + kTileB;         // bf16 per group buffer
+// (M = (t, ci) = 576, N = co = 64, K = pixels).  The grid is 4 x nsplit
+// blocks: block (s, q) owns the 144 rows of input-channel quarter q (9 taps
+// x 16 channels) over the tiles s, s + nsplit, s + 2 nsplit, ...; so the
+// partial of split s is written by four blocks, each its own rows, and a
+// layer has only nsplit partials to reduce.  The four quarter blocks of a
+// split are placed on one XCD (block ids 8 apart), where they share the
+// delta tiles through that XCD's L2.
+//
+// Per tile, each of the 8 waves takes 32 pixels (two tile rows) as one K
+// step of all 36 16x16 output tiles (9 taps x 4 blocks of co).  Both
+// operands stay pixel-major in LDS and are read with the gfx950 16-bit
+// transpose load: within a group of 16 lanes, row-lane r addresses pixel
+// p0 + r/4 and channels c0 + 4(r%4).., and lane L then holds channel c0 + L
+// of pixels p0..p0+3; two such loads give the 8 K values of an MFMA
+// fragment.  A tap shift is only a different row address.  The next tile is
+// loaded into registers while the current one is multiplied (two LDS
+// buffers, one barrier per tile).  The bias gradient (quarter-0 blocks) is
+// summed from the staged delta with 16-byte reads.  At the end the waves'
+// sums are added in wave order through LDS, three taps at a time.
+constexpr int kWgPSA = 16;                                // bf16 per staged halo pixel (one quarter)
+constexpr int kWgPSB = 68;                                // bf16 per staged delta pixel
+constexpr int kWgHaloE = kHalo * kHalo * kWgPSA;
+constexpr int kWgBufE = kWgHaloE + kTile * kTile * kWgPSB;
+constexpr int kWgHaloChunks = kHalo * kHalo * 2;          // 16-byte chunks of a halo quarter
+constexpr int kWgChunks = kWgHaloChunks + kTile * kTile * 8;
+constexpr int kWgPf = (kWgChunks + 511) / 512;            // chunks each thread carries
+constexpr int kWgRedS = 4 * 64 + 16;                      // floats per (wave, tile) in the reduction
+constexpr int kWgLdsBytes = (2 * kWgBufE * 2 > 8 * 12 * kWgRedS * 4) ? 2 * kWgBufE * 2 : 8 * 12 * kWgRedS * 4;
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
@@ -398,110 +417,153 @@ __device__ __forceinline__ bf16x8 tr16_frag(const uint16_t* p0, const uint16_t* 
     return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
+// Global -> registers: the halo quarter (channels 16q..16q+15 of the 18x18
+// pixels around the tile) and the 16x16x64 delta tile, zero outside.
+__device__ __forceinline__ void wg_load(uint4 (&pf)[kWgPf], const uint16_t* __restrict__ src,
+                                        const uint16_t* __restrict__ dlt, int tile, int tiles_x, int q, int h,
+                                        int w) {
+    const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
+#pragma unroll
+    for (int k = 0; k < kWgPf; ++k) {
+        const int c = threadIdx.x + 512 * k;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (c < kWgHaloChunks) {
+            const int hp = c >> 1, hh = c & 1;
+            const int hy = hp / kHalo, hx = hp - hy * kHalo;
+            const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+            if (gy >= 0 && gy < h && gx >= 0 && gx < w)
+                v = *reinterpret_cast<const uint4*>(src + ((long long)gy * w + gx) * kWidth + 16 * q + 8 * hh);
+        } else if (c < kWgChunks) {
+            const int c2 = c - kWgHaloChunks;
+            const int p = c2 >> 3, qd = c2 & 7;
+            const int gy = y0 + (p >> 4), gx = x0 + (p & 15);
+            if (gy < h && gx < w) v = *reinterpret_cast<const uint4*>(dlt + ((long long)gy * w + gx) * kWidth + 8 * qd);
+        }
+        pf[k] = v;
+    }
+}
+
+__device__ __forceinline__ void wg_store(const uint4 (&pf)[kWgPf], uint16_t* buf) {
+#pragma unroll
+    for (int k = 0; k < kWgPf; ++k) {
+        const int c = threadIdx.x + 512 * k;
+        if (c < kWgHaloChunks) {
+            *reinterpret_cast<uint4*>(buf + (c >> 1) * kWgPSA + 8 * (c & 1)) = pf[k];
+        } else if (c < kWgChunks) {
+            const int c2 = c - kWgHaloChunks;
+            uint2* d = reinterpret_cast<uint2*>(buf + kWgHaloE + (c2 >> 3) * kWgPSB + 8 * (c2 & 7));
+            d[0] = make_uint2(pf[k].x, pf[k].y);
+            d[1] = make_uint2(pf[k].z, pf[k].w);
+        }
+    }
+}
+
 __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__ src, const uint16_t* __restrict__ dlt,
                                                     float* __restrict__ part, int h, int w, const DevState* st) {
     if (finished(st)) return;
-    __shared__ __attribute__((aligned(16))) uint16_t buf[2 * kGroupB];
-    __shared__ float dbs[2][4][kWidth];
-    const int tid = threadIdx.x & 255, grp = threadIdx.x >> 8;
-    const int lane = threadIdx.x & 63, wq = tid >> 6;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[kWgLdsBytes];
+    __shared__ float dbs[64][kWidth];
+    uint16_t* bufs = reinterpret_cast<uint16_t*>(lds);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int g = lane >> 4, r = lane & 15;
-    uint16_t* halo = buf + grp * kGroupB;
-    uint16_t* dt = halo + kHaloB;
+    const int nsplit = gridDim.x / 4;
+    const int b = blockIdx.x;
+    int sp, q;
+    if ((nsplit & 7) == 0) {
+        q = (b >> 3) & 3;
+        sp = (b & 7) + 8 * (b >> 5);
+    } else {
+        q = b / nsplit;
+        sp = b - q * nsplit;
+    }
     const int tiles_x = (w + kTile - 1) / kTile, tiles_y = (h + kTile - 1) / kTile;
     const int ntiles = tiles_x * tiles_y;
-    const int stride = 2 * gridDim.x;
-    const int iters = (ntiles - 2 * (int)blockIdx.x + stride - 1) / stride;   // same for both groups' loop
+    const int nmine = sp < ntiles ? (ntiles - sp + nsplit - 1) / nsplit : 0;
 
     floatx4 acc[9][4];
 #pragma unroll
     for (int i = 0; i < 9; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float dbacc = 0.f;
+    // bias gradient: thread = (8-channel chunk tid & 7, pixels 4 (tid >> 3) .. +3)
+    float db[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
-    for (int it = 0; it < iters; ++it) {
-        const int tile = 2 * blockIdx.x + grp + it * stride;
-        const bool have = tile < ntiles;
-        const int x0 = have ? (tile % tiles_x) * kTile : 0, y0 = have ? (tile / tiles_x) * kTile : 0;
-        for (int idx = tid; idx < kHalo * kHalo * 8; idx += 256) {
-            const int pix = idx >> 3, q = idx & 7;
-            const int hy = pix / kHalo, hx = pix - hy * kHalo;
-            const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (have && gy >= 0 && gy < h && gx >= 0 && gx < w)
-                v = *reinterpret_cast<const uint4*>(src + ((long long)gy * w + gx) * kWidth + 8 * q);
-            uint2* d = reinterpret_cast<uint2*>(halo + pix * kPS + 8 * q);
-            d[0] = make_uint2(v.x, v.y);
-            d[1] = make_uint2(v.z, v.w);
-        }
-        for (int idx = tid; idx < kTile * kTile * 8; idx += 256) {
-            const int p = idx >> 3, q = idx & 7;
-            const int gy = y0 + (p >> 4), gx = x0 + (p & 15);
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (have && gy < h && gx < w) v = *reinterpret_cast<const uint4*>(dlt + ((long long)gy * w + gx) * kWidth + 8 * q);
-            uint2* d = reinterpret_cast<uint2*>(dt + p * kPS + 8 * q);
-            d[0] = make_uint2(v.x, v.y);
-            d[1] = make_uint2(v.z, v.w);
-        }
-        __syncthreads();
-        {
-            const int co = tid & 63, pg = tid >> 6;
-            float sacc = 0.f;
-            for (int p = pg * 64; p < pg * 64 + 64; ++p) sacc += bf16_f(dt[p * kPS + co]);
-            dbs[grp][pg][co] = sacc;
-        }
-        const int rp = r >> 2, rc = 4 * (r & 3);
-        for (int kk = 0; kk < 8; ++kk) {
-            // row-lane pixels of the two halves: kappa = 32kk + 8g + 4h + rp
-            const int k0 = 32 * kk + 8 * g + rp, k1 = k0 + 4;
-            bf16x8 b[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = tr16_frag(dt + k0 * kPS + 16 * j + rc, dt + k1 * kPS + 16 * j + rc);
-            const int py0 = k0 >> 4, px0 = k0 & 15, py1 = k1 >> 4, px1 = k1 & 15;
-#pragma unroll
-            for (int ib = 0; ib < 9; ++ib) {
-                const int mb = 9 * wq + ib;
-                const int t = mb >> 2, ci0 = (mb & 3) * 16;
-                const int dy = t / 3, dx = t - 3 * (t / 3);
-                const bf16x8 a = tr16_frag(halo + ((py0 + dy) * kHalo + px0 + dx) * kPS + ci0 + rc,
-                                           halo + ((py1 + dy) * kHalo + px1 + dx) * kPS + ci0 + rc);
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[ib][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[ib][j], 0, 0, 0);
-            }
-        }
-        __syncthreads();
-        if (tid < kWidth)
-            dbacc += ((dbs[grp][0][tid] + dbs[grp][1][tid]) + dbs[grp][2][tid]) + dbs[grp][3][tid];
-    }
-
-    // group 1 hands its sums to group 0 through LDS; group 0 adds and writes
-    float* xch = reinterpret_cast<float*>(buf);          // 4 waves x 144 values x 64 lanes
-    if (grp == 1) {
-#pragma unroll
-        for (int ib = 0; ib < 9; ++ib)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) xch[((wq * 9 + ib) * 16 + j * 4 + e) * 64 + lane] = acc[ib][j][e];
-        if (tid < kWidth) dbs[1][0][tid] = dbacc;
+    uint4 pf[kWgPf];
+    if (nmine > 0) {
+        wg_load(pf, src, dlt, sp, tiles_x, q, h, w);
+        wg_store(pf, bufs);
     }
     __syncthreads();
-    if (grp == 0) {
-        float* pp = part + (long long)blockIdx.x * kConvN;
+    // this wave's pixels: k0 = 32 wv + 8 g + r/4 and k0 + 4 of the tile
+    const int rp = r >> 2, rc = 4 * (r & 3);
+    const int k0 = 32 * wv + 8 * g + rp, k1 = k0 + 4;
+    const int py0 = k0 >> 4, px0 = k0 & 15, py1 = k1 >> 4, px1 = k1 & 15;
+    for (int it = 0; it < nmine; ++it) {
+        const uint16_t* halo = bufs + (it & 1) * kWgBufE;
+        const uint16_t* dt = halo + kWgHaloE;
+        const bool more = it + 1 < nmine;
+        if (more) wg_load(pf, src, dlt, sp + (it + 1) * nsplit, tiles_x, q, h, w);
+        if (q == 0) {
 #pragma unroll
-        for (int ib = 0; ib < 9; ++ib) {
-            const int mb = 9 * wq + ib;
-            const int t = mb >> 2, ci0 = (mb & 3) * 16;
+            for (int k = 0; k < 4; ++k) {
+                const uint2* v = reinterpret_cast<const uint2*>(dt + (4 * (tid >> 3) + k) * kWgPSB + 8 * (tid & 7));
+                const uint2 lo = v[0], hi = v[1];
+                const uint32_t u[4] = {lo.x, lo.y, hi.x, hi.y};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    db[2 * e] += __uint_as_float(u[e] << 16);
+                    db[2 * e + 1] += __uint_as_float(u[e] & 0xffff0000u);
+                }
+            }
+        }
+        bf16x8 bfr[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            bfr[j] = tr16_frag(dt + k0 * kWgPSB + 16 * j + rc, dt + k1 * kWgPSB + 16 * j + rc);
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) {
+            const int dy = t / 3, dx = t - 3 * (t / 3);
+            const bf16x8 a = tr16_frag(halo + ((py0 + dy) * kHalo + px0 + dx) * kWgPSA + rc,
+                                       halo + ((py1 + dy) * kHalo + px1 + dx) * kWgPSA + rc);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[j], acc[t][j], 0, 0, 0);
+        }
+        if (more) wg_store(pf, bufs + ((it + 1) & 1) * kWgBufE);
+        __syncthreads();
+    }
+
+    // sum the 8 waves in order, three taps at a time
+    float* red = reinterpret_cast<float*>(lds);
+    float* pp = part + (long long)sp * kConvN;
+#pragma unroll
+    for (int pass = 0; pass < 3; ++pass) {
+#pragma unroll
+        for (int tt = 0; tt < 3; ++tt)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    pp[(t * 64 + ci0 + 4 * g + e) * 64 + 16 * j + r] =
-                        acc[ib][j][e] + xch[((wq * 9 + ib) * 16 + j * 4 + e) * 64 + lane];
+                for (int e = 0; e < 4; ++e) red[(wv * 12 + tt * 4 + j) * kWgRedS + e * 64 + lane] = acc[3 * pass + tt][j][e];
+        __syncthreads();
+        for (int o = tid; o < 3 * 16 * kWidth; o += 512) {
+            const int tt = o >> 10, cil = (o >> 6) & 15, co = o & 63;
+            const int idx = (tt * 4 + (co >> 4)) * kWgRedS + (cil & 3) * 64 + 16 * (cil >> 2) + (co & 15);
+            float sum = red[idx];
+#pragma unroll
+            for (int k = 1; k < 8; ++k) sum += red[k * 12 * kWgRedS + idx];
+            pp[((3 * pass + tt) * kWidth + 16 * q + cil) * kWidth + co] = sum;
         }
-        if (tid < kWidth) pp[kConvW + tid] = dbacc + dbs[1][0][tid];
+        __syncthreads();
+    }
+    if (q == 0) {
+        // pixel groups of one chunk: lanes tid, tid + 8, ... of 64 groups, in order
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dbs[tid >> 3][8 * (tid & 7) + e] = db[e];
+        __syncthreads();
+        if (tid < kWidth) {
+            float sum = dbs[0][tid];
+            for (int k = 1; k < 64; ++k) sum += dbs[k][tid];
+            pp[kConvW + tid] = sum;
+        }
     }
 }
 
@@ -533,15 +595,16 @@ hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, v
     return hipGetLastError();
 }
 
-int wgrad_splits(int h, int w) {
+int wgrad_splits(int h, int w, int bf16) {
     const int tiles = ((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile);
-    return tiles < kMaxSplit ? tiles : kMaxSplit;
+    const int cap = bf16 ? kMaxSplitBf16 : kMaxSplit;
+    return tiles < cap ? tiles : cap;
 }
 
 hipError_t launch_wgrad(const void* src, const void* dlt, float* part, int nsplit, int bf16, int h, int w,
                         const DevState* st, hipStream_t s) {
     if (bf16) {
-        hipLaunchKernelGGL(k_wgrad_bf16, dim3(nsplit), dim3(512), 0, s, (const uint16_t*)src, (const uint16_t*)dlt,
+        hipLaunchKernelGGL(k_wgrad_bf16, dim3(4 * nsplit), dim3(512), 0, s, (const uint16_t*)src, (const uint16_t*)dlt,
                            part, h, w, st);
         return hipGetLastError();
     }

@@ -17,6 +17,7 @@ constexpr int kConvW = kTaps * kWidth * kWidth;   // weights of a 64->64 layer
 constexpr int kConvN = kConvW + kWidth;           // ... plus its bias
 constexpr int kHeadN = kWidth + 1;                // 1x1 head: 64 weights + bias
 constexpr int kMaxSplit = 256;                    // max pixel splits of a weight gradient
+constexpr int kMaxSplitBf16 = 64;                 // ... of the BF16 64->64 one (4 blocks per split)
 constexpr int kMaxHeadSplit = 1024;               // max blocks of the training head
 
 // Per-network state that lives in device memory.  The stopping rule is
@@ -76,7 +77,7 @@ hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, v
                            int h, int w, const DevState* st, hipStream_t s);
 hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, void* out, int bf16,
                            int h, int w, const DevState* st, hipStream_t s);
-int wgrad_splits(int h, int w);
+int wgrad_splits(int h, int w, int bf16);
 hipError_t launch_wgrad(const void* src, const void* dlt, float* part, int nsplit, int bf16,
                         int h, int w, const DevState* st, hipStream_t s);
 hipError_t launch_wgrad1(const float* in, int C, const void* dlt, float* part, int nsplit, int bf16,

@@ -67,6 +67,42 @@ __device__ __forceinline__ void store4(void* base, long long idx, float4 v, bool
     *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(base) + idx) = r;
 }
 
+// Eight consecutive channels of an activation row as FP32: one 16-byte load
+// (BF16) or two (FP32).
+template <bool BF>
+__device__ __forceinline__ void load8(const void* base, long long idx, float (&v)[8]) {
+    if constexpr (BF) {
+        const uint4 r = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(base) + idx);
+        const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            v[2 * e] = __uint_as_float(u[e] << 16);
+            v[2 * e + 1] = __uint_as_float(u[e] & 0xffff0000u);
+        }
+    } else {
+        const float4* q = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(base) + idx);
+        const float4 a = q[0], b = q[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    }
+}
+
+template <bool BF>
+__device__ __forceinline__ void store8(void* base, long long idx, const float (&v)[8]) {
+    if constexpr (BF) {
+        uint4 r;
+        r.x = (uint32_t)f32_to_bf16_rne(v[0]) | ((uint32_t)f32_to_bf16_rne(v[1]) << 16);
+        r.y = (uint32_t)f32_to_bf16_rne(v[2]) | ((uint32_t)f32_to_bf16_rne(v[3]) << 16);
+        r.z = (uint32_t)f32_to_bf16_rne(v[4]) | ((uint32_t)f32_to_bf16_rne(v[5]) << 16);
+        r.w = (uint32_t)f32_to_bf16_rne(v[6]) | ((uint32_t)f32_to_bf16_rne(v[7]) << 16);
+        *reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(base) + idx) = r;
+    } else {
+        float4* q = reinterpret_cast<float4*>(reinterpret_cast<float*>(base) + idx);
+        q[0] = make_float4(v[0], v[1], v[2], v[3]);
+        q[1] = make_float4(v[4], v[5], v[6], v[7]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Exact min and max of the whole image, with a non-finite flag.
 // ---------------------------------------------------------------------------
@@ -192,118 +228,163 @@ __global__ __launch_bounds__(kBlock) void k_pack(const float* __restrict__ theta
 
 // ---------------------------------------------------------------------------
 // First 3x3 conv (C <= 3 input channels, K = 9C is too short for MFMA) with
-// bias and ReLU.  Thread = (pixel, group of 16 output channels): four
-// consecutive lanes write one pixel's 64 channels contiguously.
+// bias and ReLU.  Thread = (pixel slot, group of 8 output channels): the
+// eight lanes of a pixel write its 64 channels as one contiguous row, so a
+// wave stores 8 whole pixels per instruction.  Each thread first issues the
+// input-tap loads of all its U pixels (lane-uniform within a pixel, served
+// by the cache), then computes and stores them, so one memory latency covers
+// U pixels.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_conv1(const float* __restrict__ in, int C,
-                                                  const float* __restrict__ w1, const float* __restrict__ b1,
-                                                  void* __restrict__ out, int bf, int h, int w,
+constexpr int kPxPerBlock = kBlock / 8;
+
+template <int C>
+constexpr int conv1_unroll() { return C == 1 ? 4 : (C == 2 ? 2 : 1); }
+
+template <int C, bool BF>
+__global__ __launch_bounds__(kBlock) void k_conv1(const float* __restrict__ in, const float* __restrict__ w1,
+                                                  const float* __restrict__ b1, void* __restrict__ out, int h, int w,
                                                   const DevState* st) {
     if (finished(st)) return;
-    __shared__ __attribute__((aligned(16))) float sw[kTaps * 3 * kWidth + kWidth];
+    constexpr int U = conv1_unroll<C>();
+    __shared__ __attribute__((aligned(16))) float sw[kTaps * C * kWidth + kWidth];
     for (int i = threadIdx.x; i < kTaps * C * kWidth; i += kBlock) sw[i] = w1[i];
-    for (int i = threadIdx.x; i < kWidth; i += kBlock) sw[kTaps * 3 * kWidth + i] = b1[i];
-    __syncthreads();
-    const long long p = (long long)blockIdx.x * (kBlock / 4) + (threadIdx.x >> 2);
-    const int cg = threadIdx.x & 3;
-    if (p >= (long long)h * w) return;
-    const int y = (int)(p / w), x = (int)(p - (long long)y * w);
-    float acc[16];
-    const float4* bb = reinterpret_cast<const float4*>(sw + kTaps * 3 * kWidth + 16 * cg);
+    for (int i = threadIdx.x; i < kWidth; i += kBlock) sw[kTaps * C * kWidth + i] = b1[i];
+    const long long npix = (long long)h * w;
+    const int cg = threadIdx.x & 7;
+    const long long pbase = (long long)blockIdx.x * (kPxPerBlock * U) + (threadIdx.x >> 3);
+    float xv[U][kTaps * C];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const float4 v = bb[r];
-        acc[4 * r] = v.x;
-        acc[4 * r + 1] = v.y;
-        acc[4 * r + 2] = v.z;
-        acc[4 * r + 3] = v.w;
-    }
-    for (int t = 0; t < kTaps; ++t) {
-        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-        if (yy < 0 || yy >= h || xx < 0 || xx >= w) continue;
-        const float* src = in + ((long long)yy * w + xx) * C;
-        for (int c = 0; c < C; ++c) {
-            const float v = src[c];
-            const float4* ww = reinterpret_cast<const float4*>(sw + (t * C + c) * kWidth + 16 * cg);
+    for (int u = 0; u < U; ++u) {
+        const long long p = pbase + kPxPerBlock * u;
+        const int y = (int)(p / w), x = (int)(p - (long long)y * w);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float4 wv = ww[r];
-                acc[4 * r] = fmaf(v, wv.x, acc[4 * r]);
-                acc[4 * r + 1] = fmaf(v, wv.y, acc[4 * r + 1]);
-                acc[4 * r + 2] = fmaf(v, wv.z, acc[4 * r + 2]);
-                acc[4 * r + 3] = fmaf(v, wv.w, acc[4 * r + 3]);
-            }
+        for (int t = 0; t < kTaps; ++t) {
+            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+            const bool inside = p < npix && yy >= 0 && yy < h && xx >= 0 && xx < w;
+#pragma unroll
+            for (int c = 0; c < C; ++c) xv[u][t * C + c] = inside ? in[((long long)yy * w + xx) * C + c] : 0.f;
         }
     }
+    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        store4(out, p * kWidth + 16 * cg + 4 * r,
-               make_float4(fmaxf(acc[4 * r], 0.f), fmaxf(acc[4 * r + 1], 0.f), fmaxf(acc[4 * r + 2], 0.f),
-                           fmaxf(acc[4 * r + 3], 0.f)),
-               bf != 0);
+    for (int u = 0; u < U; ++u) {
+        const long long p = pbase + kPxPerBlock * u;
+        if (p >= npix) break;
+        float acc[8];
+        {
+            const float4* bb = reinterpret_cast<const float4*>(sw + kTaps * C * kWidth + 8 * cg);
+            const float4 v0 = bb[0], v1 = bb[1];
+            acc[0] = v0.x; acc[1] = v0.y; acc[2] = v0.z; acc[3] = v0.w;
+            acc[4] = v1.x; acc[5] = v1.y; acc[6] = v1.z; acc[7] = v1.w;
+        }
+#pragma unroll
+        for (int tc = 0; tc < kTaps * C; ++tc) {
+            const float v = xv[u][tc];
+            const float4* ww = reinterpret_cast<const float4*>(sw + tc * kWidth + 8 * cg);
+            const float4 u0 = ww[0], u1 = ww[1];
+            acc[0] = fmaf(v, u0.x, acc[0]);
+            acc[1] = fmaf(v, u0.y, acc[1]);
+            acc[2] = fmaf(v, u0.z, acc[2]);
+            acc[3] = fmaf(v, u0.w, acc[3]);
+            acc[4] = fmaf(v, u1.x, acc[4]);
+            acc[5] = fmaf(v, u1.y, acc[5]);
+            acc[6] = fmaf(v, u1.z, acc[6]);
+            acc[7] = fmaf(v, u1.w, acc[7]);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[e] = fmaxf(acc[e], 0.f);
+        store8<BF>(out, p * kWidth + 8 * cg, acc);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Weight gradient of the first layer: dW1[t][c][co] = sum_p x[p + off(t)][c]
-// * d1[p][co] and db1[co] = sum_p d1[p][co], one partial sum per split of
-// 16x16 pixel tiles.  Thread = (output channel, quarter of the tile's
-// pixels): the delta read is one distinct word per lane, the input reads
-// are wave-wide broadcasts; quarters are added in a fixed order.
+// * d1[p][co] (x zero outside the image) and db1[co] = sum_p d1[p][co], one
+// partial sum per block over a contiguous range of pixels.  Thread = (pixel
+// slot, group of G output channels): the delta row of a pixel is read with
+// 16-byte (8-byte for G = 4) loads by 64/G lanes; the input taps are
+// lane-uniform per pixel.  The slots of a wave are summed by a fixed xor
+// butterfly, the waves in order through LDS.
 // ---------------------------------------------------------------------------
-template <int C>
-__global__ __launch_bounds__(kBlock) void k_wgrad1(const float* __restrict__ in,
-                                                   const void* __restrict__ dlt, int bf,
-                                                   float* __restrict__ part, int h, int w,
-                                                   const DevState* st) {
+constexpr int kWg1Block = 512;
+
+template <int C, bool BF>
+__global__ __launch_bounds__(kWg1Block) void k_wgrad1(const float* __restrict__ in, const void* __restrict__ dlt,
+                                                   float* __restrict__ part, int h, int w, const DevState* st) {
     if (finished(st)) return;
-    constexpr int nW = kTaps * C * kWidth;
-    constexpr int n1 = nW + kWidth;
+    constexpr int G = (C == 1) ? 8 : 4;          // channels per lane
+    constexpr int LPP = kWidth / G;              // lanes per pixel
+    constexpr int SLOTS = kWg1Block / LPP;
     constexpr int nacc = kTaps * C + 1;          // weights (t, c) then the bias
-    __shared__ float sx[18 * 18 * C];
-    __shared__ float sd[256 * kWidth];
-    const int co = threadIdx.x & 63, pg = threadIdx.x >> 6;
-    float acc[nacc];
+    constexpr int n1 = nacc * kWidth;
+    __shared__ float red[kWg1Block / 64][n1];
+    const int cg = threadIdx.x % LPP, slot = threadIdx.x / LPP;
+    const long long npix = (long long)h * w;
+    const long long chunk = (npix + gridDim.x - 1) / gridDim.x;
+    const long long p0 = (long long)blockIdx.x * chunk;
+    const long long p1 = min(npix, p0 + chunk);
+    float acc[nacc][G];
 #pragma unroll
-    for (int r = 0; r < nacc; ++r) acc[r] = 0.f;
-    const int tiles_x = (w + 15) >> 4, tiles_y = (h + 15) >> 4;
-    const int ntiles = tiles_x * tiles_y;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int x0 = (tile % tiles_x) * 16, y0 = (tile / tiles_x) * 16;
-        for (int i = threadIdx.x; i < 18 * 18 * C; i += kBlock) {
-            const int pix = i / C, c = i - pix * C;
-            const int gy = y0 - 1 + pix / 18, gx = x0 - 1 + pix % 18;
-            sx[i] = (gy >= 0 && gy < h && gx >= 0 && gx < w) ? in[((long long)gy * w + gx) * C + c] : 0.f;
-        }
-        for (int i = threadIdx.x; i < 256 * 16; i += kBlock) {
-            const int p = i >> 4, q = i & 15;
-            const int gy = y0 + (p >> 4), gx = x0 + (p & 15);
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (gy < h && gx < w) v = load4(dlt, ((long long)gy * w + gx) * kWidth + 4 * q, bf != 0);
-            *reinterpret_cast<float4*>(sd + p * kWidth + 4 * q) = v;
-        }
-        __syncthreads();
-        for (int p = pg * 64; p < pg * 64 + 64; ++p) {
-            const float d = sd[p * kWidth + co];
-            const int py = p >> 4, px = p & 15;
+    for (int r = 0; r < nacc; ++r)
 #pragma unroll
-            for (int t = 0; t < kTaps; ++t)
+        for (int e = 0; e < G; ++e) acc[r][e] = 0.f;
+    constexpr int U = 4;                         // pixels per slot per batch, loaded before use
+    for (long long pb = p0 + slot; pb < p1; pb += (long long)SLOTS * U) {
+        float d[U][G], xv[U][kTaps * C];
 #pragma unroll
-                for (int c = 0; c < C; ++c)
-                    acc[t * C + c] = fmaf(sx[((py + t / 3) * 18 + px + t % 3) * C + c], d, acc[t * C + c]);
-            acc[kTaps * C] += d;
+        for (int u = 0; u < U; ++u) {
+            const long long p = pb + (long long)SLOTS * u;
+            const bool live = p < p1;
+            if constexpr (G == 8) {
+                if (live) {
+                    load8<BF>(dlt, p * kWidth + 8 * cg, d[u]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) d[u][e] = 0.f;
+                }
+            } else {
+                const float4 v = live ? load4(dlt, p * kWidth + 4 * cg, BF) : make_float4(0.f, 0.f, 0.f, 0.f);
+                d[u][0] = v.x; d[u][1] = v.y; d[u][2] = v.z; d[u][3] = v.w;
+            }
+            const int y = (int)(p / w), x = (int)(p - (long long)y * w);
+#pragma unroll
+            for (int t = 0; t < kTaps; ++t) {
+                const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+                const bool inside = live && yy >= 0 && yy < h && xx >= 0 && xx < w;
+#pragma unroll
+                for (int c = 0; c < C; ++c) xv[u][t * C + c] = inside ? in[((long long)yy * w + xx) * C + c] : 0.f;
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int tc = 0; tc < kTaps * C; ++tc)
+#pragma unroll
+                for (int e = 0; e < G; ++e) acc[tc][e] = fmaf(xv[u][tc], d[u][e], acc[tc][e]);
+#pragma unroll
+            for (int e = 0; e < G; ++e) acc[kTaps * C][e] += d[u][e];
+        }
     }
-    // add the four pixel quarters in order through LDS (reusing sd)
+    // slots of one wave: lanes cg, cg + LPP, ... hold the same channels
 #pragma unroll
-    for (int r = 0; r < nacc; ++r) sd[(pg * nacc + r) * kWidth + co] = acc[r];
+    for (int off = LPP; off < 64; off <<= 1)
+#pragma unroll
+        for (int r = 0; r < nacc; ++r)
+#pragma unroll
+            for (int e = 0; e < G; ++e) acc[r][e] += __shfl_xor(acc[r][e], off);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) < LPP) {
+#pragma unroll
+        for (int r = 0; r < nacc; ++r)
+#pragma unroll
+            for (int e = 0; e < G; ++e) red[wv][r * kWidth + G * cg + e] = acc[r][e];
+    }
     __syncthreads();
-    for (int o = threadIdx.x; o < n1; o += kBlock) {
-        const int r = (o < nW) ? (o >> 6) : kTaps * C;    // (t * C + c), or the bias slot
-        const int c2 = o & 63;
-        float s = 0.f;
-        for (int q = 0; q < 4; ++q) s += sd[(q * nacc + r) * kWidth + c2];
-        part[(long long)blockIdx.x * n1 + o] = s;
+    for (int o = threadIdx.x; o < n1; o += kWg1Block) {
+        float sum = red[0][o];
+#pragma unroll
+        for (int q = 1; q < kWg1Block / 64; ++q) sum += red[q][o];
+        part[(long long)blockIdx.x * n1 + o] = sum;
     }
 }
 
@@ -311,112 +392,156 @@ __global__ __launch_bounds__(kBlock) void k_wgrad1(const float* __restrict__ in,
 // Training head: z = w9 . a8 + b9, y = sigmoid(z), dL/dz = (y - t) / P for
 // the mean BCE; d8 = dL/dz * w9 * [a8 > 0]; per-split partial sums of dW9 =
 // sum dL/dz * a8, db9 = sum dL/dz, and of the BCE (softplus(z) - t z).
-// 16 threads per pixel (4 channels each), 16 pixels per pass.
+// 8 lanes per pixel (8 channels each, one 16-byte row chunk), 32 pixels per
+// pass; z is the xor-butterfly sum over the pixel's lanes.
 // ---------------------------------------------------------------------------
+template <bool BF>
 __global__ __launch_bounds__(kBlock) void k_head_train(const void* __restrict__ a8, const float* __restrict__ tgt,
                                                        int C, int k, const float* __restrict__ w9,
                                                        const float* __restrict__ b9, void* __restrict__ d8,
                                                        float* __restrict__ part, double* __restrict__ lpart,
-                                                       int bf, long long npix, DevState* st) {
+                                                       long long npix, DevState* st) {
     if (finished(st)) return;
-    __shared__ float sacc[16][kWidth + 1];
-    __shared__ double sl[16];
-    const int q = threadIdx.x & 15, pg = threadIdx.x >> 4;
-    const float4 wv = *reinterpret_cast<const float4*>(w9 + 4 * q);
+    __shared__ float sacc[kPxPerBlock][kWidth + 1];
+    __shared__ double sl[kPxPerBlock];
+    const int q = threadIdx.x & 7, ps = threadIdx.x >> 3;
+    float wv[8];
+    {
+        const float4 u = *reinterpret_cast<const float4*>(w9 + 8 * q);
+        const float4 v = *reinterpret_cast<const float4*>(w9 + 8 * q + 4);
+        wv[0] = u.x; wv[1] = u.y; wv[2] = u.z; wv[3] = u.w;
+        wv[4] = v.x; wv[5] = v.y; wv[6] = v.z; wv[7] = v.w;
+    }
     const float bb = *b9;
-    const long long chunk = (((npix + gridDim.x - 1) / gridDim.x) + 15) & ~15LL;
+    const long long chunk = (((npix + gridDim.x - 1) / gridDim.x) + kPxPerBlock - 1) / kPxPerBlock * kPxPerBlock;
     const long long p0 = (long long)blockIdx.x * chunk;
     const long long p1 = min(npix, p0 + chunk);
     const float invP = 1.0f / (float)npix;
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, gb = 0.f;
+    float g[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) g[e] = 0.f;
+    float gb = 0.f;
     double lacc = 0.0;
-    for (long long p = p0 + pg; p < p1; p += 16) {
-        const float4 a = load4(a8, p * kWidth + 4 * q, bf != 0);
-        float z = a.x * wv.x + a.y * wv.y + a.z * wv.z + a.w * wv.w;
-        z += __shfl_xor(z, 8, 16);
-        z += __shfl_xor(z, 4, 16);
-        z += __shfl_xor(z, 2, 16);
-        z += __shfl_xor(z, 1, 16);
-        z += bb;
-        const float y = 1.0f / (1.0f + expf(-z));
-        const float t = tgt[p * C + k];
-        const float d = (y - t) * invP;
-        const float4 dv = make_float4(a.x > 0.f ? d * wv.x : 0.f, a.y > 0.f ? d * wv.y : 0.f,
-                                      a.z > 0.f ? d * wv.z : 0.f, a.w > 0.f ? d * wv.w : 0.f);
-        store4(d8, p * kWidth + 4 * q, dv, bf != 0);
-        g0 = fmaf(d, a.x, g0);
-        g1 = fmaf(d, a.y, g1);
-        g2 = fmaf(d, a.z, g2);
-        g3 = fmaf(d, a.w, g3);
-        if (q == 0) {
-            gb += d;
-            lacc += (double)(fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - t * z);
+    constexpr int U = 4;                         // pixels per thread per batch, loaded before use
+    for (long long pb = p0 + ps; pb < p1; pb += kPxPerBlock * U) {
+        float a[U][8], tv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long p = pb + kPxPerBlock * u;
+            if (p < p1) {
+                load8<BF>(a8, p * kWidth + 8 * q, a[u]);
+                tv[u] = tgt[p * C + k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long p = pb + kPxPerBlock * u;
+            if (p >= p1) break;
+            float z = a[u][0] * wv[0];
+#pragma unroll
+            for (int e = 1; e < 8; ++e) z = fmaf(a[u][e], wv[e], z);
+            z += __shfl_xor(z, 4, 8);
+            z += __shfl_xor(z, 2, 8);
+            z += __shfl_xor(z, 1, 8);
+            z += bb;
+            const float y = 1.0f / (1.0f + expf(-z));
+            const float t = tv[u];
+            const float d = (y - t) * invP;
+            float dv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dv[e] = a[u][e] > 0.f ? d * wv[e] : 0.f;
+            store8<BF>(d8, p * kWidth + 8 * q, dv);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) g[e] = fmaf(d, a[u][e], g[e]);
+            if (q == 0) {
+                gb += d;
+                lacc += (double)(fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - t * z);
+            }
         }
     }
-    sacc[pg][4 * q + 0] = g0;
-    sacc[pg][4 * q + 1] = g1;
-    sacc[pg][4 * q + 2] = g2;
-    sacc[pg][4 * q + 3] = g3;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sacc[ps][8 * q + e] = g[e];
     if (q == 0) {
-        sacc[pg][kWidth] = gb;
-        sl[pg] = lacc;
+        sacc[ps][kWidth] = gb;
+        sl[ps] = lacc;
     }
     __syncthreads();
     if (threadIdx.x <= kWidth) {
-        float s = 0.f;
-        for (int i = 0; i < 16; ++i) s += sacc[i][threadIdx.x];
-        part[(long long)blockIdx.x * kHeadN + threadIdx.x] = s;
+        float sum = 0.f;
+        for (int i = 0; i < kPxPerBlock; ++i) sum += sacc[i][threadIdx.x];
+        part[(long long)blockIdx.x * kHeadN + threadIdx.x] = sum;
     }
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < 16; ++i) s += sl[i];
-        lpart[blockIdx.x] = s;
+        double sum = 0.0;
+        for (int i = 0; i < kPxPerBlock; ++i) sum += sl[i];
+        lpart[blockIdx.x] = sum;
         // one Adam step follows this head: count it (no other block reads t)
         if (blockIdx.x == 0) st->t += 1;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Validation head: y = sigmoid(w9 . a8 + b9) over the full image, FP64
-// partial sums of (y - x_k)^2, and in the last block the score and the
-// stopping rule (strict improvement; `patience` non-improving epochs end
-// the run; or exactly `fixed_epochs` epochs).
+// Validation head: y = sigmoid(w9 . a8 + b9) over the full image and FP64
+// partial sums of (y - x_k)^2 per block.  Same lane layout and z sum as the
+// training head.
 // ---------------------------------------------------------------------------
+template <bool BF>
 __global__ __launch_bounds__(kBlock) void k_head_val(const void* __restrict__ a8, const float* __restrict__ xs,
                                                      int C, int k, const float* __restrict__ w9,
                                                      const float* __restrict__ b9, float* __restrict__ y,
-                                                     double* __restrict__ vpart, int bf, long long npix,
-                                                     DevState* st, double* __restrict__ vtrace) {
+                                                     double* __restrict__ vpart, long long npix,
+                                                     const DevState* st) {
     if (finished(st)) return;
-    __shared__ double sl[16];
-    const int q = threadIdx.x & 15, pg = threadIdx.x >> 4;
-    const float4 wv = *reinterpret_cast<const float4*>(w9 + 4 * q);
+    __shared__ double sl[kPxPerBlock];
+    const int q = threadIdx.x & 7, ps = threadIdx.x >> 3;
+    float wv[8];
+    {
+        const float4 u = *reinterpret_cast<const float4*>(w9 + 8 * q);
+        const float4 v = *reinterpret_cast<const float4*>(w9 + 8 * q + 4);
+        wv[0] = u.x; wv[1] = u.y; wv[2] = u.z; wv[3] = u.w;
+        wv[4] = v.x; wv[5] = v.y; wv[6] = v.z; wv[7] = v.w;
+    }
     const float bb = *b9;
-    const long long chunk = (((npix + gridDim.x - 1) / gridDim.x) + 15) & ~15LL;
+    const long long chunk = (((npix + gridDim.x - 1) / gridDim.x) + kPxPerBlock - 1) / kPxPerBlock * kPxPerBlock;
     const long long p0 = (long long)blockIdx.x * chunk;
     const long long p1 = min(npix, p0 + chunk);
     double acc = 0.0;
-    for (long long p = p0 + pg; p < p1; p += 16) {
-        const float4 a = load4(a8, p * kWidth + 4 * q, bf != 0);
-        float z = a.x * wv.x + a.y * wv.y + a.z * wv.z + a.w * wv.w;
-        z += __shfl_xor(z, 8, 16);
-        z += __shfl_xor(z, 4, 16);
-        z += __shfl_xor(z, 2, 16);
-        z += __shfl_xor(z, 1, 16);
-        z += bb;
-        if (q == 0) {
-            const float yv = 1.0f / (1.0f + expf(-z));
-            y[p] = yv;
-            const double e = (double)yv - (double)xs[p * C + k];
-            acc += e * e;
+    constexpr int U = 4;
+    for (long long pb = p0 + ps; pb < p1; pb += kPxPerBlock * U) {
+        float a[U][8], xk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long p = pb + kPxPerBlock * u;
+            if (p < p1) {
+                load8<BF>(a8, p * kWidth + 8 * q, a[u]);
+                xk[u] = xs[p * C + k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long p = pb + kPxPerBlock * u;
+            if (p >= p1) break;
+            float z = a[u][0] * wv[0];
+#pragma unroll
+            for (int e = 1; e < 8; ++e) z = fmaf(a[u][e], wv[e], z);
+            z += __shfl_xor(z, 4, 8);
+            z += __shfl_xor(z, 2, 8);
+            z += __shfl_xor(z, 1, 8);
+            z += bb;
+            if (q == 0) {
+                const float yv = 1.0f / (1.0f + expf(-z));
+                y[p] = yv;
+                const double e = (double)yv - (double)xk[u];
+                acc += e * e;
+            }
         }
     }
-    if (q == 0) sl[pg] = acc;
+    if (q == 0) sl[ps] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < 16; ++i) s += sl[i];
-        vpart[blockIdx.x] = s;
+        double sum = 0.0;
+        for (int i = 0; i < kPxPerBlock; ++i) sum += sl[i];
+        vpart[blockIdx.x] = sum;
     }
 }
 
@@ -527,12 +652,17 @@ __device__ __forceinline__ void adam_one(float* __restrict__ theta, float* __res
     if (l >= 1 && l < kLayers && il < kConvW) pack_one(l, il, th, fwd, bwd, fwd16, bwd16);
 }
 
-// Blocks [0, 7 * kAdamBPL) each own 256 consecutive values of one 64->64
-// layer and sum that layer's split partials with 16-byte loads (4 split
-// groups, added in group order); the remaining blocks own 32 values of the
-// first layer or the head (8 split groups).  Either way the sum order is
-// fixed.
-constexpr int kAdamBPL = (kConvN + 255) / 256;     // blocks per 64->64 layer
+// Waves [0, 7 * kAdamWPL) each own 256 consecutive values of one 64->64
+// layer: a lane sums its 4 values over all of the layer's split partials in
+// split order with 16-byte loads (16 in flight) and applies Adam to them.
+// The blocks after those own a few values of the first layer (32 values x 8
+// split groups) or of the head (4 values x 64 split groups), whose partials
+// are many short rows; the group sums are added in group order.  The last
+// block sums the loss partials.  Every sum order is fixed.
+constexpr int kAdamWPL = (kConvN + 255) / 256;           // waves per 64->64 layer
+constexpr int kAdamConvBlocks = ((kLayers - 1) * kAdamWPL + 3) / 4;
+constexpr int kAdamV0 = 32;                              // first layer: values per block
+constexpr int kAdamVH = 4;                               // head: values per block
 
 __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, float* __restrict__ m,
                                                  float* __restrict__ v, float* __restrict__ g,
@@ -542,13 +672,23 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, floa
                                                  const double* __restrict__ lpart, int nloss, long long loss_npix,
                                                  DevState* st) {
     if (finished(st)) return;
-    __shared__ float4 red4[4][64];
-    __shared__ float red[8][33];
+    __shared__ float red[kBlock];
+    __shared__ double lred[kBlock];
     const long long t_new = st->t;   // this step, already counted by the head kernel (or the bump)
-    if (blockIdx.x == 0 && threadIdx.x == 0 && !ginj) {
+    if ((int)blockIdx.x == (int)gridDim.x - 1) {
+        // the last block only reports the step's loss: fixed-order sum of
+        // the head's FP64 partials (strided per thread, then a tree)
+        if (ginj) return;
         double l = 0.0;
-        for (int b = 0; b < nloss; ++b) l += lpart[b];
-        st->loss = l / (double)loss_npix;
+        for (int b = threadIdx.x; b < nloss; b += kBlock) l += lpart[b];
+        lred[threadIdx.x] = l;
+        __syncthreads();
+        for (int k = kBlock / 2; k > 0; k >>= 1) {
+            if ((int)threadIdx.x < k) lred[threadIdx.x] += lred[threadIdx.x + k];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) st->loss = lred[0] / (double)loss_npix;
+        return;
     }
     // decay factors and their complements formed in FP64, each rounded
     // once: 1 - (float)0.999 would be off by 1e-5 relative
@@ -556,64 +696,58 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, floa
     const float omb1 = (float)(1.0 - beta1), omb2 = (float)(1.0 - beta2);
     const float bc1 = (float)(1.0 - pow(beta1, (double)t_new));
     const float bc2 = (float)(1.0 - pow(beta2, (double)t_new));
-    const int nconv = (kLayers - 1) * kAdamBPL;
-    if ((int)blockIdx.x < nconv) {
-        const int l = 1 + blockIdx.x / kAdamBPL;
-        const int il0 = (blockIdx.x % kAdamBPL) * 256;
-        const int q = threadIdx.x & 63, j = threadIdx.x >> 6;
-        const int il = il0 + 4 * q;
-        const bool valid = il < kConvN;
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (valid && !ginj) {
+    if ((int)blockIdx.x < kAdamConvBlocks) {
+        const int wid = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+        if (wid >= (kLayers - 1) * kAdamWPL) return;
+        const int l = 1 + wid / kAdamWPL;
+        const int il = (wid % kAdamWPL) * 256 + 4 * (threadIdx.x & 63);
+        if (il >= kConvN) return;
+        const int i0 = pt.off[l] + il;
+        float gg[4];
+        if (ginj) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) gg[e] = ginj[i0 + e];
+        } else {
             const float4* pp = reinterpret_cast<const float4*>(part + pt.poff[l] + il);
             const int row4 = kConvN / 4;
-#pragma unroll 8
-            for (int sp = j; sp < pt.split[l]; sp += 4) {
+            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 16
+            for (int sp = 0; sp < pt.split[l]; ++sp) {
                 const float4 x = pp[(long long)sp * row4];
                 acc.x += x.x;
                 acc.y += x.y;
                 acc.z += x.z;
                 acc.w += x.w;
             }
+            gg[0] = acc.x;
+            gg[1] = acc.y;
+            gg[2] = acc.z;
+            gg[3] = acc.w;
         }
-        red4[j][q] = acc;
-        __syncthreads();
-        if (j == 0 && valid) {
-            const int i0 = pt.off[l] + il;
-            float gg[4];
-            if (ginj) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) gg[e] = ginj[i0 + e];
-            } else {
-                const float4 s0 = red4[0][q], s1 = red4[1][q], s2 = red4[2][q], s3 = red4[3][q];
-                gg[0] = ((s0.x + s1.x) + s2.x) + s3.x;
-                gg[1] = ((s0.y + s1.y) + s2.y) + s3.y;
-                gg[2] = ((s0.z + s1.z) + s2.z) + s3.z;
-                gg[3] = ((s0.w + s1.w) + s2.w) + s3.w;
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                g[i0 + e] = gg[e];
-                adam_one(theta, m, v, i0 + e, gg[e], lr, b1, b2, omb1, omb2, bc1, bc2, eps, l, il + e, fwd, bwd,
-                         fwd16, bwd16);
-            }
+        for (int e = 0; e < 4; ++e) {
+            g[i0 + e] = gg[e];
+            adam_one(theta, m, v, i0 + e, gg[e], lr, b1, b2, omb1, omb2, bc1, bc2, eps, l, il + e, fwd, bwd, fwd16,
+                     bwd16);
         }
         return;
     }
-    // first layer (block range 0) and head (range 1), 32 values per block
-    const int nb0 = (pt.n[0] + 31) / 32;
-    const int rb = blockIdx.x - nconv;
-    const int l = (rb < nb0) ? 0 : kLayers;
-    const int il_base = (rb < nb0 ? rb : rb - nb0) * 32;
-    const int p = threadIdx.x & 31, j = threadIdx.x >> 5;
-    const int il = il_base + p;
+    // first layer, then the head
+    const int nb0 = (pt.n[0] + kAdamV0 - 1) / kAdamV0;
+    const int rb = blockIdx.x - kAdamConvBlocks;
+    const bool first = rb < nb0;
+    const int l = first ? 0 : kLayers;
+    const int V = first ? kAdamV0 : kAdamVH;
+    const int G = kBlock / V;
+    const int il = (first ? rb : rb - nb0) * V + (int)threadIdx.x % V;
+    const int j = (int)threadIdx.x / V;
     const bool valid = il < pt.n[l];
     float sum = 0.f;
     if (valid && !ginj) {
         const float* pp = part + pt.poff[l] + il;
-        for (int sp = j; sp < pt.split[l]; sp += 8) sum += pp[(long long)sp * pt.n[l]];
+        for (int sp = j; sp < pt.split[l]; sp += G) sum += pp[(long long)sp * pt.n[l]];
     }
-    red[j][p] = sum;
+    red[threadIdx.x] = sum;
     __syncthreads();
     if (j == 0 && valid) {
         const int i = pt.off[l] + il;
@@ -621,9 +755,8 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, floa
         if (ginj) {
             gi = ginj[i];
         } else {
-            gi = red[0][p];
-#pragma unroll
-            for (int k = 1; k < 8; ++k) gi += red[k][p];
+            gi = red[threadIdx.x];
+            for (int k = 1; k < G; ++k) gi += red[k * V + threadIdx.x];
         }
         g[i] = gi;
         adam_one(theta, m, v, i, gi, lr, b1, b2, omb1, omb2, bc1, bc2, eps, l, il, fwd, bwd, fwd16, bwd16);
@@ -674,18 +807,34 @@ hipError_t launch_pack(const float* theta, const ParamTable& pt, float* fwd, flo
     return hipGetLastError();
 }
 
+template <int C>
+void launch_conv1_c(const float* in, const float* w1, const float* b1, void* out, int bf16, int h, int w,
+                    const DevState* st, hipStream_t s) {
+    const dim3 grid(nblocks((long long)h * w, kPxPerBlock * conv1_unroll<C>()));
+    if (bf16) hipLaunchKernelGGL((k_conv1<C, true>), grid, dim3(kBlock), 0, s, in, w1, b1, out, h, w, st);
+    else hipLaunchKernelGGL((k_conv1<C, false>), grid, dim3(kBlock), 0, s, in, w1, b1, out, h, w, st);
+}
+
 hipError_t launch_conv1(const float* in, int C, const float* w1, const float* b1, void* out, int bf16, int h,
                         int w, const DevState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_conv1, dim3(nblocks((long long)h * w, kBlock / 4)), dim3(kBlock), 0, s, in, C, w1, b1, out, bf16,
-                       h, w, st);
+    if (C == 1) launch_conv1_c<1>(in, w1, b1, out, bf16, h, w, st, s);
+    else if (C == 2) launch_conv1_c<2>(in, w1, b1, out, bf16, h, w, st, s);
+    else launch_conv1_c<3>(in, w1, b1, out, bf16, h, w, st, s);
     return hipGetLastError();
+}
+
+template <int C>
+void launch_wgrad1_c(const float* in, const void* dlt, float* part, int nsplit, int bf16, int h, int w,
+                     const DevState* st, hipStream_t s) {
+    if (bf16) hipLaunchKernelGGL((k_wgrad1<C, true>), dim3(nsplit), dim3(kWg1Block), 0, s, in, dlt, part, h, w, st);
+    else hipLaunchKernelGGL((k_wgrad1<C, false>), dim3(nsplit), dim3(kWg1Block), 0, s, in, dlt, part, h, w, st);
 }
 
 hipError_t launch_wgrad1(const float* in, int C, const void* dlt, float* part, int nsplit, int bf16, int h, int w,
                          const DevState* st, hipStream_t s) {
-    if (C == 1) hipLaunchKernelGGL(k_wgrad1<1>, dim3(nsplit), dim3(kBlock), 0, s, in, dlt, bf16, part, h, w, st);
-    else if (C == 2) hipLaunchKernelGGL(k_wgrad1<2>, dim3(nsplit), dim3(kBlock), 0, s, in, dlt, bf16, part, h, w, st);
-    else hipLaunchKernelGGL(k_wgrad1<3>, dim3(nsplit), dim3(kBlock), 0, s, in, dlt, bf16, part, h, w, st);
+    if (C == 1) launch_wgrad1_c<1>(in, dlt, part, nsplit, bf16, h, w, st, s);
+    else if (C == 2) launch_wgrad1_c<2>(in, dlt, part, nsplit, bf16, h, w, st, s);
+    else launch_wgrad1_c<3>(in, dlt, part, nsplit, bf16, h, w, st, s);
     return hipGetLastError();
 }
 
@@ -697,16 +846,24 @@ int head_splits(long long npix) {
 hipError_t launch_head_train(const void* a8, const float* tgt, int C, int k, const float* w9, const float* b9,
                              void* d8, float* part, double* lpart, int nsplit, int bf16, long long npix,
                              DevState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_head_train, dim3(nsplit), dim3(kBlock), 0, s, a8, tgt, C, k, w9, b9, d8, part, lpart,
-                       bf16, npix, st);
+    if (bf16)
+        hipLaunchKernelGGL(k_head_train<true>, dim3(nsplit), dim3(kBlock), 0, s, a8, tgt, C, k, w9, b9, d8, part,
+                           lpart, npix, st);
+    else
+        hipLaunchKernelGGL(k_head_train<false>, dim3(nsplit), dim3(kBlock), 0, s, a8, tgt, C, k, w9, b9, d8, part,
+                           lpart, npix, st);
     return hipGetLastError();
 }
 
 hipError_t launch_head_val(const void* a8, const float* xs, int C, int k, const float* w9, const float* b9,
                            float* y, double* vpart, int nblk, int bf16, long long npix, DevState* st,
                            double* vtrace, hipStream_t s) {
-    hipLaunchKernelGGL(k_head_val, dim3(nblk), dim3(kBlock), 0, s, a8, xs, C, k, w9, b9, y, vpart, bf16, npix, st,
-                       vtrace);
+    if (bf16)
+        hipLaunchKernelGGL(k_head_val<true>, dim3(nblk), dim3(kBlock), 0, s, a8, xs, C, k, w9, b9, y, vpart, npix,
+                           (const DevState*)st);
+    else
+        hipLaunchKernelGGL(k_head_val<false>, dim3(nblk), dim3(kBlock), 0, s, a8, xs, C, k, w9, b9, y, vpart, npix,
+                           (const DevState*)st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(kBlock), 0, s, (const double*)vpart, nblk, npix, st, vtrace);
@@ -736,7 +893,7 @@ hipError_t launch_adam(float* theta, float* m, float* v, float* g, const float* 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const int nblk = (kLayers - 1) * kAdamBPL + (pt.n[0] + 31) / 32 + (pt.n[kLayers] + 31) / 32;
+    const int nblk = kAdamConvBlocks + (pt.n[0] + kAdamV0 - 1) / kAdamV0 + (pt.n[kLayers] + kAdamVH - 1) / kAdamVH + 1;
     hipLaunchKernelGGL(k_adam, dim3(nblk), dim3(kBlock), 0, s, theta, m, v, g, part, ginj, pt,
                        lr, beta1, beta2, eps, fwd, bwd, fwd16, bwd16, lpart, nloss, loss_npix, st);
     return hipGetLastError();

@@ -29,7 +29,7 @@ SYMBOLS = [
     "n2f_server_submit", "n2f_server_step", "n2f_server_poll", "n2f_server_memory", "n2f_server_destroy",
 ]
 SERVER_SIMULATE = 1
-K_CONV_FWD, K_CONV_BWD, K_WGRAD = 0, 1, 2
+K_CONV_FWD, K_BACKWARD, K_ADAM = 0, 1, 2
 
 
 class N2FError(RuntimeError):
