@@ -128,7 +128,7 @@ struct Plan {
     ParamTable pt;
     size_t o_misc, o_xs, o_ds[4], o_net[3], net_bytes;
     size_t n_state, n_theta, n_pack32, n_pack16, n_trace, n_img;
-    size_t o_act, o_dlt, o_part, o_lpart, o_vpart, bytes;
+    size_t o_act, o_mbits, o_dlt, o_part, o_lpart, o_vpart, bytes;
     size_t act_elems, dlt_elems;
     // offsets inside one network's block
     size_t s_state, s_theta, s_m, s_v, s_g, s_fwd, s_bwd, s_fwd16, s_bwd16, s_trace, s_S, s_yb, s_y;
@@ -227,6 +227,8 @@ n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
     q.dlt_elems = (size_t)q.P * kWidth;
     q.o_act = o;
     o += align_up(es * q.act_elems);
+    q.o_mbits = o;      // BF16: ReLU bit masks of stashed layers 0..6, 8 bytes per pixel
+    if (q.bf) o += align_up((size_t)(kLayers - 1) * q.P * 8);
     q.o_dlt = o;
     o += 2 * align_up(es * q.dlt_elems);
     q.o_part = o;
@@ -307,6 +309,7 @@ struct n2f_run {
         float *S, *yb, *y;
     } net[3];
     char* act;
+    char* mbits;       // BF16 ReLU bit masks of the stashed training layers
     char* dlt[2];
     float* part;
     double* lpart;
@@ -335,6 +338,12 @@ n2f_status check_run(n2f_run* r, int net) {
 void* act_layer(n2f_run* r, int i, size_t npix) {
     const size_t es = r->pl.bf ? 2 : 4;
     return r->act + es * (size_t)i * npix * kWidth;
+}
+
+// ReLU bit mask of stashed training layer i (BF16 runs, i < 7), else NULL.
+uint16_t* mask_layer(n2f_run* r, int i, size_t npix) {
+    if (!r->pl.bf || i >= kLayers - 1) return nullptr;
+    return reinterpret_cast<uint16_t*>(r->mbits) + (size_t)i * npix * 4;
 }
 
 // Images and shapes of training pair `pair`.
@@ -370,11 +379,11 @@ n2f_status enqueue_train_step(n2f_run* r, int k, int pair) {
         return bf ? (const void*)(N.bwd16 + (size_t)(l - 1) * kPackN) : (const void*)(N.bwd + (size_t)(l - 1) * kPackN);
     };
     // forward with stash: act layer i holds a_{i+1}
-    N2F_HIP(launch_conv1(in, pl.C, Wl(0), Bl(0), act_layer(r, 0, npix), bf, h, w, N.st, s));
+    N2F_HIP(launch_conv1(in, pl.C, Wl(0), Bl(0), act_layer(r, 0, npix), mask_layer(r, 0, npix), bf, h, w, N.st, s));
     N2F_HIP(timed(N2F_K_CONV_FWD, kLayers - 1, (long long)npix, s, [&]() -> hipError_t {
         for (int l = 1; l < kLayers; ++l) {
-            hipError_t e = launch_conv_fwd(act_layer(r, l - 1, npix), fwdpk(l), Bl(l), act_layer(r, l, npix), bf, h, w,
-                                           N.st, s);
+            hipError_t e = launch_conv_fwd(act_layer(r, l - 1, npix), fwdpk(l), Bl(l), act_layer(r, l, npix),
+                                           mask_layer(r, l, npix), bf, h, w, N.st, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -390,7 +399,8 @@ n2f_status enqueue_train_step(n2f_run* r, int k, int pair) {
             hipError_t e = launch_wgrad(act_layer(r, l - 1, npix), r->dlt[cur], r->part + pt.poff[l], pt.split[l], bf,
                                         h, w, N.st, s);
             if (e != hipSuccess) return e;
-            e = launch_conv_bwd(r->dlt[cur], bwdpk(l), act_layer(r, l - 1, npix), r->dlt[1 - cur], bf, h, w, N.st, s);
+            const void* mask = bf ? (const void*)mask_layer(r, l - 1, npix) : act_layer(r, l - 1, npix);
+            e = launch_conv_bwd(r->dlt[cur], bwdpk(l), mask, r->dlt[1 - cur], bf, h, w, N.st, s);
             if (e != hipSuccess) return e;
             cur = 1 - cur;
         }
@@ -414,12 +424,12 @@ n2f_status enqueue_validate(n2f_run* r, int k) {
     hipStream_t s = r->stream;
     auto buf = [&](int i) { return act_layer(r, i & 1, npix); };
     auto Bl = [&](int l) { return N.theta + pt.off[l] + kTaps * pt.cin[l] * kWidth; };
-    N2F_HIP(launch_conv1(r->xs, pl.C, N.theta + pt.off[0], Bl(0), buf(0), bf, pl.H, pl.W, N.st, s));
+    N2F_HIP(launch_conv1(r->xs, pl.C, N.theta + pt.off[0], Bl(0), buf(0), nullptr, bf, pl.H, pl.W, N.st, s));
     N2F_HIP(timed(N2F_K_CONV_FWD, kLayers - 1, (long long)npix, s, [&]() -> hipError_t {
         for (int l = 1; l < kLayers; ++l) {
             const void* pk = bf ? (const void*)(N.fwd16 + (size_t)(l - 1) * kPackN)
                                 : (const void*)(N.fwd + (size_t)(l - 1) * kPackN);
-            hipError_t e = launch_conv_fwd(buf(l - 1), pk, Bl(l), buf(l), bf, pl.H, pl.W, N.st, s);
+            hipError_t e = launch_conv_fwd(buf(l - 1), pk, Bl(l), buf(l), nullptr, bf, pl.H, pl.W, N.st, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -597,6 +607,7 @@ n2f_status n2f_run_create(n2f_run** out, const float* d_in, int H, int W, int C,
         r->host_epochs[k] = 0;
     }
     r->act = b + pl.o_act;
+    r->mbits = b + pl.o_mbits;
     const size_t es = pl.bf ? 2 : 4;
     r->dlt[0] = b + pl.o_dlt;
     r->dlt[1] = b + pl.o_dlt + align_up(es * pl.dlt_elems);

@@ -235,17 +235,17 @@ __device__ __forceinline__ bf16x8 shift_in_row(bf16x8 src, bf16x8 last) {
     return __builtin_bit_cast(bf16x8, d);
 }
 
-// a > 0 for a BF16 value: sign clear and not zero.
-__device__ __forceinline__ uint32_t keep_positive(uint32_t val, uint32_t mm) {
-    uint32_t keep = 0;
-    if ((mm & 0x8000u) == 0 && (mm & 0x7fffu) != 0) keep |= 0xffffu;
-    if ((mm & 0x80000000u) == 0 && (mm & 0x7fff0000u) != 0) keep |= 0xffff0000u;
-    return val & keep;
-}
+// BF16 bit pattern b (low 16 bits) is > 0: sign clear and not zero.
+__device__ __forceinline__ bool bf16_pos(uint32_t b) { return (b & 0x8000u) == 0u && (b & 0x7fffu) != 0u; }
 
+// ReLU bit masks of BF16 activations: 64 bits per pixel, bit 16 g + 4 j + r
+// for channel 16 j + 4 g + r (g, r < 4), so each of the four lanes that hold
+// a pixel's MFMA outputs owns one 16-bit word.  Bit set = the stored BF16
+// value is > 0.  MODE 0 writes them (when mbits is given), MODE 1 applies
+// them to the data gradient.
 template <int MODE>
 __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
-                                                   const float* __restrict__ bias, const uint16_t* __restrict__ mask,
+                                                   const float* __restrict__ bias, uint16_t* __restrict__ mbits,
                                                    uint16_t* __restrict__ out, int h, int w, const DevState* st) {
     if (finished(st)) return;
     __shared__ __attribute__((aligned(16))) uint16_t sw[kTaps * kWidth * kWidth];
@@ -254,8 +254,13 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
     const int lane = tid & 63, wq = gt >> 6;
     const int g = lane >> 4, n = lane & 15;
     uint16_t* halo = hb[grp];
-    for (int i = tid; i < kTaps * kWidth * kWidth / 8; i += 512)
-        reinterpret_cast<uint4*>(sw)[i] = reinterpret_cast<const uint4*>(wpk)[i];
+    // weights: all nine 16-byte loads of a thread in flight together with
+    // the first halo's loads, then both go to LDS (one memory latency)
+    constexpr int kWChunks = kTaps * kWidth * kWidth / 8 / 512;
+    static_assert(kWChunks * 512 * 8 == kTaps * kWidth * kWidth, "weight chunks");
+    uint4 wr[kWChunks];
+#pragma unroll
+    for (int k = 0; k < kWChunks; ++k) wr[k] = reinterpret_cast<const uint4*>(wpk)[tid + 512 * k];
     const int tiles_x = (w + kTile - 1) / kTile, tiles_y = (h + kTile - 1) / kTile;
     const int ntiles = tiles_x * tiles_y;
     const int stride = 2 * gridDim.x;
@@ -277,6 +282,8 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
         }
     };
     if (iters > 0) fetch(2 * blockIdx.x + grp);
+#pragma unroll
+    for (int k = 0; k < kWChunks; ++k) reinterpret_cast<uint4*>(sw)[tid + 512 * k] = wr[k];
 
     for (int k = 0; k < iters; ++k) {
         const int tile = 2 * blockIdx.x + grp + k * stride;
@@ -344,11 +351,21 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                     for (int r = 0; r < 4; ++r) bv[j][r] = bias[16 * j + 4 * g + r];
             }
             const int gx = x0 + n;
+            // the data gradient's ReLU mask words of this lane's 4 pixels
+            uint32_t mk[4];
+            if (MODE == 1) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int gy = y0 + 4 * wq + i;
+                    mk[i] = (gy < h && gx < w) ? mbits[((long long)gy * w + gx) * 4 + g] : 0u;
+                }
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int gy = y0 + 4 * wq + i;
                 if (gy >= h || gx >= w) continue;
                 const long long base = ((long long)gy * w + gx) * kWidth + 4 * g;
+                uint32_t word = 0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     float v[4];
@@ -357,12 +374,18 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                     uint2 o = make_uint2((uint32_t)bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[1]) << 16),
                                          (uint32_t)bf16_rne(v[2]) | ((uint32_t)bf16_rne(v[3]) << 16));
                     if (MODE == 1) {
-                        const uint2 mk = *reinterpret_cast<const uint2*>(mask + base + 16 * j);
-                        o.x = keep_positive(o.x, mk.x);
-                        o.y = keep_positive(o.y, mk.y);
+                        const uint32_t m = mk[i] >> (4 * j);
+                        o.x &= ((m & 1u) ? 0x0000ffffu : 0u) | ((m & 2u) ? 0xffff0000u : 0u);
+                        o.y &= ((m & 4u) ? 0x0000ffffu : 0u) | ((m & 8u) ? 0xffff0000u : 0u);
+                    } else {
+                        word |= (bf16_pos(o.x & 0xffffu) ? 1u : 0u) << (4 * j);
+                        word |= (bf16_pos(o.x >> 16) ? 2u : 0u) << (4 * j);
+                        word |= (bf16_pos(o.y & 0xffffu) ? 4u : 0u) << (4 * j);
+                        word |= (bf16_pos(o.y >> 16) ? 8u : 0u) << (4 * j);
                     }
                     *reinterpret_cast<uint2*>(out + base + 16 * j) = o;
                 }
+                if (MODE == 0 && mbits) mbits[((long long)gy * w + gx) * 4 + g] = (uint16_t)word;
             }
         }
         __syncthreads();   // the next tile's halo overwrites this buffer
@@ -569,12 +592,12 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
 
 }  // namespace
 
-hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, void* out, int bf16, int h, int w,
-                           const DevState* st, hipStream_t s) {
+hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, void* out, uint16_t* mbits, int bf16,
+                           int h, int w, const DevState* st, hipStream_t s) {
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
     if (bf16) {
-        hipLaunchKernelGGL(k_conv_bf16<0>, dim3(conv_bf16_blocks(h, w)), dim3(512), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
-                           (const uint16_t*)nullptr, (uint16_t*)out, h, w, st);
+        hipLaunchKernelGGL(k_conv_bf16<0>, dim3(conv_bf16_blocks(h, w)), dim3(512), 0, s, (const uint16_t*)in,
+                           (const uint16_t*)wpk, bias, mbits, (uint16_t*)out, h, w, st);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_conv_f32<0>, grid, dim3(256), 0, s, (const float*)in, (const float*)wpk, bias,
@@ -586,8 +609,9 @@ hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, v
                            const DevState* st, hipStream_t s) {
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
     if (bf16) {
-        hipLaunchKernelGGL(k_conv_bf16<1>, dim3(conv_bf16_blocks(h, w)), dim3(512), 0, s, (const uint16_t*)dlt, (const uint16_t*)wpk,
-                           (const float*)nullptr, (const uint16_t*)mask, (uint16_t*)out, h, w, st);
+        hipLaunchKernelGGL(k_conv_bf16<1>, dim3(conv_bf16_blocks(h, w)), dim3(512), 0, s, (const uint16_t*)dlt,
+                           (const uint16_t*)wpk, (const float*)nullptr, (uint16_t*)const_cast<void*>(mask),
+                           (uint16_t*)out, h, w, st);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_conv_f32<1>, grid, dim3(256), 0, s, (const float*)dlt, (const float*)wpk,

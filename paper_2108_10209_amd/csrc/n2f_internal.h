@@ -71,10 +71,14 @@ hipError_t launch_prepare(const float* x, int H, int W, int C, const float* lohi
 hipError_t launch_init_state(DevState* st, int patience, int max_epochs, int fixed_epochs, hipStream_t s);
 hipError_t launch_pack(const float* theta, const ParamTable& pt, float* fwd, float* bwd,
                        uint16_t* fwd16, uint16_t* bwd16, hipStream_t s);
-hipError_t launch_conv1(const float* in, int C, const float* w1, const float* b1, void* out, int bf16,
-                        int h, int w, const DevState* st, hipStream_t s);
-hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, void* out, int bf16,
-                           int h, int w, const DevState* st, hipStream_t s);
+// BF16 runs keep a ReLU bit mask per stashed activation (8 bytes per pixel,
+// see k_conv_bf16); the forward launchers write it when `mbits` is given and
+// the BF16 data gradient takes it as `mask`.  FP32 runs pass mbits = NULL
+// and give the data gradient the FP32 activation itself as `mask`.
+hipError_t launch_conv1(const float* in, int C, const float* w1, const float* b1, void* out, uint16_t* mbits,
+                        int bf16, int h, int w, const DevState* st, hipStream_t s);
+hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, void* out, uint16_t* mbits,
+                           int bf16, int h, int w, const DevState* st, hipStream_t s);
 hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, void* out, int bf16,
                            int h, int w, const DevState* st, hipStream_t s);
 int wgrad_splits(int h, int w, int bf16);

@@ -228,12 +228,14 @@ __global__ __launch_bounds__(kBlock) void k_pack(const float* __restrict__ theta
 
 // ---------------------------------------------------------------------------
 // First 3x3 conv (C <= 3 input channels, K = 9C is too short for MFMA) with
-// bias and ReLU.  Thread = (pixel slot, group of 8 output channels): the
-// eight lanes of a pixel write its 64 channels as one contiguous row, so a
-// wave stores 8 whole pixels per instruction.  Each thread first issues the
-// input-tap loads of all its U pixels (lane-uniform within a pixel, served
-// by the cache), then computes and stores them, so one memory latency covers
-// U pixels.
+// bias and ReLU.  Thread = (pixel slot, lane c of the pixel's 8): it owns
+// channels 16 j + 4 g + r for g = c / 2, j = 2 (c % 2) + {0, 1}, r < 4, so
+// the eight lanes of a pixel write its 64 channels (two 4-channel stores
+// each) and, for BF16 training runs, lane c writes byte c of the pixel's
+// ReLU bit mask (bit 16 g + 4 j + r, the layout of the BF16 3x3 kernels).
+// Each thread first issues the input-tap loads of all its U pixels
+// (lane-uniform within a pixel, served by the cache), then computes and
+// stores them, so one memory latency covers U pixels.
 // ---------------------------------------------------------------------------
 constexpr int kPxPerBlock = kBlock / 8;
 
@@ -242,15 +244,16 @@ constexpr int conv1_unroll() { return C == 1 ? 4 : (C == 2 ? 2 : 1); }
 
 template <int C, bool BF>
 __global__ __launch_bounds__(kBlock) void k_conv1(const float* __restrict__ in, const float* __restrict__ w1,
-                                                  const float* __restrict__ b1, void* __restrict__ out, int h, int w,
-                                                  const DevState* st) {
+                                                  const float* __restrict__ b1, void* __restrict__ out,
+                                                  uint8_t* __restrict__ mbits, int h, int w, const DevState* st) {
     if (finished(st)) return;
     constexpr int U = conv1_unroll<C>();
     __shared__ __attribute__((aligned(16))) float sw[kTaps * C * kWidth + kWidth];
     for (int i = threadIdx.x; i < kTaps * C * kWidth; i += kBlock) sw[i] = w1[i];
     for (int i = threadIdx.x; i < kWidth; i += kBlock) sw[kTaps * C * kWidth + i] = b1[i];
     const long long npix = (long long)h * w;
-    const int cg = threadIdx.x & 7;
+    const int cl = threadIdx.x & 7;
+    const int c0 = 32 * (cl & 1) + 4 * (cl >> 1), c1 = c0 + 16;
     const long long pbase = (long long)blockIdx.x * (kPxPerBlock * U) + (threadIdx.x >> 3);
     float xv[U][kTaps * C];
 #pragma unroll
@@ -270,30 +273,36 @@ __global__ __launch_bounds__(kBlock) void k_conv1(const float* __restrict__ in, 
     for (int u = 0; u < U; ++u) {
         const long long p = pbase + kPxPerBlock * u;
         if (p >= npix) break;
-        float acc[8];
-        {
-            const float4* bb = reinterpret_cast<const float4*>(sw + kTaps * C * kWidth + 8 * cg);
-            const float4 v0 = bb[0], v1 = bb[1];
-            acc[0] = v0.x; acc[1] = v0.y; acc[2] = v0.z; acc[3] = v0.w;
-            acc[4] = v1.x; acc[5] = v1.y; acc[6] = v1.z; acc[7] = v1.w;
-        }
+        float4 a0 = *reinterpret_cast<const float4*>(sw + kTaps * C * kWidth + c0);
+        float4 a1 = *reinterpret_cast<const float4*>(sw + kTaps * C * kWidth + c1);
 #pragma unroll
         for (int tc = 0; tc < kTaps * C; ++tc) {
             const float v = xv[u][tc];
-            const float4* ww = reinterpret_cast<const float4*>(sw + tc * kWidth + 8 * cg);
-            const float4 u0 = ww[0], u1 = ww[1];
-            acc[0] = fmaf(v, u0.x, acc[0]);
-            acc[1] = fmaf(v, u0.y, acc[1]);
-            acc[2] = fmaf(v, u0.z, acc[2]);
-            acc[3] = fmaf(v, u0.w, acc[3]);
-            acc[4] = fmaf(v, u1.x, acc[4]);
-            acc[5] = fmaf(v, u1.y, acc[5]);
-            acc[6] = fmaf(v, u1.z, acc[6]);
-            acc[7] = fmaf(v, u1.w, acc[7]);
+            const float4 u0 = *reinterpret_cast<const float4*>(sw + tc * kWidth + c0);
+            const float4 u1 = *reinterpret_cast<const float4*>(sw + tc * kWidth + c1);
+            a0.x = fmaf(v, u0.x, a0.x);
+            a0.y = fmaf(v, u0.y, a0.y);
+            a0.z = fmaf(v, u0.z, a0.z);
+            a0.w = fmaf(v, u0.w, a0.w);
+            a1.x = fmaf(v, u1.x, a1.x);
+            a1.y = fmaf(v, u1.y, a1.y);
+            a1.z = fmaf(v, u1.z, a1.z);
+            a1.w = fmaf(v, u1.w, a1.w);
         }
+        a0 = make_float4(fmaxf(a0.x, 0.f), fmaxf(a0.y, 0.f), fmaxf(a0.z, 0.f), fmaxf(a0.w, 0.f));
+        a1 = make_float4(fmaxf(a1.x, 0.f), fmaxf(a1.y, 0.f), fmaxf(a1.z, 0.f), fmaxf(a1.w, 0.f));
+        store4(out, p * kWidth + c0, a0, BF);
+        store4(out, p * kWidth + c1, a1, BF);
+        if (BF && mbits) {
+            const float v[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+            uint32_t byte = 0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) acc[e] = fmaxf(acc[e], 0.f);
-        store8<BF>(out, p * kWidth + 8 * cg, acc);
+            for (int e = 0; e < 8; ++e) {
+                const uint16_t bb = f32_to_bf16_rne(v[e]);
+                if ((bb & 0x8000u) == 0 && (bb & 0x7fffu) != 0) byte |= 1u << e;    // stored value > 0
+            }
+            mbits[p * 8 + cl] = (uint8_t)byte;
+        }
     }
 }
 
@@ -808,18 +817,19 @@ hipError_t launch_pack(const float* theta, const ParamTable& pt, float* fwd, flo
 }
 
 template <int C>
-void launch_conv1_c(const float* in, const float* w1, const float* b1, void* out, int bf16, int h, int w,
-                    const DevState* st, hipStream_t s) {
+void launch_conv1_c(const float* in, const float* w1, const float* b1, void* out, uint8_t* mbits, int bf16, int h,
+                    int w, const DevState* st, hipStream_t s) {
     const dim3 grid(nblocks((long long)h * w, kPxPerBlock * conv1_unroll<C>()));
-    if (bf16) hipLaunchKernelGGL((k_conv1<C, true>), grid, dim3(kBlock), 0, s, in, w1, b1, out, h, w, st);
-    else hipLaunchKernelGGL((k_conv1<C, false>), grid, dim3(kBlock), 0, s, in, w1, b1, out, h, w, st);
+    if (bf16) hipLaunchKernelGGL((k_conv1<C, true>), grid, dim3(kBlock), 0, s, in, w1, b1, out, mbits, h, w, st);
+    else hipLaunchKernelGGL((k_conv1<C, false>), grid, dim3(kBlock), 0, s, in, w1, b1, out, mbits, h, w, st);
 }
 
-hipError_t launch_conv1(const float* in, int C, const float* w1, const float* b1, void* out, int bf16, int h,
-                        int w, const DevState* st, hipStream_t s) {
-    if (C == 1) launch_conv1_c<1>(in, w1, b1, out, bf16, h, w, st, s);
-    else if (C == 2) launch_conv1_c<2>(in, w1, b1, out, bf16, h, w, st, s);
-    else launch_conv1_c<3>(in, w1, b1, out, bf16, h, w, st, s);
+hipError_t launch_conv1(const float* in, int C, const float* w1, const float* b1, void* out, uint16_t* mbits,
+                        int bf16, int h, int w, const DevState* st, hipStream_t s) {
+    uint8_t* mb = reinterpret_cast<uint8_t*>(mbits);
+    if (C == 1) launch_conv1_c<1>(in, w1, b1, out, mb, bf16, h, w, st, s);
+    else if (C == 2) launch_conv1_c<2>(in, w1, b1, out, mb, bf16, h, w, st, s);
+    else launch_conv1_c<3>(in, w1, b1, out, mb, bf16, h, w, st, s);
     return hipGetLastError();
 }
 

@@ -43,7 +43,8 @@ def bf16_cfg(**kw):
     return n2f.default_config(precision=n2f.BF16, **kw)
 
 
-@pytest.mark.parametrize("C,H,W", [(1, 64, 64), (3, 40, 33), (1, 45, 70)])
+# 512x512 is the benchmark's image size, in the launch configuration it times
+@pytest.mark.parametrize("C,H,W", [(1, 64, 64), (3, 40, 33), (1, 45, 70), (1, 512, 512)])
 def test_bf16_validation_forward(C, H, W):
     say("bf16 validate", C, H, W)
     clean = synth.blobs(H, W, 1, C=C)
@@ -59,7 +60,7 @@ def test_bf16_validation_forward(C, H, W):
         assert rel(y, y_or) < TOL and abs(v - v_or) / v_or < TOL
 
 
-@pytest.mark.parametrize("C,H,W,pre", [(1, 64, 64, 0), (1, 64, 64, 6), (3, 36, 40, 2), (1, 50, 97, 1)])
+@pytest.mark.parametrize("C,H,W,pre", [(1, 64, 64, 0), (1, 64, 64, 6), (3, 36, 40, 2), (1, 50, 97, 1), (1, 512, 512, 1)])
 def test_bf16_train_step_teacher_forced(C, H, W, pre):
     say("bf16 step", C, H, W, pre)
     clean = synth.blobs(H, W, 2, C=C)
