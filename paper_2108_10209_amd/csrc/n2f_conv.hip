@@ -216,7 +216,7 @@ __device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float(((u
 // 8-byte store.  The activation fragment of a tile row is read once per
 // (dy, channel half): the dx = 1 and dx = 2 fragments are the same data
 // moved one lane down each 16-lane DPP row, with the one pixel that enters
-// at the row end read from LDS by the row's last lane alone.
+// at the row end taken from a broadcast LDS read.
 constexpr int kHaloPix = kHalo * kHalo;               // 324 staged pixels
 constexpr int kHaloChunks = kHaloPix * 8;             // 16-byte chunks per halo
 constexpr int kPf = (kHaloChunks + 255) / 256;        // chunks each thread prefetches
@@ -307,18 +307,15 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
             for (int kc = 0; kc < 2; ++kc) {
                 // activation fragments of tile rows 4wq+i at dx = 0 (lane n: pixel n),
                 // and the pixels 16, 17 that enter at the row end for dx = 1, 2
-                // (only the last lane of each row reads the entering pixels)
+                // (broadcast reads: an exec-masked read for the last lane alone
+                // splits the unrolled MFMA block into basic blocks and measured slower)
                 bf16x8 a0[4], e1[4], e2[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int prow = (4 * wq + i + dy) * kHalo;
                     a0[i] = *reinterpret_cast<const bf16x8*>(halo + swz(prow + n, 4 * kc + g));
-                    e1[i] = bf16x8{};
-                    e2[i] = bf16x8{};
-                    if (n == 15) {
-                        e1[i] = *reinterpret_cast<const bf16x8*>(halo + swz(prow + 16, 4 * kc + g));
-                        e2[i] = *reinterpret_cast<const bf16x8*>(halo + swz(prow + 17, 4 * kc + g));
-                    }
+                    e1[i] = *reinterpret_cast<const bf16x8*>(halo + swz(prow + 16, 4 * kc + g));
+                    e2[i] = *reinterpret_cast<const bf16x8*>(halo + swz(prow + 17, 4 * kc + g));
                 }
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) {
