@@ -247,7 +247,10 @@ template <int MODE>
 __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
                                                    const float* __restrict__ bias, uint16_t* __restrict__ mbits,
                                                    uint16_t* __restrict__ out, int h, int w, const DevState* st) {
-    if (finished(st)) return;
+    // the stop flag (st is never NULL here) is read first but tested only
+    // once the weight and halo loads are in flight, so its memory latency
+    // hides under theirs
+    const int stop = st->done;
     __shared__ __attribute__((aligned(16))) uint16_t sw[kTaps * kWidth * kWidth];
     __shared__ __attribute__((aligned(16))) uint16_t hb[2][kHaloPix * kWidth];
     const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
@@ -282,6 +285,8 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
         }
     };
     if (iters > 0) fetch(2 * blockIdx.x + grp);
+    asm volatile("" ::: "memory");   // keeps those loads ahead of the test
+    if (stop) return;
 #pragma unroll
     for (int k = 0; k < kWChunks; ++k) reinterpret_cast<uint4*>(sw)[tid + 512 * k] = wr[k];
 
@@ -480,7 +485,7 @@ __device__ __forceinline__ void wg_store(const uint4 (&pf)[kWgPf], uint16_t* buf
 
 __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__ src, const uint16_t* __restrict__ dlt,
                                                     float* __restrict__ part, int h, int w, const DevState* st) {
-    if (finished(st)) return;
+    const int stop = st->done;   // tested once the first tile's loads are in flight
     __shared__ __attribute__((aligned(16))) unsigned char lds[kWgLdsBytes];
     __shared__ float dbs[64][kWidth];
     uint16_t* bufs = reinterpret_cast<uint16_t*>(lds);
@@ -509,10 +514,10 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
     float db[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
     uint4 pf[kWgPf];
-    if (nmine > 0) {
-        wg_load(pf, src, dlt, sp, tiles_x, q, h, w);
-        wg_store(pf, bufs);
-    }
+    if (nmine > 0) wg_load(pf, src, dlt, sp, tiles_x, q, h, w);
+    asm volatile("" ::: "memory");   // keeps those loads ahead of the test
+    if (stop) return;
+    if (nmine > 0) wg_store(pf, bufs);
     __syncthreads();
     // this wave's pixels: k0 = 32 wv + 8 g + r/4 and k0 + 4 of the tile
     const int rp = r >> 2, rc = 4 * (r & 3);

@@ -246,7 +246,7 @@ template <int C, bool BF>
 __global__ __launch_bounds__(kBlock) void k_conv1(const float* __restrict__ in, const float* __restrict__ w1,
                                                   const float* __restrict__ b1, void* __restrict__ out,
                                                   uint8_t* __restrict__ mbits, int h, int w, const DevState* st) {
-    if (finished(st)) return;
+    const int stop = st->done;   // tested once the loads are in flight
     constexpr int U = conv1_unroll<C>();
     __shared__ __attribute__((aligned(16))) float sw[kTaps * C * kWidth + kWidth];
     for (int i = threadIdx.x; i < kTaps * C * kWidth; i += kBlock) sw[i] = w1[i];
@@ -268,6 +268,8 @@ __global__ __launch_bounds__(kBlock) void k_conv1(const float* __restrict__ in, 
             for (int c = 0; c < C; ++c) xv[u][t * C + c] = inside ? in[((long long)yy * w + xx) * C + c] : 0.f;
         }
     }
+    asm volatile("" ::: "memory");
+    if (stop) return;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -320,7 +322,7 @@ constexpr int kWg1Block = 512;
 template <int C, bool BF>
 __global__ __launch_bounds__(kWg1Block) void k_wgrad1(const float* __restrict__ in, const void* __restrict__ dlt,
                                                    float* __restrict__ part, int h, int w, const DevState* st) {
-    if (finished(st)) return;
+    const int stop = st->done;                   // tested after the loads of the pixel loop
     constexpr int G = (C == 1) ? 8 : 4;          // channels per lane
     constexpr int LPP = kWidth / G;              // lanes per pixel
     constexpr int SLOTS = kWg1Block / LPP;
@@ -374,6 +376,8 @@ __global__ __launch_bounds__(kWg1Block) void k_wgrad1(const float* __restrict__ 
             for (int e = 0; e < G; ++e) acc[kTaps * C][e] += d[u][e];
         }
     }
+    asm volatile("" ::: "memory");
+    if (stop) return;
     // slots of one wave: lanes cg, cg + LPP, ... hold the same channels
 #pragma unroll
     for (int off = LPP; off < 64; off <<= 1)
@@ -410,7 +414,9 @@ __global__ __launch_bounds__(kBlock) void k_head_train(const void* __restrict__ 
                                                        const float* __restrict__ b9, void* __restrict__ d8,
                                                        float* __restrict__ part, double* __restrict__ lpart,
                                                        long long npix, DevState* st) {
-    if (finished(st)) return;
+    // the stop flag is tested after the pixel loop, so its load overlaps the
+    // loop's; a stopped network's delta writes are never read
+    const int stop = st->done;
     __shared__ float sacc[kPxPerBlock][kWidth + 1];
     __shared__ double sl[kPxPerBlock];
     const int q = threadIdx.x & 7, ps = threadIdx.x >> 3;
@@ -468,6 +474,8 @@ __global__ __launch_bounds__(kBlock) void k_head_train(const void* __restrict__ 
             }
         }
     }
+    asm volatile("" ::: "memory");
+    if (stop) return;
 #pragma unroll
     for (int e = 0; e < 8; ++e) sacc[ps][8 * q + e] = g[e];
     if (q == 0) {
