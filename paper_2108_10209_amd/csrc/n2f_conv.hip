@@ -485,12 +485,15 @@ __device__ __forceinline__ void wg_store(const uint4 (&pf)[kWgPf], uint16_t* buf
 
 __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__ src, const uint16_t* __restrict__ dlt,
                                                     float* __restrict__ part, int h, int w, const DevState* st) {
-    const int stop = st->done;   // tested once the first tile's loads are in flight
+    const int stop = st->done;   // tested once the first tiles' loads are in flight
     __shared__ __attribute__((aligned(16))) unsigned char lds[kWgLdsBytes];
     __shared__ float dbs[64][kWidth];
     uint16_t* bufs = reinterpret_cast<uint16_t*>(lds);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int g = lane >> 4, r = lane & 15;
+    // wave wv: pixels 64 (wv / 2) .. + 63 of each tile (two K steps) and
+    // output-channel blocks 2 (wv % 2), 2 (wv % 2) + 1
+    const int pr = wv >> 1, oh = wv & 1;
     const int nsplit = gridDim.x / 4;
     const int b = blockIdx.x;
     int sp, q;
@@ -505,29 +508,32 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
     const int ntiles = tiles_x * tiles_y;
     const int nmine = sp < ntiles ? (ntiles - sp + nsplit - 1) / nsplit : 0;
 
-    floatx4 acc[9][4];
+    floatx4 acc[9][2];
 #pragma unroll
     for (int i = 0; i < 9; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     // bias gradient: thread = (8-channel chunk tid & 7, pixels 4 (tid >> 3) .. +3)
     float db[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
-    uint4 pf[kWgPf];
-    if (nmine > 0) wg_load(pf, src, dlt, sp, tiles_x, q, h, w);
+    // tiles flow global -> registers -> LDS two tiles ahead: while tile it is
+    // multiplied from one LDS buffer, tile it + 1 waits in one register set
+    // and tile it + 2 loads into the other
+    uint4 pfa[kWgPf], pfb[kWgPf];
+    if (nmine > 0) wg_load(pfa, src, dlt, sp, tiles_x, q, h, w);
+    if (nmine > 1) wg_load(pfb, src, dlt, sp + nsplit, tiles_x, q, h, w);
     asm volatile("" ::: "memory");   // keeps those loads ahead of the test
     if (stop) return;
-    if (nmine > 0) wg_store(pf, bufs);
+    if (nmine > 0) wg_store(pfa, bufs);
     __syncthreads();
-    // this wave's pixels: k0 = 32 wv + 8 g + r/4 and k0 + 4 of the tile
     const int rp = r >> 2, rc = 4 * (r & 3);
-    const int k0 = 32 * wv + 8 * g + rp, k1 = k0 + 4;
-    const int py0 = k0 >> 4, px0 = k0 & 15, py1 = k1 >> 4, px1 = k1 & 15;
-    for (int it = 0; it < nmine; ++it) {
+
+    // multiply tile `it` from LDS; `ld` takes the loads of tile it + 2 (it
+    // held tile it, already in LDS); `sv` holds tile it + 1, stored at the end
+    auto step = [&](uint4 (&ld)[kWgPf], uint4 (&sv)[kWgPf], int it) __attribute__((always_inline)) {
         const uint16_t* halo = bufs + (it & 1) * kWgBufE;
         const uint16_t* dt = halo + kWgHaloE;
-        const bool more = it + 1 < nmine;
-        if (more) wg_load(pf, src, dlt, sp + (it + 1) * nsplit, tiles_x, q, h, w);
+        if (it + 2 < nmine) wg_load(ld, src, dlt, sp + (it + 2) * nsplit, tiles_x, q, h, w);
         if (q == 0) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -541,23 +547,36 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
                 }
             }
         }
-        bf16x8 bfr[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            bfr[j] = tr16_frag(dt + k0 * kWgPSB + 16 * j + rc, dt + k1 * kWgPSB + 16 * j + rc);
+        for (int ks = 0; ks < 2; ++ks) {
+            // pixels of K step ks: k0 = 64 pr + 32 ks + 8 g + r/4 and k0 + 4
+            const int k0 = 64 * pr + 32 * ks + 8 * g + rp, k1 = k0 + 4;
+            const int py0 = k0 >> 4, px0 = k0 & 15, py1 = k1 >> 4, px1 = k1 & 15;
+            bf16x8 bfr[2];
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t) {
-            const int dy = t / 3, dx = t - 3 * (t / 3);
-            const bf16x8 a = tr16_frag(halo + ((py0 + dy) * kHalo + px0 + dx) * kWgPSA + rc,
-                                       halo + ((py1 + dy) * kHalo + px1 + dx) * kWgPSA + rc);
+            for (int j = 0; j < 2; ++j) {
+                const int cb = 16 * (2 * oh + j) + rc;
+                bfr[j] = tr16_frag(dt + k0 * kWgPSB + cb, dt + k1 * kWgPSB + cb);
+            }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[j], acc[t][j], 0, 0, 0);
+            for (int t = 0; t < kTaps; ++t) {
+                const int dy = t / 3, dx = t - 3 * (t / 3);
+                const bf16x8 a = tr16_frag(halo + ((py0 + dy) * kHalo + px0 + dx) * kWgPSA + rc,
+                                           halo + ((py1 + dy) * kHalo + px1 + dx) * kWgPSA + rc);
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[j], acc[t][j], 0, 0, 0);
+            }
         }
-        if (more) wg_store(pf, bufs + ((it + 1) & 1) * kWgBufE);
+        if (it + 1 < nmine) wg_store(sv, bufs + ((it + 1) & 1) * kWgBufE);
         __syncthreads();
+    };
+    for (int it = 0; it < nmine; it += 2) {
+        step(pfa, pfb, it);
+        if (it + 1 < nmine) step(pfb, pfa, it + 1);
     }
 
-    // sum the 8 waves in order, three taps at a time
+    // sum the 4 waves of each channel half in order, three taps at a time
     float* red = reinterpret_cast<float*>(lds);
     float* pp = part + (long long)sp * kConvN;
 #pragma unroll
@@ -565,16 +584,18 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
 #pragma unroll
         for (int tt = 0; tt < 3; ++tt)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) red[(wv * 12 + tt * 4 + j) * kWgRedS + e * 64 + lane] = acc[3 * pass + tt][j][e];
+                for (int e = 0; e < 4; ++e)
+                    red[(wv * 6 + tt * 2 + j) * kWgRedS + e * 64 + lane] = acc[3 * pass + tt][j][e];
         __syncthreads();
         for (int o = tid; o < 3 * 16 * kWidth; o += 512) {
             const int tt = o >> 10, cil = (o >> 6) & 15, co = o & 63;
-            const int idx = (tt * 4 + (co >> 4)) * kWgRedS + (cil & 3) * 64 + 16 * (cil >> 2) + (co & 15);
-            float sum = red[idx];
+            const int cbk = co >> 4, ohh = cbk >> 1, jj = cbk & 1;
+            const int idx = (tt * 2 + jj) * kWgRedS + (cil & 3) * 64 + 16 * (cil >> 2) + (co & 15);
+            float sum = red[(2 * 0 + ohh) * 6 * kWgRedS + idx];
 #pragma unroll
-            for (int k = 1; k < 8; ++k) sum += red[k * 12 * kWgRedS + idx];
+            for (int k = 1; k < 4; ++k) sum += red[(2 * k + ohh) * 6 * kWgRedS + idx];
             pp[((3 * pass + tt) * kWidth + 16 * q + cil) * kWidth + co] = sum;
         }
         __syncthreads();
