@@ -279,6 +279,9 @@ def main():
                                "patience 100, one image per step",
                    "precision": head, "global_batch": 1, "image": f"{args.size}x{args.size}x1"},
         "mpx_per_s": round(r["ips"] * npx / 1e6, 4),
+        # per-epoch time: the kernel-speed figure (images/s also moves with
+        # the stopping epoch, which any change of rounding shifts)
+        "ms_per_epoch": round(1e3 * r["wall"] / max(1, sum(p["epochs"] for p in r["per_image"])), 4),
         "latency_s": r["latency"],
         "epochs_mean": r["epochs_mean"],
         "per_image": r["per_image"],

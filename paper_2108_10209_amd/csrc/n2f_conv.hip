@@ -422,7 +422,7 @@ int conv_bf16_blocks(int h, int w) {
 // summed from the staged delta with 16-byte reads.  At the end the waves'
 // sums are added in wave order through LDS, three taps at a time.
 constexpr int kWgPSA = 16;                                // bf16 per staged halo pixel (one quarter)
-constexpr int kWgPSB = 68;                                // bf16 per staged delta pixel
+constexpr int kWgPSB = 64;                                // bf16 per staged delta pixel (chunks XOR-placed)
 constexpr int kWgHaloE = kHalo * kHalo * kWgPSA;
 constexpr int kWgBufE = kWgHaloE + kTile * kTile * kWgPSB;
 constexpr int kWgHaloChunks = kHalo * kHalo * 2;          // 16-byte chunks of a halo quarter
@@ -441,6 +441,17 @@ __device__ __forceinline__ bf16x8 tr16_frag(const uint16_t* p0, const uint16_t* 
         (lds_bf16x4*)((__attribute__((address_space(3))) uint16_t*)p1));
     return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
+
+// LDS placement of the staged operands, so that the transpose reads of the
+// lane groups LDS serves together hit distinct banks: halo pixel (hy, hx)
+// sits in 32-byte slot hy * 18 + wg_hslot(hx) (columns 8..15 swap their
+// halves, so the columns x and x + 8 that two lane groups read together
+// never share a bank, and a row shift stays a constant offset); delta
+// pixel p keeps its 128-byte row and its 16-byte chunk c moves to
+// c ^ wg_dswz(p).
+__device__ __forceinline__ int wg_hslot(int hx) { return hx ^ (((hx >> 3) & 1) << 2); }
+__device__ __forceinline__ int wg_dswz(int p) { return (p & 2) | ((p >> 1) & 4); }
+__device__ __forceinline__ int wg_dt(int p, int ch) { return p * kWgPSB + ((((ch >> 3) ^ wg_dswz(p))) << 3) + (ch & 7); }
 
 // Global -> registers: the halo quarter (channels 16q..16q+15 of the 18x18
 // pixels around the tile) and the 16x16x64 delta tile, zero outside.
@@ -473,12 +484,11 @@ __device__ __forceinline__ void wg_store(const uint4 (&pf)[kWgPf], uint16_t* buf
     for (int k = 0; k < kWgPf; ++k) {
         const int c = threadIdx.x + 512 * k;
         if (c < kWgHaloChunks) {
-            *reinterpret_cast<uint4*>(buf + (c >> 1) * kWgPSA + 8 * (c & 1)) = pf[k];
+            const int hp = c >> 1, hy = hp / kHalo, hx = hp - hy * kHalo;
+            *reinterpret_cast<uint4*>(buf + (hy * kHalo + wg_hslot(hx)) * kWgPSA + 8 * (c & 1)) = pf[k];
         } else if (c < kWgChunks) {
             const int c2 = c - kWgHaloChunks;
-            uint2* d = reinterpret_cast<uint2*>(buf + kWgHaloE + (c2 >> 3) * kWgPSB + 8 * (c2 & 7));
-            d[0] = make_uint2(pf[k].x, pf[k].y);
-            d[1] = make_uint2(pf[k].z, pf[k].w);
+            *reinterpret_cast<uint4*>(buf + kWgHaloE + wg_dt(c2 >> 3, 8 * (c2 & 7))) = pf[k];
         }
     }
 }
@@ -513,7 +523,7 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
     for (int i = 0; i < 9; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // bias gradient: thread = (8-channel chunk tid & 7, pixels 4 (tid >> 3) .. +3)
+    // bias gradient: thread = (8-channel chunk tid & 7, pixels (tid >> 3) + 64 k)
     float db[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
     // tiles flow global -> registers -> LDS two tiles ahead: while tile it is
@@ -537,9 +547,8 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
         if (q == 0) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const uint2* v = reinterpret_cast<const uint2*>(dt + (4 * (tid >> 3) + k) * kWgPSB + 8 * (tid & 7));
-                const uint2 lo = v[0], hi = v[1];
-                const uint32_t u[4] = {lo.x, lo.y, hi.x, hi.y};
+                const uint4 v = *reinterpret_cast<const uint4*>(dt + wg_dt((tid >> 3) + 64 * k, 8 * (tid & 7)));
+                const uint32_t u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     db[2 * e] += __uint_as_float(u[e] << 16);
@@ -556,13 +565,13 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const int cb = 16 * (2 * oh + j) + rc;
-                bfr[j] = tr16_frag(dt + k0 * kWgPSB + cb, dt + k1 * kWgPSB + cb);
+                bfr[j] = tr16_frag(dt + wg_dt(k0, cb), dt + wg_dt(k1, cb));
             }
 #pragma unroll
             for (int t = 0; t < kTaps; ++t) {
                 const int dy = t / 3, dx = t - 3 * (t / 3);
-                const bf16x8 a = tr16_frag(halo + ((py0 + dy) * kHalo + px0 + dx) * kWgPSA + rc,
-                                           halo + ((py1 + dy) * kHalo + px1 + dx) * kWgPSA + rc);
+                const bf16x8 a = tr16_frag(halo + ((py0 + dy) * kHalo + wg_hslot(px0 + dx)) * kWgPSA + rc,
+                                           halo + ((py1 + dy) * kHalo + wg_hslot(px1 + dx)) * kWgPSA + rc);
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[j], acc[t][j], 0, 0, 0);
