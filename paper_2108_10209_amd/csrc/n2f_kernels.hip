@@ -669,17 +669,21 @@ __device__ __forceinline__ void adam_one(float* __restrict__ theta, float* __res
     if (l >= 1 && l < kLayers && il < kConvW) pack_one(l, il, th, fwd, bwd, fwd16, bwd16);
 }
 
-// Waves [0, 7 * kAdamWPL) each own 256 consecutive values of one 64->64
-// layer: a lane sums its 4 values over all of the layer's split partials in
-// split order with 16-byte loads (16 in flight) and applies Adam to them.
-// The blocks after those own a few values of the first layer (32 values x 8
-// split groups) or of the head (4 values x 64 split groups), whose partials
-// are many short rows; the group sums are added in group order.  The last
-// block sums the loss partials.  Every sum order is fixed.
-constexpr int kAdamWPL = (kConvN + 255) / 256;           // waves per 64->64 layer
-constexpr int kAdamConvBlocks = ((kLayers - 1) * kAdamWPL + 3) / 4;
-constexpr int kAdamV0 = 32;                              // first layer: values per block
-constexpr int kAdamVH = 4;                               // head: values per block
+// Blocks [0, 7 * kAdamWPL) each own 256 consecutive values of one 64->64
+// layer.  Wave k of such a block sums a lane's 4 values over the k-th
+// quarter of the layer's split partials, in split order, with 16-byte loads
+// (16 in flight); the four quarter sums are then added in quarter order and
+// wave 0 applies Adam.  Four waves per chunk keep enough loads in flight to
+// cover the memory latency of the partial reads.
+// The blocks after those own a few values of the first layer (4 values x 64
+// split groups) or of the head (1 value x 256 split groups), whose partials
+// are many short rows: a thread sums every G-th row (a few loads, all in
+// flight), and the group sums meet in a fixed-order tree.  The last block
+// sums the loss partials.  Every sum order is fixed.
+constexpr int kAdamWPL = (kConvN + 255) / 256;           // 256-value chunks per 64->64 layer
+constexpr int kAdamConvBlocks = (kLayers - 1) * kAdamWPL;
+constexpr int kAdamV0 = 4;                               // first layer: values per block
+constexpr int kAdamVH = 1;                               // head: values per block
 
 __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, float* __restrict__ m,
                                                  float* __restrict__ v, float* __restrict__ g,
@@ -714,32 +718,42 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, floa
     const float bc1 = (float)(1.0 - pow(beta1, (double)t_new));
     const float bc2 = (float)(1.0 - pow(beta2, (double)t_new));
     if ((int)blockIdx.x < kAdamConvBlocks) {
-        const int wid = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-        if (wid >= (kLayers - 1) * kAdamWPL) return;
-        const int l = 1 + wid / kAdamWPL;
-        const int il = (wid % kAdamWPL) * 256 + 4 * (threadIdx.x & 63);
-        if (il >= kConvN) return;
+        const int l = 1 + (int)blockIdx.x / kAdamWPL;
+        const int il = ((int)blockIdx.x % kAdamWPL) * 256 + 4 * (threadIdx.x & 63);
+        const int wq = threadIdx.x >> 6;
+        const bool valid = il < kConvN;   // the layer's last chunk is partly empty
         const int i0 = pt.off[l] + il;
-        float gg[4];
+        float gg[4] = {0.f, 0.f, 0.f, 0.f};
         if (ginj) {
+            if (wq != 0 || !valid) return;
 #pragma unroll
             for (int e = 0; e < 4; ++e) gg[e] = ginj[i0 + e];
         } else {
-            const float4* pp = reinterpret_cast<const float4*>(part + pt.poff[l] + il);
-            const int row4 = kConvN / 4;
+            __shared__ float4 qsum[4][64];
             float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (valid) {
+                const float4* pp = reinterpret_cast<const float4*>(part + pt.poff[l] + il);
+                const int row4 = kConvN / 4;
+                const int S = pt.split[l];
+                const int lo = (wq * S) / 4, hi = ((wq + 1) * S) / 4;
 #pragma unroll 16
-            for (int sp = 0; sp < pt.split[l]; ++sp) {
-                const float4 x = pp[(long long)sp * row4];
-                acc.x += x.x;
-                acc.y += x.y;
-                acc.z += x.z;
-                acc.w += x.w;
+                for (int sp = lo; sp < hi; ++sp) {
+                    const float4 x = pp[(long long)sp * row4];
+                    acc.x += x.x;
+                    acc.y += x.y;
+                    acc.z += x.z;
+                    acc.w += x.w;
+                }
             }
-            gg[0] = acc.x;
-            gg[1] = acc.y;
-            gg[2] = acc.z;
-            gg[3] = acc.w;
+            qsum[wq][threadIdx.x & 63] = acc;
+            __syncthreads();
+            if (wq != 0 || !valid) return;
+            const int ln = threadIdx.x & 63;
+            const float4 a = qsum[0][ln], b = qsum[1][ln], c = qsum[2][ln], d = qsum[3][ln];
+            gg[0] = ((a.x + b.x) + c.x) + d.x;
+            gg[1] = ((a.y + b.y) + c.y) + d.y;
+            gg[2] = ((a.z + b.z) + c.z) + d.z;
+            gg[3] = ((a.w + b.w) + c.w) + d.w;
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -762,10 +776,15 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, floa
     float sum = 0.f;
     if (valid && !ginj) {
         const float* pp = part + pt.poff[l] + il;
+#pragma unroll 4
         for (int sp = j; sp < pt.split[l]; sp += G) sum += pp[(long long)sp * pt.n[l]];
     }
     red[threadIdx.x] = sum;
     __syncthreads();
+    for (int half = G / 2; half > 0; half >>= 1) {   // G is a power of two
+        if (j < half) red[threadIdx.x] += red[threadIdx.x + half * V];
+        __syncthreads();
+    }
     if (j == 0 && valid) {
         const int i = pt.off[l] + il;
         float gi;
@@ -773,7 +792,6 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, floa
             gi = ginj[i];
         } else {
             gi = red[threadIdx.x];
-            for (int k = 1; k < G; ++k) gi += red[k * V + threadIdx.x];
         }
         g[i] = gi;
         adam_one(theta, m, v, i, gi, lr, b1, b2, omb1, omb2, bc1, bc2, eps, l, il, fwd, bwd, fwd16, bwd16);
