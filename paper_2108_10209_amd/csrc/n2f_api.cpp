@@ -171,7 +171,9 @@ n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
     q.P = q.Hc * q.Wc / 2;
     q.nsplit = std::max(wgrad_splits(q.hu, q.wu, q.bf), wgrad_splits(q.hl, q.wl, q.bf));
     q.n1split = (int)std::max(1LL, std::min((long long)kMaxSplit, ((long long)q.P + 511) / 512));
-    q.hsplit = head_splits(q.P);
+    // BF16: the head runs in the last forward convolution's epilogue, one
+    // partial row per block of its grid (the larger of the two pair shapes)
+    q.hsplit = q.bf ? std::max(head_fused_blocks(q.hu, q.wu), head_fused_blocks(q.hl, q.wl)) : head_splits(q.P);
     const long long HW = (long long)H * W;
     q.vblk = (int)std::max(1LL, std::min((HW + 255) / 256, 1024LL));
     q.mmblk = (int)std::max(1LL, std::min((HW * C + 4095) / 4096, 1024LL));
@@ -378,10 +380,12 @@ n2f_status enqueue_train_step(n2f_run* r, int k, int pair) {
     auto bwdpk = [&](int l) -> const void* {
         return bf ? (const void*)(N.bwd16 + (size_t)(l - 1) * kPackN) : (const void*)(N.bwd + (size_t)(l - 1) * kPackN);
     };
-    // forward with stash: act layer i holds a_{i+1}
+    // forward with stash: act layer i holds a_{i+1}; BF16 fuses the head
+    // into the last layer, whose a8 is then never stored
+    const int nplain = bf ? kLayers - 2 : kLayers - 1;
     N2F_HIP(launch_conv1(in, pl.C, Wl(0), Bl(0), act_layer(r, 0, npix), mask_layer(r, 0, npix), bf, h, w, N.st, s));
-    N2F_HIP(timed(N2F_K_CONV_FWD, kLayers - 1, (long long)npix, s, [&]() -> hipError_t {
-        for (int l = 1; l < kLayers; ++l) {
+    N2F_HIP(timed(N2F_K_CONV_FWD, nplain, (long long)npix, s, [&]() -> hipError_t {
+        for (int l = 1; l <= nplain; ++l) {
             hipError_t e = launch_conv_fwd(act_layer(r, l - 1, npix), fwdpk(l), Bl(l), act_layer(r, l, npix),
                                            mask_layer(r, l, npix), bf, h, w, N.st, s);
             if (e != hipSuccess) return e;
@@ -390,8 +394,15 @@ n2f_status enqueue_train_step(n2f_run* r, int k, int pair) {
     }));
     // head, BCE gradient
     const float* w9 = N.theta + pt.off[kLayers];
-    N2F_HIP(launch_head_train(act_layer(r, kLayers - 1, npix), tgt, pl.C, k, w9, w9 + kWidth, r->dlt[0],
-                              r->part + pt.poff[kLayers], r->lpart, pt.split[kLayers], bf, (long long)npix, N.st, s));
+    if (bf) {
+        ConvHead hd{w9, tgt, r->part + pt.poff[kLayers], r->lpart, N.st, pl.C, k, 1.0f / (float)npix};
+        N2F_HIP(launch_conv_fwd_head(act_layer(r, kLayers - 2, npix), fwdpk(kLayers - 1), Bl(kLayers - 1), r->dlt[0],
+                                     hd, pt.split[kLayers], h, w, N.st, s));
+    } else {
+        N2F_HIP(launch_head_train(act_layer(r, kLayers - 1, npix), tgt, pl.C, k, w9, w9 + kWidth, r->dlt[0],
+                                  r->part + pt.poff[kLayers], r->lpart, pt.split[kLayers], bf, (long long)npix, N.st,
+                                  s));
+    }
     // backward: layer l (0-based 7..1) takes delta of its output
     int cur = 0;
     N2F_HIP(timed(N2F_K_BACKWARD, kLayers - 1, (long long)npix, s, [&]() -> hipError_t {

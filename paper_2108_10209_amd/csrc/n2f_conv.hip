@@ -243,16 +243,28 @@ __device__ __forceinline__ bool bf16_pos(uint32_t b) { return (b & 0x8000u) == 0
 // a pixel's MFMA outputs owns one 16-bit word.  Bit set = the stored BF16
 // value is > 0.  MODE 0 writes them (when mbits is given), MODE 1 applies
 // them to the data gradient.
+// MODE 2: forward of the last layer with the training head in the epilogue
+// (see ConvHead): the lane's 16 channels of a pixel give a partial of z, the
+// four lanes of the pixel add theirs by an xor butterfly, and the head
+// gradient sums over a row's 16 pixels by another, then over the waves in
+// order through LDS.
 template <int MODE>
 __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
                                                    const float* __restrict__ bias, uint16_t* __restrict__ mbits,
-                                                   uint16_t* __restrict__ out, int h, int w, const DevState* st) {
+                                                   uint16_t* __restrict__ out, int h, int w, int nblk,
+                                                   const DevState* st, ConvHead hd) {
+    // nblk = gridDim.x, passed among the first arguments: reading the
+    // hidden grid size after the head arguments costs a second round trip
+    // of scalar loads before the first global load
     // the stop flag (st is never NULL here) is read first but tested only
     // once the weight and halo loads are in flight, so its memory latency
     // hides under theirs
     const int stop = st->done;
     __shared__ __attribute__((aligned(16))) uint16_t sw[kTaps * kWidth * kWidth];
     __shared__ __attribute__((aligned(16))) uint16_t hb[2][kHaloPix * kWidth];
+    __shared__ float shw[kHeadN];          // MODE 2: head weights and bias
+    __shared__ float shred[8][kHeadN];     // MODE 2: per-wave dW9, db9 sums
+    __shared__ double slred[8];            // MODE 2: per-wave BCE sums
     const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
     const int lane = tid & 63, wq = gt >> 6;
     const int g = lane >> 4, n = lane & 15;
@@ -266,7 +278,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
     for (int k = 0; k < kWChunks; ++k) wr[k] = reinterpret_cast<const uint4*>(wpk)[tid + 512 * k];
     const int tiles_x = (w + kTile - 1) / kTile, tiles_y = (h + kTile - 1) / kTile;
     const int ntiles = tiles_x * tiles_y;
-    const int stride = 2 * gridDim.x;
+    const int stride = 2 * nblk;
     const int iters = (ntiles - 2 * (int)blockIdx.x + stride - 1) / stride;
 
     uint4 pf[kPf];
@@ -285,8 +297,14 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
         }
     };
     if (iters > 0) fetch(2 * blockIdx.x + grp);
+    const float hwv = (MODE == 2 && tid < kHeadN) ? hd.w9[tid] : 0.f;
     asm volatile("" ::: "memory");   // keeps those loads ahead of the test
     if (stop) return;
+    if (MODE == 2) {
+        if (tid < kHeadN) shw[tid] = hwv;
+        for (int i = tid; i < 8 * kHeadN; i += 512) (&shred[0][0])[i] = 0.f;
+        if (tid < 8) slred[tid] = 0.0;
+    }
 #pragma unroll
     for (int k = 0; k < kWChunks; ++k) reinterpret_cast<uint4*>(sw)[tid + 512 * k] = wr[k];
 
@@ -344,7 +362,85 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
         }
 
         // D row = channel 16j + 4g + r, column = pixel x = n of tile row 4wq + i.
-        if (have) {
+        if (MODE == 2 && have) {
+            const int gx = x0 + n;
+            float hg[4][4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) hg[j][r] = 0.f;
+            float hbs = 0.f;
+            double hls = 0.0;
+            float bv[4][4];   // bias of the lane's 16 channels
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) bv[j][r] = bias[16 * j + 4 * g + r];
+            const float hb9 = shw[kWidth];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int gy = y0 + 4 * wq + i;
+                const bool valid = gy < h && gx < w;
+                const long long pix = (long long)gy * w + gx;
+                const float t = valid ? hd.tgt[pix * hd.C + hd.k] : 0.f;
+                // a8 as the BF16 value the forward would store
+                float a[4][4];
+                float zp = 0.f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        a[j][r] = bf16_f(bf16_rne(fmaxf(acc[i][j][r] + bv[j][r], 0.f)));
+                        zp = fmaf(a[j][r], shw[16 * j + 4 * g + r], zp);
+                    }
+                zp += __shfl_xor(zp, 16);
+                zp += __shfl_xor(zp, 32);
+                const float z = zp + hb9;
+                const float y = 1.0f / (1.0f + expf(-z));
+                const float d = valid ? (y - t) * hd.invP : 0.f;
+                if (valid) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        float dv[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) dv[r] = a[j][r] > 0.f ? d * shw[16 * j + 4 * g + r] : 0.f;
+                        const uint2 o = make_uint2((uint32_t)bf16_rne(dv[0]) | ((uint32_t)bf16_rne(dv[1]) << 16),
+                                                   (uint32_t)bf16_rne(dv[2]) | ((uint32_t)bf16_rne(dv[3]) << 16));
+                        *reinterpret_cast<uint2*>(out + pix * kWidth + 16 * j + 4 * g) = o;
+                    }
+                    if (g == 0) {
+                        hbs += d;
+                        hls += (double)(fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - t * z);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) hg[j][r] = fmaf(d, a[j][r], hg[j][r]);
+            }
+            // the 16 pixels (lanes n) of each row, then the wave's slot
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) hg[j][r] += __shfl_xor(hg[j][r], off);
+                hbs += __shfl_xor(hbs, off);
+                hls += __shfl_xor(hls, off);
+            }
+            if (n == 0) {
+                const int wv = tid >> 6;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) shred[wv][16 * j + 4 * g + r] += hg[j][r];
+                if (g == 0) {
+                    shred[wv][kWidth] += hbs;
+                    slred[wv] += hls;
+                }
+            }
+        }
+        if (MODE != 2 && have) {
             float bv[4][4];
             if (MODE == 0) {
 #pragma unroll
@@ -391,6 +487,23 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
             }
         }
         __syncthreads();   // the next tile's halo overwrites this buffer
+    }
+    if (MODE == 2) {
+        __syncthreads();
+        if (tid < kHeadN) {
+            float sum = 0.f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sum += shred[q][tid];
+            hd.part[(long long)blockIdx.x * kHeadN + tid] = sum;
+        }
+        if (tid == 0) {
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sum += slred[q];
+            hd.lpart[blockIdx.x] = sum;
+            // one Adam step follows this head: count it (no other block reads t)
+            if (blockIdx.x == 0) hd.st->t += 1;
+        }
     }
 }
 
@@ -628,8 +741,9 @@ hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, v
                            int h, int w, const DevState* st, hipStream_t s) {
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
     if (bf16) {
-        hipLaunchKernelGGL(k_conv_bf16<0>, dim3(conv_bf16_blocks(h, w)), dim3(512), 0, s, (const uint16_t*)in,
-                           (const uint16_t*)wpk, bias, mbits, (uint16_t*)out, h, w, st);
+        const int nb = conv_bf16_blocks(h, w);
+        hipLaunchKernelGGL(k_conv_bf16<0>, dim3(nb), dim3(512), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
+                           mbits, (uint16_t*)out, h, w, nb, st, ConvHead{});
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_conv_f32<0>, grid, dim3(256), 0, s, (const float*)in, (const float*)wpk, bias,
@@ -637,19 +751,30 @@ hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, v
     return hipGetLastError();
 }
 
+hipError_t launch_conv_fwd_head(const void* in, const void* wpk, const float* bias, void* d8, const ConvHead& hd,
+                                int nblk, int h, int w, const DevState* st, hipStream_t s) {
+    if (nblk < conv_bf16_blocks(h, w) || nblk > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_conv_bf16<2>, dim3(nblk), dim3(512), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
+                       (uint16_t*)nullptr, (uint16_t*)d8, h, w, nblk, st, hd);
+    return hipGetLastError();
+}
+
 hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, void* out, int bf16, int h, int w,
                            const DevState* st, hipStream_t s) {
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
     if (bf16) {
-        hipLaunchKernelGGL(k_conv_bf16<1>, dim3(conv_bf16_blocks(h, w)), dim3(512), 0, s, (const uint16_t*)dlt,
-                           (const uint16_t*)wpk, (const float*)nullptr, (uint16_t*)const_cast<void*>(mask),
-                           (uint16_t*)out, h, w, st);
+        const int nb = conv_bf16_blocks(h, w);
+        hipLaunchKernelGGL(k_conv_bf16<1>, dim3(nb), dim3(512), 0, s, (const uint16_t*)dlt, (const uint16_t*)wpk,
+                           (const float*)nullptr, (uint16_t*)const_cast<void*>(mask), (uint16_t*)out, h, w, nb, st,
+                           ConvHead{});
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_conv_f32<1>, grid, dim3(256), 0, s, (const float*)dlt, (const float*)wpk,
                        (const float*)nullptr, (const float*)mask, (float*)out, h, w, st);
     return hipGetLastError();
 }
+
+int head_fused_blocks(int h, int w) { return conv_bf16_blocks(h, w); }
 
 int wgrad_splits(int h, int w, int bf16) {
     const int tiles = ((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile);

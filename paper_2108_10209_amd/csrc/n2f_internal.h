@@ -81,6 +81,23 @@ hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, v
                            int bf16, int h, int w, const DevState* st, hipStream_t s);
 hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, void* out, int bf16,
                            int h, int w, const DevState* st, hipStream_t s);
+// BF16 path: the last 3x3 forward layer with the training head in its
+// epilogue (z = w9 . a8 + b9, the mean-BCE gradient, d8 = dL/dz w9 [a8 > 0],
+// one partial row of dW9, db9 and of the loss per block); a8 itself is not
+// stored.  The grid is nblk blocks (>= head_fused_blocks(h, w)), one head
+// partial row each, so every pair shape fills the same nblk rows.
+struct ConvHead {
+    const float* w9;     // head weights, then b9
+    const float* tgt;    // target image, C channels per pixel
+    float* part;         // nblk x kHeadN partial sums of dW9, db9
+    double* lpart;       // nblk partial sums of the BCE
+    DevState* st;        // its step counter counts the Adam step that follows
+    int C, k;            // target channels, and the one this network predicts
+    float invP;          // 1 / pixels of the pair
+};
+int head_fused_blocks(int h, int w);   // blocks of the BF16 convolution grid at h x w
+hipError_t launch_conv_fwd_head(const void* in, const void* wpk, const float* bias, void* d8, const ConvHead& hd,
+                                int nblk, int h, int w, const DevState* st, hipStream_t s);
 int wgrad_splits(int h, int w, int bf16);
 hipError_t launch_wgrad(const void* src, const void* dlt, float* part, int nsplit, int bf16,
                         int h, int w, const DevState* st, hipStream_t s);
