@@ -395,7 +395,7 @@ n2f_status enqueue_train_step(n2f_run* r, int k, int pair) {
     // head, BCE gradient
     const float* w9 = N.theta + pt.off[kLayers];
     if (bf) {
-        ConvHead hd{w9, tgt, r->part + pt.poff[kLayers], r->lpart, N.st, pl.C, k, 1.0f / (float)npix};
+        ConvHead hd{w9, tgt, r->part + pt.poff[kLayers], r->lpart, nullptr, N.st, pl.C, k, 1.0f / (float)npix};
         N2F_HIP(launch_conv_fwd_head(act_layer(r, kLayers - 2, npix), fwdpk(kLayers - 1), Bl(kLayers - 1), r->dlt[0],
                                      hd, pt.split[kLayers], h, w, N.st, s));
     } else {
@@ -435,19 +435,28 @@ n2f_status enqueue_validate(n2f_run* r, int k) {
     hipStream_t s = r->stream;
     auto buf = [&](int i) { return act_layer(r, i & 1, npix); };
     auto Bl = [&](int l) { return N.theta + pt.off[l] + kTaps * pt.cin[l] * kWidth; };
+    auto pk = [&](int l) -> const void* {
+        return bf ? (const void*)(N.fwd16 + (size_t)(l - 1) * kPackN) : (const void*)(N.fwd + (size_t)(l - 1) * kPackN);
+    };
+    // BF16 fuses the head into the last layer (see enqueue_train_step)
+    const int nplain = bf ? kLayers - 2 : kLayers - 1;
     N2F_HIP(launch_conv1(r->xs, pl.C, N.theta + pt.off[0], Bl(0), buf(0), nullptr, bf, pl.H, pl.W, N.st, s));
-    N2F_HIP(timed(N2F_K_CONV_FWD, kLayers - 1, (long long)npix, s, [&]() -> hipError_t {
-        for (int l = 1; l < kLayers; ++l) {
-            const void* pk = bf ? (const void*)(N.fwd16 + (size_t)(l - 1) * kPackN)
-                                : (const void*)(N.fwd + (size_t)(l - 1) * kPackN);
-            hipError_t e = launch_conv_fwd(buf(l - 1), pk, Bl(l), buf(l), nullptr, bf, pl.H, pl.W, N.st, s);
+    N2F_HIP(timed(N2F_K_CONV_FWD, nplain, (long long)npix, s, [&]() -> hipError_t {
+        for (int l = 1; l <= nplain; ++l) {
+            hipError_t e = launch_conv_fwd(buf(l - 1), pk(l), Bl(l), buf(l), nullptr, bf, pl.H, pl.W, N.st, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     }));
     const float* w9 = N.theta + pt.off[kLayers];
-    N2F_HIP(launch_head_val(buf(kLayers - 1), r->xs, pl.C, k, w9, w9 + kWidth, N.y, r->vpart, pl.vblk, bf,
-                            (long long)npix, N.st, N.trace, s));
+    if (bf) {
+        ConvHead hd{w9, r->xs, nullptr, r->vpart, N.y, N.st, pl.C, k, 0.f};
+        N2F_HIP(launch_conv_fwd_val(buf(kLayers - 2), pk(kLayers - 1), Bl(kLayers - 1), hd, pl.H, pl.W, N.st, N.trace,
+                                    s));
+    } else {
+        N2F_HIP(launch_head_val(buf(kLayers - 1), r->xs, pl.C, k, w9, w9 + kWidth, N.y, r->vpart, pl.vblk, bf,
+                                (long long)npix, N.st, N.trace, s));
+    }
     N2F_HIP(launch_accumulate(N.y, N.S, N.yb, (long long)npix, N.st, s));
     return N2F_OK;
 }

@@ -244,7 +244,8 @@ __device__ __forceinline__ bool bf16_pos(uint32_t b) { return (b & 0x8000u) == 0
 // value is > 0.  MODE 0 writes them (when mbits is given), MODE 1 applies
 // them to the data gradient.
 // MODE 2: forward of the last layer with the training head in the epilogue
-// (see ConvHead): the lane's 16 channels of a pixel give a partial of z, the
+// (see ConvHead); MODE 3: the same with the validation head (the output
+// image and the squared error).  The lane's 16 channels of a pixel give a partial of z, the
 // four lanes of the pixel add theirs by an xor butterfly, and the head
 // gradient sums over a row's 16 pixels by another, then over the waves in
 // order through LDS.
@@ -297,10 +298,10 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
         }
     };
     if (iters > 0) fetch(2 * blockIdx.x + grp);
-    const float hwv = (MODE == 2 && tid < kHeadN) ? hd.w9[tid] : 0.f;
+    const float hwv = (MODE >= 2 && tid < kHeadN) ? hd.w9[tid] : 0.f;
     asm volatile("" ::: "memory");   // keeps those loads ahead of the test
     if (stop) return;
-    if (MODE == 2) {
+    if (MODE >= 2) {
         if (tid < kHeadN) shw[tid] = hwv;
         for (int i = tid; i < 8 * kHeadN; i += 512) (&shred[0][0])[i] = 0.f;
         if (tid < 8) slred[tid] = 0.0;
@@ -362,7 +363,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
         }
 
         // D row = channel 16j + 4g + r, column = pixel x = n of tile row 4wq + i.
-        if (MODE == 2 && have) {
+        if (MODE >= 2 && have) {
             const int gx = x0 + n;
             float hg[4][4];
 #pragma unroll
@@ -397,6 +398,15 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                 zp += __shfl_xor(zp, 32);
                 const float z = zp + hb9;
                 const float y = 1.0f / (1.0f + expf(-z));
+                if (MODE == 3) {
+                    // validation: the output pixel and its squared error against the noisy image
+                    if (valid && g == 0) {
+                        hd.y[pix] = y;
+                        const double e = (double)y - (double)t;
+                        hls += e * e;
+                    }
+                    continue;
+                }
                 const float d = valid ? (y - t) * hd.invP : 0.f;
                 if (valid) {
 #pragma unroll
@@ -421,26 +431,30 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
             // the 16 pixels (lanes n) of each row, then the wave's slot
 #pragma unroll
             for (int off = 8; off > 0; off >>= 1) {
+                if (MODE == 2) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < 4; ++j)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) hg[j][r] += __shfl_xor(hg[j][r], off);
-                hbs += __shfl_xor(hbs, off);
+                        for (int r = 0; r < 4; ++r) hg[j][r] += __shfl_xor(hg[j][r], off);
+                    hbs += __shfl_xor(hbs, off);
+                }
                 hls += __shfl_xor(hls, off);
             }
             if (n == 0) {
                 const int wv = tid >> 6;
+                if (MODE == 2) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < 4; ++j)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) shred[wv][16 * j + 4 * g + r] += hg[j][r];
+                        for (int r = 0; r < 4; ++r) shred[wv][16 * j + 4 * g + r] += hg[j][r];
+                }
                 if (g == 0) {
-                    shred[wv][kWidth] += hbs;
+                    if (MODE == 2) shred[wv][kWidth] += hbs;
                     slred[wv] += hls;
                 }
             }
         }
-        if (MODE != 2 && have) {
+        if (MODE < 2 && have) {
             float bv[4][4];
             if (MODE == 0) {
 #pragma unroll
@@ -487,6 +501,15 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
             }
         }
         __syncthreads();   // the next tile's halo overwrites this buffer
+    }
+    if (MODE == 3) {
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sum += slred[q];
+            hd.lpart[blockIdx.x] = sum;
+        }
     }
     if (MODE == 2) {
         __syncthreads();
@@ -757,6 +780,16 @@ hipError_t launch_conv_fwd_head(const void* in, const void* wpk, const float* bi
     hipLaunchKernelGGL(k_conv_bf16<2>, dim3(nblk), dim3(512), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
                        (uint16_t*)nullptr, (uint16_t*)d8, h, w, nblk, st, hd);
     return hipGetLastError();
+}
+
+hipError_t launch_conv_fwd_val(const void* in, const void* wpk, const float* bias, const ConvHead& hd, int h, int w,
+                               DevState* st, double* vtrace, hipStream_t s) {
+    const int nb = conv_bf16_blocks(h, w);
+    hipLaunchKernelGGL(k_conv_bf16<3>, dim3(nb), dim3(512), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
+                       (uint16_t*)nullptr, (uint16_t*)nullptr, h, w, nb, (const DevState*)st, hd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_decide(hd.lpart, nb, (long long)h * w, st, vtrace, s);
 }
 
 hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, void* out, int bf16, int h, int w,

@@ -88,16 +88,24 @@ hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, v
 // partial row each, so every pair shape fills the same nblk rows.
 struct ConvHead {
     const float* w9;     // head weights, then b9
-    const float* tgt;    // target image, C channels per pixel
-    float* part;         // nblk x kHeadN partial sums of dW9, db9
-    double* lpart;       // nblk partial sums of the BCE
-    DevState* st;        // its step counter counts the Adam step that follows
+    const float* tgt;    // target image (validation: the noisy image), C channels per pixel
+    float* part;         // nblk x kHeadN partial sums of dW9, db9 (training)
+    double* lpart;       // nblk partial sums of the BCE (training) or of the squared error (validation)
+    float* y;            // validation: the network's output image
+    DevState* st;        // training: its step counter counts the Adam step that follows
     int C, k;            // target channels, and the one this network predicts
-    float invP;          // 1 / pixels of the pair
+    float invP;          // training: 1 / pixels of the pair
 };
 int head_fused_blocks(int h, int w);   // blocks of the BF16 convolution grid at h x w
 hipError_t launch_conv_fwd_head(const void* in, const void* wpk, const float* bias, void* d8, const ConvHead& hd,
                                 int nblk, int h, int w, const DevState* st, hipStream_t s);
+// The same for the validation pass: y = sigmoid(z) and one partial sum of
+// (y - x)^2 per block, in FP64 (then the stopping decision, as after
+// launch_head_val); a8 is not stored.
+hipError_t launch_conv_fwd_val(const void* in, const void* wpk, const float* bias, const ConvHead& hd, int h, int w,
+                               DevState* st, double* vtrace, hipStream_t s);
+// Fixed-order sum of nblk validation partials and the stopping decision.
+hipError_t launch_decide(const double* vpart, int nblk, long long npix, DevState* st, double* vtrace, hipStream_t s);
 int wgrad_splits(int h, int w, int bf16);
 hipError_t launch_wgrad(const void* src, const void* dlt, float* part, int nsplit, int bf16,
                         int h, int w, const DevState* st, hipStream_t s);

@@ -902,7 +902,11 @@ hipError_t launch_head_val(const void* a8, const float* xs, int C, int k, const 
                            (const DevState*)st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kBlock), 0, s, (const double*)vpart, nblk, npix, st, vtrace);
+    return launch_decide(vpart, nblk, npix, st, vtrace, s);
+}
+
+hipError_t launch_decide(const double* vpart, int nblk, long long npix, DevState* st, double* vtrace, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kBlock), 0, s, vpart, nblk, npix, st, vtrace);
     return hipGetLastError();
 }
 
