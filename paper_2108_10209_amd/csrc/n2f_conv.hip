@@ -564,8 +564,9 @@ constexpr int kWgBufE = kWgHaloE + kTile * kTile * kWgPSB;
 constexpr int kWgHaloChunks = kHalo * kHalo * 2;          // 16-byte chunks of a halo quarter
 constexpr int kWgChunks = kWgHaloChunks + kTile * kTile * 8;
 constexpr int kWgPf = (kWgChunks + 511) / 512;            // chunks each thread carries
-constexpr int kWgRedS = 4 * 64 + 16;                      // floats per (wave, tile) in the reduction
-constexpr int kWgLdsBytes = (2 * kWgBufE * 2 > 8 * 12 * kWgRedS * 4) ? 2 * kWgBufE * 2 : 8 * 12 * kWgRedS * 4;
+constexpr int kWgRedT = 5;                                 // taps per pass of the final reduction
+constexpr int kWgRedBytes = 8 * 2 * kWgRedT * 64 * 16;     // 8 waves x (taps x 2) tiles x 64 lanes x 16 B
+constexpr int kWgLdsBytes = (2 * kWgBufE * 2 > kWgRedBytes) ? 2 * kWgBufE * 2 : kWgRedBytes;
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
@@ -633,7 +634,8 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
                                                     float* __restrict__ part, int h, int w, const DevState* st) {
     const int stop = st->done;   // tested once the first tiles' loads are in flight
     __shared__ __attribute__((aligned(16))) unsigned char lds[kWgLdsBytes];
-    __shared__ float dbs[64][kWidth];
+    __shared__ float dbs[256][16];     // bias gradient: per-thread sums of this block's 16 channels
+    __shared__ float dbs2[32][16];
     uint16_t* bufs = reinterpret_cast<uint16_t*>(lds);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int g = lane >> 4, r = lane & 15;
@@ -659,7 +661,9 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
     for (int i = 0; i < 9; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // bias gradient: thread = (8-channel chunk tid & 7, pixels (tid >> 3) + 64 k)
+    // bias gradient of the block's 16 channels 16 q ..: thread = (pixel
+    // tid / 2 of each tile, 8-channel chunk 2 q + tid % 2); every quarter
+    // block does a quarter of the work
     float db[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
     // tiles flow global -> registers -> LDS two tiles ahead: while tile it is
@@ -680,16 +684,13 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
         const uint16_t* halo = bufs + (it & 1) * kWgBufE;
         const uint16_t* dt = halo + kWgHaloE;
         if (it + 2 < nmine) wg_load(ld, src, dlt, sp + (it + 2) * nsplit, tiles_x, q, h, w);
-        if (q == 0) {
+        {
+            const uint4 v = *reinterpret_cast<const uint4*>(dt + wg_dt(tid >> 1, 8 * (2 * q + (tid & 1))));
+            const uint32_t u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint4 v = *reinterpret_cast<const uint4*>(dt + wg_dt((tid >> 3) + 64 * k, 8 * (tid & 7)));
-                const uint32_t u[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    db[2 * e] += __uint_as_float(u[e] << 16);
-                    db[2 * e + 1] += __uint_as_float(u[e] & 0xffff0000u);
-                }
+            for (int e = 0; e < 4; ++e) {
+                db[2 * e] += __uint_as_float(u[e] << 16);
+                db[2 * e + 1] += __uint_as_float(u[e] & 0xffff0000u);
             }
         }
 #pragma unroll
@@ -721,40 +722,62 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
         if (it + 1 < nmine) step(pfb, pfa, it + 1);
     }
 
-    // sum the 4 waves of each channel half in order, three taps at a time
-    float* red = reinterpret_cast<float*>(lds);
+    // sum the 4 waves of each channel half in order, taps 0-4 then 5-8: a
+    // lane's 4 accumulator values (rows 4 (lane / 16) + e, column lane % 16
+    // of an MFMA tile) move as one 16-byte LDS word; a reader adds the same
+    // word of the 4 waves and stores its 4 rows
+    float4* red = reinterpret_cast<float4*>(lds);
     float* pp = part + (long long)sp * kConvN;
 #pragma unroll
-    for (int pass = 0; pass < 3; ++pass) {
+    for (int pass = 0; pass < 2; ++pass) {
+        const int t0 = pass * kWgRedT, nt = pass == 0 ? kWgRedT : kTaps - kWgRedT;
 #pragma unroll
-        for (int tt = 0; tt < 3; ++tt)
+        for (int tt = 0; tt < kWgRedT; ++tt)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    red[(wv * 6 + tt * 2 + j) * kWgRedS + e * 64 + lane] = acc[3 * pass + tt][j][e];
+            for (int j = 0; j < 2; ++j) {
+                if (tt < nt) {
+                    const floatx4 v = acc[t0 + tt][j];
+                    red[(wv * 2 * kWgRedT + tt * 2 + j) * 64 + lane] = make_float4(v[0], v[1], v[2], v[3]);
+                }
+            }
         __syncthreads();
-        for (int o = tid; o < 3 * 16 * kWidth; o += 512) {
-            const int tt = o >> 10, cil = (o >> 6) & 15, co = o & 63;
-            const int cbk = co >> 4, ohh = cbk >> 1, jj = cbk & 1;
-            const int idx = (tt * 2 + jj) * kWgRedS + (cil & 3) * 64 + 16 * (cil >> 2) + (co & 15);
-            float sum = red[(2 * 0 + ohh) * 6 * kWgRedS + idx];
+        for (int gi = tid; gi < nt * 2 * 2 * 64; gi += 512) {
+            const int ln = gi & 63, jj = (gi >> 6) & 1, ohh = (gi >> 7) & 1, tt = gi >> 8;
+            float4 sum = red[(ohh * 2 * kWgRedT + tt * 2 + jj) * 64 + ln];
 #pragma unroll
-            for (int k = 1; k < 4; ++k) sum += red[(2 * k + ohh) * 6 * kWgRedS + idx];
-            pp[((3 * pass + tt) * kWidth + 16 * q + cil) * kWidth + co] = sum;
+            for (int k = 1; k < 4; ++k) {
+                const float4 x = red[((2 * k + ohh) * 2 * kWgRedT + tt * 2 + jj) * 64 + ln];
+                sum.x += x.x;
+                sum.y += x.y;
+                sum.z += x.z;
+                sum.w += x.w;
+            }
+            const int co = 16 * (2 * ohh + jj) + (ln & 15), cil = 4 * (ln >> 4);
+            float* o = pp + ((t0 + tt) * kWidth + 16 * q + cil) * kWidth + co;
+            o[0] = sum.x;
+            o[kWidth] = sum.y;
+            o[2 * kWidth] = sum.z;
+            o[3 * kWidth] = sum.w;
         }
         __syncthreads();
     }
-    if (q == 0) {
-        // pixel groups of one chunk: lanes tid, tid + 8, ... of 64 groups, in order
+    // the 256 pixel slots of each channel: 32 runs of 8 slots, then the runs, in order
 #pragma unroll
-        for (int e = 0; e < 8; ++e) dbs[tid >> 3][8 * (tid & 7) + e] = db[e];
-        __syncthreads();
-        if (tid < kWidth) {
-            float sum = dbs[0][tid];
-            for (int k = 1; k < 64; ++k) sum += dbs[k][tid];
-            pp[kConvW + tid] = sum;
-        }
+    for (int e = 0; e < 8; ++e) dbs[tid >> 1][8 * (tid & 1) + e] = db[e];
+    __syncthreads();
+    {
+        const int c = tid & 15, run = tid >> 4;
+        float sum = dbs[8 * run][c];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) sum += dbs[8 * run + k][c];
+        dbs2[run][c] = sum;
+    }
+    __syncthreads();
+    if (tid < 16) {
+        float sum = dbs2[0][tid];
+#pragma unroll
+        for (int k = 1; k < 32; ++k) sum += dbs2[k][tid];
+        pp[kConvW + 16 * q + tid] = sum;
     }
 }
 
