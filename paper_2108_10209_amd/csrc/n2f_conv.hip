@@ -199,6 +199,13 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 
 __device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
+// bf16_rne for a value that cannot be NaN (a ReLU output): the rounding add
+// alone is exact there, +inf and overflow included.
+__device__ __forceinline__ uint16_t bf16_rne_nonan(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
 
 
 // MODE 0: forward, bias + ReLU.  MODE 1: data gradient masked by [a > 0].
@@ -391,7 +398,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        a[j][r] = bf16_f(bf16_rne(fmaxf(acc[i][j][r] + bv[j][r], 0.f)));
+                        a[j][r] = bf16_f(bf16_rne_nonan(fmaxf(acc[i][j][r] + bv[j][r], 0.f)));
                         zp = fmaf(a[j][r], shw[16 * j + 4 * g + r], zp);
                     }
                 zp += __shfl_xor(zp, 16);
@@ -483,8 +490,9 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                     float v[4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) v[r] = (MODE == 0) ? fmaxf(acc[i][j][r] + bv[j][r], 0.f) : acc[i][j][r];
-                    uint2 o = make_uint2((uint32_t)bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[1]) << 16),
-                                         (uint32_t)bf16_rne(v[2]) | ((uint32_t)bf16_rne(v[3]) << 16));
+                    // a ReLU output (MODE 0) is never NaN
+                    auto rnd = [](float x) { return (uint32_t)(MODE == 0 ? bf16_rne_nonan(x) : bf16_rne(x)); };
+                    uint2 o = make_uint2(rnd(v[0]) | (rnd(v[1]) << 16), rnd(v[2]) | (rnd(v[3]) << 16));
                     if (MODE == 1) {
                         const uint32_t m = mk[i] >> (4 * j);
                         o.x &= ((m & 1u) ? 0x0000ffffu : 0u) | ((m & 2u) ? 0xffff0000u : 0u);

@@ -293,17 +293,30 @@ __global__ __launch_bounds__(kBlock) void k_conv1(const float* __restrict__ in, 
         }
         a0 = make_float4(fmaxf(a0.x, 0.f), fmaxf(a0.y, 0.f), fmaxf(a0.z, 0.f), fmaxf(a0.w, 0.f));
         a1 = make_float4(fmaxf(a1.x, 0.f), fmaxf(a1.y, 0.f), fmaxf(a1.z, 0.f), fmaxf(a1.w, 0.f));
-        store4(out, p * kWidth + c0, a0, BF);
-        store4(out, p * kWidth + c1, a1, BF);
-        if (BF && mbits) {
+        if (!BF) {
+            store4(out, p * kWidth + c0, a0, false);
+            store4(out, p * kWidth + c1, a1, false);
+        } else {
+            // each value rounded to BF16 once, for the store and the mask; a
+            // ReLU output is never NaN, and the rounding add carries +inf
+            // (and overflow) to the BF16 infinity without a special case
             const float v[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-            uint32_t byte = 0;
+            uint32_t b[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const uint16_t bb = f32_to_bf16_rne(v[e]);
-                if ((bb & 0x8000u) == 0 && (bb & 0x7fffu) != 0) byte |= 1u << e;    // stored value > 0
+                const uint32_t u = __float_as_uint(v[e]);
+                b[e] = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
             }
-            mbits[p * 8 + cl] = (uint8_t)byte;
+            uint16_t* o = reinterpret_cast<uint16_t*>(out) + p * kWidth;
+            *reinterpret_cast<uint2*>(o + c0) = make_uint2(b[0] | (b[1] << 16), b[2] | (b[3] << 16));
+            *reinterpret_cast<uint2*>(o + c1) = make_uint2(b[4] | (b[5] << 16), b[6] | (b[7] << 16));
+            if (mbits) {
+                uint32_t byte = 0;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if ((b[e] & 0x8000u) == 0 && (b[e] & 0x7fffu) != 0) byte |= 1u << e;    // stored value > 0
+                mbits[p * 8 + cl] = (uint8_t)byte;
+            }
         }
     }
 }
