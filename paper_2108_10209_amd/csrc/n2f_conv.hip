@@ -242,6 +242,46 @@ __device__ __forceinline__ bf16x8 shift_in_row(bf16x8 src, bf16x8 last) {
     return __builtin_bit_cast(bf16x8, d);
 }
 
+// Cross-lane sums on the VALU (no LDS round trip): x plus its partner lane.
+// add_xor8: partner l ^ 8 inside each 16-lane row (DPP rotate by 8);
+// add_xor16 / add_xor32: partner l ^ 16 / l ^ 32, from the gfx950 lane swaps
+// of a value with itself (the two results are each lane's own value and its
+// partner's, in some order; the sum is the same either way).
+__device__ __forceinline__ float add_xor8(float x) {
+    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float add_xor16(float x) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float add_xor32(float x) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// One step of a sum over the 16 lanes of a row, toward lane 0 of the row:
+// partner l + off (mod 16) for off = 8, 4 (DPP rotates), l ^ 2, l ^ 1 (quad
+// permutes).  For lane 0 these are the partners of an xor butterfly.
+template <int OFF>
+__device__ __forceinline__ int row_step_src(int x) {
+    constexpr int ctrl = OFF == 8 ? 0x128 : OFF == 4 ? 0x124 : OFF == 2 ? 0x4e : 0xb1;
+    return __builtin_amdgcn_update_dpp(0, x, ctrl, 0xf, 0xf, false);
+}
+template <int OFF>
+__device__ __forceinline__ float row_step(float x) {
+    return x + __int_as_float(row_step_src<OFF>(__float_as_int(x)));
+}
+template <int OFF>
+__device__ __forceinline__ double row_step(double x) {
+    const unsigned long long u = __double_as_longlong(x);
+    const unsigned long long lo = (unsigned)row_step_src<OFF>((int)(u & 0xffffffffu));
+    const unsigned long long hi = (unsigned)row_step_src<OFF>((int)(u >> 32));
+    return x + __longlong_as_double((long long)((hi << 32) | lo));
+}
+template <typename T>
+__device__ __forceinline__ T row_sum16(T x) {
+    return row_step<1>(row_step<2>(row_step<4>(row_step<8>(x))));
+}
+
 // BF16 bit pattern b (low 16 bits) is > 0: sign clear and not zero.
 __device__ __forceinline__ bool bf16_pos(uint32_t b) { return (b & 0x8000u) == 0u && (b & 0x7fffu) != 0u; }
 
@@ -401,8 +441,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                         a[j][r] = bf16_f(bf16_rne_nonan(fmaxf(acc[i][j][r] + bv[j][r], 0.f)));
                         zp = fmaf(a[j][r], shw[16 * j + 4 * g + r], zp);
                     }
-                zp += __shfl_xor(zp, 16);
-                zp += __shfl_xor(zp, 32);
+                zp = add_xor32(add_xor16(zp));
                 const float z = zp + hb9;
                 const float y = 1.0f / (1.0f + expf(-z));
                 if (MODE == 3) {
@@ -436,17 +475,14 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                     for (int r = 0; r < 4; ++r) hg[j][r] = fmaf(d, a[j][r], hg[j][r]);
             }
             // the 16 pixels (lanes n) of each row, then the wave's slot
+            if (MODE == 2) {
 #pragma unroll
-            for (int off = 8; off > 0; off >>= 1) {
-                if (MODE == 2) {
+                for (int j = 0; j < 4; ++j)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) hg[j][r] += __shfl_xor(hg[j][r], off);
-                    hbs += __shfl_xor(hbs, off);
-                }
-                hls += __shfl_xor(hls, off);
+                    for (int r = 0; r < 4; ++r) hg[j][r] = row_sum16(hg[j][r]);
+                hbs = row_sum16(hbs);
             }
+            hls = row_sum16(hls);
             if (n == 0) {
                 const int wv = tid >> 6;
                 if (MODE == 2) {

@@ -46,6 +46,23 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
     return (uint16_t)(u >> 16);
 }
 
+// Cross-lane sums on the VALU (no LDS round trip): x plus its partner lane.
+// add_xor8: partner l ^ 8 inside each 16-lane row (DPP rotate by 8);
+// add_xor16 / add_xor32: partner l ^ 16 / l ^ 32, from the gfx950 lane swaps
+// of a value with itself (the two results are each lane's own value and its
+// partner's, in some order; the sum is the same either way).
+__device__ __forceinline__ float add_xor8(float x) {
+    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float add_xor16(float x) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float add_xor32(float x) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
 // Load 4 consecutive channels of an activation row as FP32.
@@ -392,12 +409,16 @@ __global__ __launch_bounds__(kWg1Block) void k_wgrad1(const float* __restrict__ 
     asm volatile("" ::: "memory");
     if (stop) return;
     // slots of one wave: lanes cg, cg + LPP, ... hold the same channels
+    // (LPP is 8 or 16: an xor butterfly over the remaining lane bits)
 #pragma unroll
-    for (int off = LPP; off < 64; off <<= 1)
+    for (int r = 0; r < nacc; ++r)
 #pragma unroll
-        for (int r = 0; r < nacc; ++r)
-#pragma unroll
-            for (int e = 0; e < G; ++e) acc[r][e] += __shfl_xor(acc[r][e], off);
+        for (int e = 0; e < G; ++e) {
+            float v = acc[r][e];
+            if (LPP == 8) v = add_xor8(v);
+            v = add_xor16(v);
+            acc[r][e] = add_xor32(v);
+        }
     const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) < LPP) {
 #pragma unroll
