@@ -190,21 +190,22 @@ __global__ __launch_bounds__(256) void k_wgrad_f32(const float* __restrict__ src
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// Two FP32 values rounded to BF16 (to nearest, ties to even) and packed, the
+// first in bits 0-15: one gfx950 conversion instruction.  For every non-NaN
+// FP32 input it gives the same bits as the software rounding (add 0x7fff plus
+// the kept LSB, then truncate), denormals and ties included; a NaN stays NaN.
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    const f32x2_t f = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2_t));
 }
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) { return (uint16_t)pack_bf16x2(f, 0.f); }
 
 __device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
-// bf16_rne for a value that cannot be NaN (a ReLU output): the rounding add
-// alone is exact there, +inf and overflow included.
-__device__ __forceinline__ uint16_t bf16_rne_nonan(float f) {
-    const uint32_t u = __float_as_uint(f);
-    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
 
 
 
@@ -435,12 +436,17 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                 float a[4][4];
                 float zp = 0.f;
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < 4; ++j) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        a[j][r] = bf16_f(bf16_rne_nonan(fmaxf(acc[i][j][r] + bv[j][r], 0.f)));
-                        zp = fmaf(a[j][r], shw[16 * j + 4 * g + r], zp);
+                    for (int r = 0; r < 4; r += 2) {
+                        const uint32_t pk = pack_bf16x2(fmaxf(acc[i][j][r] + bv[j][r], 0.f),
+                                                        fmaxf(acc[i][j][r + 1] + bv[j][r + 1], 0.f));
+                        a[j][r] = __uint_as_float(pk << 16);
+                        a[j][r + 1] = __uint_as_float(pk & 0xffff0000u);
                     }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) zp = fmaf(a[j][r], shw[16 * j + 4 * g + r], zp);
+                }
                 zp = add_xor32(add_xor16(zp));
                 const float z = zp + hb9;
                 const float y = 1.0f / (1.0f + expf(-z));
@@ -460,8 +466,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                         float dv[4];
 #pragma unroll
                         for (int r = 0; r < 4; ++r) dv[r] = a[j][r] > 0.f ? d * shw[16 * j + 4 * g + r] : 0.f;
-                        const uint2 o = make_uint2((uint32_t)bf16_rne(dv[0]) | ((uint32_t)bf16_rne(dv[1]) << 16),
-                                                   (uint32_t)bf16_rne(dv[2]) | ((uint32_t)bf16_rne(dv[3]) << 16));
+                        const uint2 o = make_uint2(pack_bf16x2(dv[0], dv[1]), pack_bf16x2(dv[2], dv[3]));
                         *reinterpret_cast<uint2*>(out + pix * kWidth + 16 * j + 4 * g) = o;
                     }
                     if (g == 0) {
@@ -526,9 +531,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                     float v[4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) v[r] = (MODE == 0) ? fmaxf(acc[i][j][r] + bv[j][r], 0.f) : acc[i][j][r];
-                    // a ReLU output (MODE 0) is never NaN
-                    auto rnd = [](float x) { return (uint32_t)(MODE == 0 ? bf16_rne_nonan(x) : bf16_rne(x)); };
-                    uint2 o = make_uint2(rnd(v[0]) | (rnd(v[1]) << 16), rnd(v[2]) | (rnd(v[3]) << 16));
+                    uint2 o = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
                     if (MODE == 1) {
                         const uint32_t m = mk[i] >> (4 * j);
                         o.x &= ((m & 1u) ? 0x0000ffffu : 0u) | ((m & 2u) ? 0xffff0000u : 0u);

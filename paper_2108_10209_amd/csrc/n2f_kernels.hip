@@ -37,14 +37,19 @@ __device__ __forceinline__ bool last_block(unsigned* counter) {
     return s_last != 0;
 }
 
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) {              // inf or nan
-        return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    }
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// Two FP32 values rounded to BF16 (to nearest, ties to even) and packed, the
+// first in bits 0-15: one gfx950 conversion instruction.  For every non-NaN
+// FP32 input it gives the same bits as the software rounding (add 0x7fff plus
+// the kept LSB, then truncate), denormals and ties included; a NaN stays NaN.
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    const f32x2_t f = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2_t));
 }
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) { return (uint16_t)pack_bf16x2(f, 0.f); }
 
 // Cross-lane sums on the VALU (no LDS round trip): x plus its partner lane.
 // add_xor8: partner l ^ 8 inside each 16-lane row (DPP rotate by 8);
@@ -79,8 +84,8 @@ __device__ __forceinline__ void store4(void* base, long long idx, float4 v, bool
         return;
     }
     uint2 r;
-    r.x = (uint32_t)f32_to_bf16_rne(v.x) | ((uint32_t)f32_to_bf16_rne(v.y) << 16);
-    r.y = (uint32_t)f32_to_bf16_rne(v.z) | ((uint32_t)f32_to_bf16_rne(v.w) << 16);
+    r.x = pack_bf16x2(v.x, v.y);
+    r.y = pack_bf16x2(v.z, v.w);
     *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(base) + idx) = r;
 }
 
@@ -108,10 +113,10 @@ template <bool BF>
 __device__ __forceinline__ void store8(void* base, long long idx, const float (&v)[8]) {
     if constexpr (BF) {
         uint4 r;
-        r.x = (uint32_t)f32_to_bf16_rne(v[0]) | ((uint32_t)f32_to_bf16_rne(v[1]) << 16);
-        r.y = (uint32_t)f32_to_bf16_rne(v[2]) | ((uint32_t)f32_to_bf16_rne(v[3]) << 16);
-        r.z = (uint32_t)f32_to_bf16_rne(v[4]) | ((uint32_t)f32_to_bf16_rne(v[5]) << 16);
-        r.w = (uint32_t)f32_to_bf16_rne(v[6]) | ((uint32_t)f32_to_bf16_rne(v[7]) << 16);
+        r.x = pack_bf16x2(v[0], v[1]);
+        r.y = pack_bf16x2(v[2], v[3]);
+        r.z = pack_bf16x2(v[4], v[5]);
+        r.w = pack_bf16x2(v[6], v[7]);
         *reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(base) + idx) = r;
     } else {
         float4* q = reinterpret_cast<float4*>(reinterpret_cast<float*>(base) + idx);
@@ -314,19 +319,18 @@ __global__ __launch_bounds__(kBlock) void k_conv1(const float* __restrict__ in, 
             store4(out, p * kWidth + c0, a0, false);
             store4(out, p * kWidth + c1, a1, false);
         } else {
-            // each value rounded to BF16 once, for the store and the mask; a
-            // ReLU output is never NaN, and the rounding add carries +inf
-            // (and overflow) to the BF16 infinity without a special case
-            const float v[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+            // each value rounded to BF16 once, for the store and the mask
+            const uint32_t pk[4] = {pack_bf16x2(a0.x, a0.y), pack_bf16x2(a0.z, a0.w), pack_bf16x2(a1.x, a1.y),
+                                    pack_bf16x2(a1.z, a1.w)};
             uint32_t b[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const uint32_t u = __float_as_uint(v[e]);
-                b[e] = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+            for (int e = 0; e < 4; ++e) {
+                b[2 * e] = pk[e] & 0xffffu;
+                b[2 * e + 1] = pk[e] >> 16;
             }
             uint16_t* o = reinterpret_cast<uint16_t*>(out) + p * kWidth;
-            *reinterpret_cast<uint2*>(o + c0) = make_uint2(b[0] | (b[1] << 16), b[2] | (b[3] << 16));
-            *reinterpret_cast<uint2*>(o + c1) = make_uint2(b[4] | (b[5] << 16), b[6] | (b[7] << 16));
+            *reinterpret_cast<uint2*>(o + c0) = make_uint2(pk[0], pk[1]);
+            *reinterpret_cast<uint2*>(o + c1) = make_uint2(pk[2], pk[3]);
             if (mbits) {
                 uint32_t byte = 0;
 #pragma unroll
