@@ -382,10 +382,21 @@ n2f_status enqueue_train_step(n2f_run* r, int k, int pair) {
     };
     // forward with stash: act layer i holds a_{i+1}; BF16 fuses the head
     // into the last layer, whose a8 is then never stored
+    // BF16 with one channel also computes the first layer inside the layer-2
+    // forward (a1 and its mask are still stored for the backward pass)
     const int nplain = bf ? kLayers - 2 : kLayers - 1;
-    N2F_HIP(launch_conv1(in, pl.C, Wl(0), Bl(0), act_layer(r, 0, npix), mask_layer(r, 0, npix), bf, h, w, N.st, s));
-    N2F_HIP(timed(N2F_K_CONV_FWD, nplain, (long long)npix, s, [&]() -> hipError_t {
-        for (int l = 1; l <= nplain; ++l) {
+    const bool first_fused = bf && pl.C == 1;
+    if (first_fused) {
+        ConvFirst cf{in, Wl(0), Bl(0), (uint16_t*)act_layer(r, 0, npix), mask_layer(r, 0, npix)};
+        N2F_HIP(launch_conv_fwd_first(cf, fwdpk(1), Bl(1), act_layer(r, 1, npix), mask_layer(r, 1, npix), h, w, N.st,
+                                      s));
+    } else {
+        N2F_HIP(launch_conv1(in, pl.C, Wl(0), Bl(0), act_layer(r, 0, npix), mask_layer(r, 0, npix), bf, h, w, N.st,
+                             s));
+    }
+    const int lfirst = first_fused ? 2 : 1;
+    N2F_HIP(timed(N2F_K_CONV_FWD, nplain - lfirst + 1, (long long)npix, s, [&]() -> hipError_t {
+        for (int l = lfirst; l <= nplain; ++l) {
             hipError_t e = launch_conv_fwd(act_layer(r, l - 1, npix), fwdpk(l), Bl(l), act_layer(r, l, npix),
                                            mask_layer(r, l, npix), bf, h, w, N.st, s);
             if (e != hipSuccess) return e;
@@ -440,9 +451,16 @@ n2f_status enqueue_validate(n2f_run* r, int k) {
     };
     // BF16 fuses the head into the last layer (see enqueue_train_step)
     const int nplain = bf ? kLayers - 2 : kLayers - 1;
-    N2F_HIP(launch_conv1(r->xs, pl.C, N.theta + pt.off[0], Bl(0), buf(0), nullptr, bf, pl.H, pl.W, N.st, s));
-    N2F_HIP(timed(N2F_K_CONV_FWD, nplain, (long long)npix, s, [&]() -> hipError_t {
-        for (int l = 1; l <= nplain; ++l) {
+    const bool first_fused = bf && pl.C == 1;   // as in enqueue_train_step; a1 is not stored here
+    if (first_fused) {
+        ConvFirst cf{r->xs, N.theta + pt.off[0], Bl(0), nullptr, nullptr};
+        N2F_HIP(launch_conv_fwd_first(cf, pk(1), Bl(1), buf(1), nullptr, pl.H, pl.W, N.st, s));
+    } else {
+        N2F_HIP(launch_conv1(r->xs, pl.C, N.theta + pt.off[0], Bl(0), buf(0), nullptr, bf, pl.H, pl.W, N.st, s));
+    }
+    const int lfirst = first_fused ? 2 : 1;
+    N2F_HIP(timed(N2F_K_CONV_FWD, nplain - lfirst + 1, (long long)npix, s, [&]() -> hipError_t {
+        for (int l = lfirst; l <= nplain; ++l) {
             hipError_t e = launch_conv_fwd(buf(l - 1), pk(l), Bl(l), buf(l), nullptr, bf, pl.H, pl.W, N.st, s);
             if (e != hipSuccess) return e;
         }

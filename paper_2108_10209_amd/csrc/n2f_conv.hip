@@ -19,6 +19,8 @@
 // B operands stream from the packed weights in L2.
 #include "n2f_internal.h"
 
+#include <type_traits>
+
 namespace n2f {
 
 namespace {
@@ -229,6 +231,9 @@ constexpr int kHaloPix = kHalo * kHalo;               // 324 staged pixels
 constexpr int kHaloChunks = kHaloPix * 8;             // 16-byte chunks per halo
 constexpr int kPf = (kHaloChunks + 255) / 256;        // chunks each thread prefetches
 constexpr int kDppRowShl1 = 0x101;                    // DPP control: lane n takes lane n+1 of its row
+constexpr int kXHalo = kTile + 4;                     // first layer fused in: input halo side (20)
+constexpr int kXHaloPix = kXHalo * kXHalo;
+constexpr int kXPf = (kXHaloPix + 255) / 256;         // input values each thread prefetches
 
 __device__ __forceinline__ int swz(int pix, int q) { return pix * 64 + ((q ^ (pix & 7)) << 3); }
 
@@ -286,6 +291,76 @@ __device__ __forceinline__ T row_sum16(T x) {
 // BF16 bit pattern b (low 16 bits) is > 0: sign clear and not zero.
 __device__ __forceinline__ bool bf16_pos(uint32_t b) { return (b & 0x8000u) == 0u && (b & 0x7fffu) != 0u; }
 
+// The first layer (one input channel) on the 18 x 18 halo of a tile, into
+// the staged BF16 halo of the layer-2 forward.  Thread gt computes 8-channel
+// chunk q = gt % 8 of pixels gt / 8, gt / 8 + 32, ...: the bias plus the 9
+// taps in tap order (the order of the separate first-layer kernel), ReLU,
+// BF16.  Pixels outside the image stay zero (the 3x3 padding of a1).
+// Interior pixels inside the image also go to global memory (a1) with their
+// ReLU bit mask (the layout of the 3x3 kernels), whose 8 bytes the pixel's 8
+// lanes gather by DPP row shifts.
+__device__ __forceinline__ void first_layer_halo(uint16_t* halo, const float* sxg, const float* sw1, int gt, int x0,
+                                                 int y0, bool have, int h, int w, const ConvFirst& cf) {
+    const int q = gt & 7;
+    float wq[kTaps][8], bq[8];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) wq[t][e] = sw1[t * kWidth + 8 * q + e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) bq[e] = sw1[kTaps * kWidth + 8 * q + e];
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        const int idx = gt + 256 * u;
+        if (idx >= kHaloChunks) break;   // whole 8-lane pixel groups
+        const int pix = idx >> 3;
+        const int hy = pix / kHalo, hx = pix - hy * kHalo;
+        const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+        const bool inside = have && gy >= 0 && gy < h && gx >= 0 && gx < w;
+        float a[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[e] = bq[e];
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) {
+            const float xv = sxg[(hy + t / 3) * kXHalo + hx + t % 3];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a[e] = fmaf(xv, wq[t][e], a[e]);
+        }
+        uint4 c = make_uint4(pack_bf16x2(fmaxf(a[0], 0.f), fmaxf(a[1], 0.f)), pack_bf16x2(fmaxf(a[2], 0.f), fmaxf(a[3], 0.f)),
+                             pack_bf16x2(fmaxf(a[4], 0.f), fmaxf(a[5], 0.f)), pack_bf16x2(fmaxf(a[6], 0.f), fmaxf(a[7], 0.f)));
+        if (!inside) c = make_uint4(0u, 0u, 0u, 0u);
+        *reinterpret_cast<uint4*>(halo + swz(pix, q)) = c;
+        const bool interior = inside && hy >= 1 && hy <= kTile && hx >= 1 && hx <= kTile;
+        const long long gp = (long long)gy * w + gx;
+        if (cf.a1 && interior) *reinterpret_cast<uint4*>(cf.a1 + gp * kWidth + 8 * q) = c;
+        if (cf.m1) {
+            // channel 8q + e is bit 16 (2 (q & 1) + e / 4) + 4 (q / 2) + e % 4:
+            // the low word for even q, the high word for odd q
+            const uint32_t hv[8] = {c.x & 0xffffu, c.x >> 16, c.y & 0xffffu, c.y >> 16,
+                                    c.z & 0xffffu, c.z >> 16, c.w & 0xffffu, c.w >> 16};
+            uint32_t bits = 0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (bf16_pos(hv[e])) bits |= 1u << (16 * (e >> 2) + 4 * (q >> 1) + (e & 3));
+            uint32_t lo = (q & 1) ? 0u : bits, hi = (q & 1) ? bits : 0u;
+            // OR over the pixel's 8 lanes (aligned groups inside each 16-lane row)
+            auto gather = [&](auto shr) {
+                constexpr int sft = decltype(shr)::value;
+                const uint32_t l2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x110 + sft, 0xf, 0xf, false);
+                const uint32_t h2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x110 + sft, 0xf, 0xf, false);
+                if (q >= sft) {   // row_shr:sft stays inside the 8-lane group
+                    lo |= l2;
+                    hi |= h2;
+                }
+            };
+            gather(std::integral_constant<int, 1>{});
+            gather(std::integral_constant<int, 2>{});
+            gather(std::integral_constant<int, 4>{});
+            if (q == 7 && interior) reinterpret_cast<uint2*>(cf.m1)[gp] = make_uint2(lo, hi);
+        }
+    }
+}
+
 // ReLU bit masks of BF16 activations: 64 bits per pixel, bit 16 g + 4 j + r
 // for channel 16 j + 4 g + r (g, r < 4), so each of the four lanes that hold
 // a pixel's MFMA outputs owns one 16-bit word.  Bit set = the stored BF16
@@ -301,7 +376,10 @@ template <int MODE>
 __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
                                                    const float* __restrict__ bias, uint16_t* __restrict__ mbits,
                                                    uint16_t* __restrict__ out, int h, int w, int nblk,
-                                                   const DevState* st, ConvHead hd) {
+                                                   const DevState* st, ConvHead hd, ConvFirst cf) {
+    constexpr bool kHead = (MODE == 2 || MODE == 3);   // head in the epilogue
+    constexpr bool kFirst = (MODE == 4);               // first layer computed into the halo
+    constexpr bool kFwd = (MODE == 0 || MODE == 4);    // plain forward epilogue
     // nblk = gridDim.x, passed among the first arguments: reading the
     // hidden grid size after the head arguments costs a second round trip
     // of scalar loads before the first global load
@@ -314,6 +392,8 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
     __shared__ float shw[kHeadN];          // MODE 2: head weights and bias
     __shared__ float shred[8][kHeadN];     // MODE 2: per-wave dW9, db9 sums
     __shared__ double slred[8];            // MODE 2: per-wave BCE sums
+    __shared__ float sx[2][kXHaloPix];     // MODE 4: input halo (20 x 20) of each group's tile
+    __shared__ float sw1[kTaps * kWidth + kWidth];   // MODE 4: first-layer weights [t][co], then biases
     const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
     const int lane = tid & 63, wq = gt >> 6;
     const int g = lane >> 4, n = lane & 15;
@@ -345,11 +425,38 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                 pf[u] = *reinterpret_cast<const uint4*>(in + ((long long)gy * w + gx) * kWidth + 8 * q);
         }
     };
-    if (iters > 0) fetch(2 * blockIdx.x + grp);
-    const float hwv = (MODE >= 2 && tid < kHeadN) ? hd.w9[tid] : 0.f;
+    // MODE 4: the input halo (tile + 2 pixels each side) of the next tile,
+    // two values per thread
+    float xf[kXPf];
+    auto fetch_x = [&](int tile) {
+        const bool have = tile < ntiles;
+        const int x0 = have ? (tile % tiles_x) * kTile : 0, y0 = have ? (tile / tiles_x) * kTile : 0;
+#pragma unroll
+        for (int u = 0; u < kXPf; ++u) {
+            const int idx = gt + 256 * u;
+            const int hy = idx / kXHalo, hx = idx - hy * kXHalo;
+            const int gy = y0 - 2 + hy, gx = x0 - 2 + hx;
+            xf[u] = 0.f;
+            if (have && idx < kXHaloPix && gy >= 0 && gy < h && gx >= 0 && gx < w) xf[u] = cf.x[(long long)gy * w + gx];
+        }
+    };
+    if (iters > 0) {
+        if constexpr (kFirst) fetch_x(2 * blockIdx.x + grp);
+        else fetch(2 * blockIdx.x + grp);
+    }
+    float w1v[2] = {0.f, 0.f};
+    if constexpr (kFirst) {
+        w1v[0] = cf.w1[tid];   // 576 weights, then 64 biases
+        if (tid < kTaps * kWidth + kWidth - 512) w1v[1] = (tid + 512 < kTaps * kWidth) ? cf.w1[tid + 512] : cf.b1[tid + 512 - kTaps * kWidth];
+    }
+    const float hwv = (kHead && tid < kHeadN) ? hd.w9[tid] : 0.f;
     asm volatile("" ::: "memory");   // keeps those loads ahead of the test
     if (stop) return;
-    if (MODE >= 2) {
+    if constexpr (kFirst) {
+        sw1[tid] = w1v[0];
+        if (tid < kTaps * kWidth + kWidth - 512) sw1[tid + 512] = w1v[1];
+    }
+    if (kHead) {
         if (tid < kHeadN) shw[tid] = hwv;
         for (int i = tid; i < 8 * kHeadN; i += 512) (&shred[0][0])[i] = 0.f;
         if (tid < 8) slred[tid] = 0.0;
@@ -361,13 +468,25 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
         const int tile = 2 * blockIdx.x + grp + k * stride;
         const bool have = tile < ntiles;
         const int x0 = have ? (tile % tiles_x) * kTile : 0, y0 = have ? (tile / tiles_x) * kTile : 0;
+        if constexpr (kFirst) {
 #pragma unroll
-        for (int u = 0; u < kPf; ++u) {
-            const int idx = gt + 256 * u;
-            if (idx < kHaloChunks) *reinterpret_cast<uint4*>(halo + swz(idx >> 3, idx & 7)) = pf[u];
+            for (int u = 0; u < kXPf; ++u) {
+                const int idx = gt + 256 * u;
+                if (idx < kXHaloPix) sx[grp][idx] = xf[u];
+            }
+            __syncthreads();
+            if (k + 1 < iters) fetch_x(tile + stride);   // in flight during the rest of the tile
+            first_layer_halo(halo, sx[grp], sw1, gt, x0, y0, have, h, w, cf);
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int u = 0; u < kPf; ++u) {
+                const int idx = gt + 256 * u;
+                if (idx < kHaloChunks) *reinterpret_cast<uint4*>(halo + swz(idx >> 3, idx & 7)) = pf[u];
+            }
+            __syncthreads();
+            if (k + 1 < iters) fetch(tile + stride);   // in flight during the MFMA loop
         }
-        __syncthreads();
-        if (k + 1 < iters) fetch(tile + stride);   // in flight during the MFMA loop
 
         floatx4 acc[4][4];
 #pragma unroll
@@ -411,7 +530,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
         }
 
         // D row = channel 16j + 4g + r, column = pixel x = n of tile row 4wq + i.
-        if (MODE >= 2 && have) {
+        if (kHead && have) {
             const int gx = x0 + n;
             float hg[4][4];
 #pragma unroll
@@ -502,9 +621,9 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                 }
             }
         }
-        if (MODE < 2 && have) {
+        if (!kHead && have) {
             float bv[4][4];
-            if (MODE == 0) {
+            if (kFwd) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -530,7 +649,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                 for (int j = 0; j < 4; ++j) {
                     float v[4];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] = (MODE == 0) ? fmaxf(acc[i][j][r] + bv[j][r], 0.f) : acc[i][j][r];
+                    for (int r = 0; r < 4; ++r) v[r] = kFwd ? fmaxf(acc[i][j][r] + bv[j][r], 0.f) : acc[i][j][r];
                     uint2 o = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
                     if (MODE == 1) {
                         const uint32_t m = mk[i] >> (4 * j);
@@ -544,7 +663,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                     }
                     *reinterpret_cast<uint2*>(out + base + 16 * j) = o;
                 }
-                if (MODE == 0 && mbits) mbits[((long long)gy * w + gx) * 4 + g] = (uint16_t)word;
+                if (kFwd && mbits) mbits[((long long)gy * w + gx) * 4 + g] = (uint16_t)word;
             }
         }
         __syncthreads();   // the next tile's halo overwrites this buffer
@@ -836,7 +955,7 @@ hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, v
     if (bf16) {
         const int nb = conv_bf16_blocks(h, w);
         hipLaunchKernelGGL(k_conv_bf16<0>, dim3(nb), dim3(512), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
-                           mbits, (uint16_t*)out, h, w, nb, st, ConvHead{});
+                           mbits, (uint16_t*)out, h, w, nb, st, ConvHead{}, ConvFirst{});
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_conv_f32<0>, grid, dim3(256), 0, s, (const float*)in, (const float*)wpk, bias,
@@ -848,7 +967,15 @@ hipError_t launch_conv_fwd_head(const void* in, const void* wpk, const float* bi
                                 int nblk, int h, int w, const DevState* st, hipStream_t s) {
     if (nblk < conv_bf16_blocks(h, w) || nblk > 256) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_conv_bf16<2>, dim3(nblk), dim3(512), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
-                       (uint16_t*)nullptr, (uint16_t*)d8, h, w, nblk, st, hd);
+                       (uint16_t*)nullptr, (uint16_t*)d8, h, w, nblk, st, hd, ConvFirst{});
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_fwd_first(const ConvFirst& cf, const void* wpk, const float* bias, void* out,
+                                 uint16_t* mbits, int h, int w, const DevState* st, hipStream_t s) {
+    const int nb = conv_bf16_blocks(h, w);
+    hipLaunchKernelGGL(k_conv_bf16<4>, dim3(nb), dim3(512), 0, s, (const uint16_t*)nullptr, (const uint16_t*)wpk, bias,
+                       mbits, (uint16_t*)out, h, w, nb, st, ConvHead{}, cf);
     return hipGetLastError();
 }
 
@@ -856,7 +983,7 @@ hipError_t launch_conv_fwd_val(const void* in, const void* wpk, const float* bia
                                DevState* st, double* vtrace, hipStream_t s) {
     const int nb = conv_bf16_blocks(h, w);
     hipLaunchKernelGGL(k_conv_bf16<3>, dim3(nb), dim3(512), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
-                       (uint16_t*)nullptr, (uint16_t*)nullptr, h, w, nb, (const DevState*)st, hd);
+                       (uint16_t*)nullptr, (uint16_t*)nullptr, h, w, nb, (const DevState*)st, hd, ConvFirst{});
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_decide(hd.lpart, nb, (long long)h * w, st, vtrace, s);
@@ -869,7 +996,7 @@ hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, v
         const int nb = conv_bf16_blocks(h, w);
         hipLaunchKernelGGL(k_conv_bf16<1>, dim3(nb), dim3(512), 0, s, (const uint16_t*)dlt, (const uint16_t*)wpk,
                            (const float*)nullptr, (uint16_t*)const_cast<void*>(mask), (uint16_t*)out, h, w, nb, st,
-                           ConvHead{});
+                           ConvHead{}, ConvFirst{});
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_conv_f32<1>, grid, dim3(256), 0, s, (const float*)dlt, (const float*)wpk,

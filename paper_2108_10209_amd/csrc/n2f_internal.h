@@ -96,6 +96,19 @@ struct ConvHead {
     int C, k;            // target channels, and the one this network predicts
     float invP;          // training: 1 / pixels of the pair
 };
+// BF16 path, one input channel: the first layer (3x3, 1 -> 64, bias, ReLU)
+// computed inside the layer-2 forward kernel from a 20 x 20 input halo per
+// tile, straight into its staged LDS halo; a1 and its ReLU bit mask are
+// still stored (the backward pass reads them) unless the pointers are NULL.
+struct ConvFirst {
+    const float* x;      // input image, h x w, one channel
+    const float* w1;     // first-layer weights [t][co] (9 x 64)
+    const float* b1;     // first-layer biases (64)
+    uint16_t* a1;        // a1 out (BF16, h x w x 64), or NULL
+    uint16_t* m1;        // a1's ReLU bit mask out (8 bytes per pixel), or NULL
+};
+hipError_t launch_conv_fwd_first(const ConvFirst& cf, const void* wpk, const float* bias, void* out,
+                                 uint16_t* mbits, int h, int w, const DevState* st, hipStream_t s);
 int head_fused_blocks(int h, int w);   // blocks of the BF16 convolution grid at h x w
 hipError_t launch_conv_fwd_head(const void* in, const void* wpk, const float* bias, void* d8, const ConvHead& hd,
                                 int nblk, int h, int w, const DevState* st, hipStream_t s);
