@@ -630,6 +630,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                     for (int r = 0; r < 4; ++r) bv[j][r] = bias[16 * j + 4 * g + r];
             }
             const int gx = x0 + n;
+            const bool want_mask = kFwd && mbits != nullptr;   // the forward's mask words (not in validation)
             // the data gradient's ReLU mask words of this lane's 4 pixels
             uint32_t mk[4];
             if (MODE == 1) {
@@ -655,15 +656,17 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                         const uint32_t m = mk[i] >> (4 * j);
                         o.x &= ((m & 1u) ? 0x0000ffffu : 0u) | ((m & 2u) ? 0xffff0000u : 0u);
                         o.y &= ((m & 4u) ? 0x0000ffffu : 0u) | ((m & 8u) ? 0xffff0000u : 0u);
-                    } else {
-                        word |= (bf16_pos(o.x & 0xffffu) ? 1u : 0u) << (4 * j);
-                        word |= (bf16_pos(o.x >> 16) ? 2u : 0u) << (4 * j);
-                        word |= (bf16_pos(o.y & 0xffffu) ? 4u : 0u) << (4 * j);
-                        word |= (bf16_pos(o.y >> 16) ? 8u : 0u) << (4 * j);
+                    } else if (want_mask) {
+                        // a BF16 value is > 0 iff its bits, as the high half of
+                        // a signed 32-bit integer, are > 0 (-0 is not)
+                        word |= ((int)(o.x << 16) > 0 ? 1u : 0u) << (4 * j);
+                        word |= ((int)(o.x & 0xffff0000u) > 0 ? 2u : 0u) << (4 * j);
+                        word |= ((int)(o.y << 16) > 0 ? 4u : 0u) << (4 * j);
+                        word |= ((int)(o.y & 0xffff0000u) > 0 ? 8u : 0u) << (4 * j);
                     }
                     *reinterpret_cast<uint2*>(out + base + 16 * j) = o;
                 }
-                if (kFwd && mbits) mbits[((long long)gy * w + gx) * 4 + g] = (uint16_t)word;
+                if (want_mask) mbits[((long long)gy * w + gx) * 4 + g] = (uint16_t)word;
             }
         }
         __syncthreads();   // the next tile's halo overwrites this buffer
