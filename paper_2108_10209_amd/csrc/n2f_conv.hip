@@ -394,6 +394,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
     __shared__ double slred[8];            // MODE 2: per-wave BCE sums
     __shared__ float sx[2][kXHaloPix];     // MODE 4: input halo (20 x 20) of each group's tile
     __shared__ float sw1[kTaps * kWidth + kWidth];   // MODE 4: first-layer weights [t][co], then biases
+    __shared__ float sbias[kWidth];        // forward and head modes: the layer's biases
     const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
     const int lane = tid & 63, wq = gt >> 6;
     const int g = lane >> 4, n = lane & 15;
@@ -450,8 +451,10 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
         if (tid < kTaps * kWidth + kWidth - 512) w1v[1] = (tid + 512 < kTaps * kWidth) ? cf.w1[tid + 512] : cf.b1[tid + 512 - kTaps * kWidth];
     }
     const float hwv = (kHead && tid < kHeadN) ? hd.w9[tid] : 0.f;
+    const float bvv = (MODE != 1 && tid < kWidth) ? bias[tid] : 0.f;
     asm volatile("" ::: "memory");   // keeps those loads ahead of the test
     if (stop) return;
+    if (MODE != 1 && tid < kWidth) sbias[tid] = bvv;
     if constexpr (kFirst) {
         sw1[tid] = w1v[0];
         if (tid < kTaps * kWidth + kWidth - 512) sw1[tid + 512] = w1v[1];
@@ -488,6 +491,16 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
             if (k + 1 < iters) fetch(tile + stride);   // in flight during the MFMA loop
         }
 
+        // the data gradient's ReLU mask words of this lane's 4 pixels load
+        // before the MFMA loop, so their latency hides under it
+        uint32_t mk[4];
+        if (MODE == 1) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int gy = y0 + 4 * wq + i, gx = x0 + n;
+                mk[i] = (have && gy < h && gx < w) ? mbits[((long long)gy * w + gx) * 4 + g] : 0u;
+            }
+        }
         floatx4 acc[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -543,7 +556,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) bv[j][r] = bias[16 * j + 4 * g + r];
+                for (int r = 0; r < 4; ++r) bv[j][r] = sbias[16 * j + 4 * g + r];
             const float hb9 = shw[kWidth];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -627,19 +640,10 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) bv[j][r] = bias[16 * j + 4 * g + r];
+                    for (int r = 0; r < 4; ++r) bv[j][r] = sbias[16 * j + 4 * g + r];
             }
             const int gx = x0 + n;
             const bool want_mask = kFwd && mbits != nullptr;   // the forward's mask words (not in validation)
-            // the data gradient's ReLU mask words of this lane's 4 pixels
-            uint32_t mk[4];
-            if (MODE == 1) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int gy = y0 + 4 * wq + i;
-                    mk[i] = (gy < h && gx < w) ? mbits[((long long)gy * w + gx) * 4 + g] : 0u;
-                }
-            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int gy = y0 + 4 * wq + i;
