@@ -19,8 +19,6 @@
 // B operands stream from the packed weights in L2.
 #include "n2f_internal.h"
 
-#include <type_traits>
-
 namespace n2f {
 
 namespace {
@@ -297,8 +295,8 @@ __device__ __forceinline__ bool bf16_pos(uint32_t b) { return (b & 0x8000u) == 0
 // taps in tap order (the order of the separate first-layer kernel), ReLU,
 // BF16.  Pixels outside the image stay zero (the 3x3 padding of a1).
 // Interior pixels inside the image also go to global memory (a1) with their
-// ReLU bit mask (the layout of the 3x3 kernels), whose 8 bytes the pixel's 8
-// lanes gather by DPP row shifts.
+// ReLU bit mask (the layout of the 3x3 kernels), whose two words the pixel's
+// 8 lanes gather by DPP row shifts.
 __device__ __forceinline__ void first_layer_halo(uint16_t* halo, const float* sxg, const float* sw1, int gt, int x0,
                                                  int y0, bool have, int h, int w, const ConvFirst& cf) {
     const int q = gt & 7;
@@ -335,28 +333,27 @@ __device__ __forceinline__ void first_layer_halo(uint16_t* halo, const float* sx
         if (cf.a1 && interior) *reinterpret_cast<uint4*>(cf.a1 + gp * kWidth + 8 * q) = c;
         if (cf.m1) {
             // channel 8q + e is bit 16 (2 (q & 1) + e / 4) + 4 (q / 2) + e % 4:
-            // the low word for even q, the high word for odd q
-            const uint32_t hv[8] = {c.x & 0xffffu, c.x >> 16, c.y & 0xffffu, c.y >> 16,
-                                    c.z & 0xffffu, c.z >> 16, c.w & 0xffffu, c.w >> 16};
+            // within the low word (even q) or the high word (odd q), bit
+            // 16 (e / 4) + e % 4, shifted by 4 (q / 2).  A BF16 value is > 0
+            // iff its bits, as the high half of a signed 32-bit integer, are.
+            const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
             uint32_t bits = 0;
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if (bf16_pos(hv[e])) bits |= 1u << (16 * (e >> 2) + 4 * (q >> 1) + (e & 3));
-            uint32_t lo = (q & 1) ? 0u : bits, hi = (q & 1) ? bits : 0u;
-            // OR over the pixel's 8 lanes (aligned groups inside each 16-lane row)
-            auto gather = [&](auto shr) {
-                constexpr int sft = decltype(shr)::value;
-                const uint32_t l2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x110 + sft, 0xf, 0xf, false);
-                const uint32_t h2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x110 + sft, 0xf, 0xf, false);
-                if (q >= sft) {   // row_shr:sft stays inside the 8-lane group
-                    lo |= l2;
-                    hi |= h2;
-                }
-            };
-            gather(std::integral_constant<int, 1>{});
-            gather(std::integral_constant<int, 2>{});
-            gather(std::integral_constant<int, 4>{});
-            if (q == 7 && interior) reinterpret_cast<uint2*>(cf.m1)[gp] = make_uint2(lo, hi);
+            for (int e2 = 0; e2 < 4; ++e2) {
+                const int e = 2 * e2;
+                bits |= ((int)(cw[e2] << 16) > 0 ? 1u : 0u) << (16 * (e >> 2) + (e & 3));
+                bits |= ((int)(cw[e2] & 0xffff0000u) > 0 ? 1u : 0u) << (16 * ((e + 1) >> 2) + ((e + 1) & 3));
+            }
+            bits <<= 4 * (q >> 1);
+            // OR over the lanes of the same parity (row_shr 2, 4 stay inside
+            // the pixel's aligned 8-lane group), then lane 7 takes lane 6's
+            // low word (row_shr 1)
+            uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x112, 0xf, 0xf, false);
+            if (q >= 2) bits |= t;
+            t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x114, 0xf, 0xf, false);
+            if (q >= 4) bits |= t;
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x111, 0xf, 0xf, false);
+            if (q == 7 && interior) reinterpret_cast<uint2*>(cf.m1)[gp] = make_uint2(lo, bits);
         }
     }
 }
@@ -395,6 +392,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
     __shared__ float sx[2][kXHaloPix];     // MODE 4: input halo (20 x 20) of each group's tile
     __shared__ float sw1[kTaps * kWidth + kWidth];   // MODE 4: first-layer weights [t][co], then biases
     __shared__ float sbias[kWidth];        // forward and head modes: the layer's biases
+    __shared__ float stgt[2][kTile * kTile];   // head modes: each group's tile of targets
     const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
     const int lane = tid & 63, wq = gt >> 6;
     const int g = lane >> 4, n = lane & 15;
@@ -491,6 +489,13 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
             if (k + 1 < iters) fetch(tile + stride);   // in flight during the MFMA loop
         }
 
+        // head modes: target pixel gt of the tile, loaded before the MFMA loop
+        // and staged in LDS after it
+        float tq = 0.f;
+        if (kHead) {
+            const int gy = y0 + (gt >> 4), gx = x0 + (gt & 15);
+            if (have && gy < h && gx < w) tq = hd.tgt[((long long)gy * w + gx) * hd.C + hd.k];
+        }
         // the data gradient's ReLU mask words of this lane's 4 pixels load
         // before the MFMA loop, so their latency hides under it
         uint32_t mk[4];
@@ -542,6 +547,10 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
             }
         }
 
+        if (kHead) {
+            stgt[grp][gt] = tq;
+            __syncthreads();
+        }
         // D row = channel 16j + 4g + r, column = pixel x = n of tile row 4wq + i.
         if (kHead && have) {
             const int gx = x0 + n;
@@ -563,7 +572,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
                 const int gy = y0 + 4 * wq + i;
                 const bool valid = gy < h && gx < w;
                 const long long pix = (long long)gy * w + gx;
-                const float t = valid ? hd.tgt[pix * hd.C + hd.k] : 0.f;
+                const float t = stgt[grp][(4 * wq + i) * kTile + n];   // 0 outside the image
                 // a8 as the BF16 value the forward would store
                 float a[4][4];
                 float zp = 0.f;
