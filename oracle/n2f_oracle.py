@@ -29,7 +29,12 @@ self-contradictory the reading taken here is stated in the function:
 * stop once 100 epochs pass with no strict improvement of the best validation
   score and output the mean of the last 100 validation outputs, which are the
   100 outputs after the best epoch; outputs are mapped back by the inverse of
-  the standardisation.
+  the standardisation;
+* ablations (Methods, Ablation Study; Table 1): the 2x2-block ("Quad")
+  downsamples, paired along the block diagonals in both directions (the
+  pairing is not stated), and the "Exact" targets, from which the known
+  signal difference between target and input is removed (the clean image
+  standardised with the noisy image's extremes).
 
 Parity pins for every function live in tests/test_oracle_*.py.
 """
@@ -138,11 +143,69 @@ def checkerboard_left(x: np.ndarray):
     return xe, xo
 
 
-def training_pairs(x_std: np.ndarray):
-    """The four (input, target) pairs of the Methods table, in table order."""
-    ue, uo = checkerboard_up(x_std)
-    le, lo = checkerboard_left(x_std)
-    return [(ue, uo), (uo, ue), (le, lo), (lo, le)]
+def quad_downsample(x: np.ndarray):
+    """2x2-block downsamples of the ablation study (Methods, Ablation Study;
+    Table 1, "Quad").
+
+    The image is cut into 2x2 blocks; the four images hold the top-left,
+    top-right, bottom-left and bottom-right pixel of every block:
+    TL(i, j) = x(2i, 2j), TR(i, j) = x(2i, 2j + 1), BL(i, j) = x(2i + 1, 2j),
+    BR(i, j) = x(2i + 1, 2j + 1).  Odd sizes drop the last row/column, as for
+    the checkerboard.  Shapes (C, H'/2, W'/2).
+    """
+    C, H, W = x.shape
+    Hc, Wc = even_extent(H, W)
+    tl = np.empty((C, Hc // 2, Wc // 2), dtype=x.dtype)
+    tr = np.empty_like(tl)
+    bl = np.empty_like(tl)
+    br = np.empty_like(tl)
+    for i in range(Hc // 2):
+        for j in range(Wc // 2):
+            tl[:, i, j] = x[:, 2 * i, 2 * j]
+            tr[:, i, j] = x[:, 2 * i, 2 * j + 1]
+            bl[:, i, j] = x[:, 2 * i + 1, 2 * j]
+            br[:, i, j] = x[:, 2 * i + 1, 2 * j + 1]
+    return tl, tr, bl, br
+
+
+DOWNSAMPLES = ("checkerboard", "quad")
+
+
+def training_pairs(x_std: np.ndarray, downsample: str = "checkerboard"):
+    """The four (input, target) pairs of one epoch, in table order.
+
+    checkerboard: the Methods table, up-even -> up-odd, up-odd -> up-even,
+    left-even -> left-odd, left-odd -> left-even.
+    quad: the paper does not say how its four 2x2-block images are paired.
+    Reading: the two diagonals of a block, both ways: TL -> BR, BR -> TL,
+    TR -> BL, BL -> TR.  Input and target of a pair then sit at a shared
+    block corner, and an epoch still has four steps.
+    """
+    if downsample == "checkerboard":
+        ue, uo = checkerboard_up(x_std)
+        le, lo = checkerboard_left(x_std)
+        return [(ue, uo), (uo, ue), (le, lo), (lo, le)]
+    if downsample == "quad":
+        tl, tr, bl, br = quad_downsample(x_std)
+        return [(tl, br), (br, tl), (tr, bl), (bl, tr)]
+    raise ValueError(f"unknown downsample {downsample!r}")
+
+
+def exact_pairs(x_std: np.ndarray, s_std: np.ndarray, downsample: str = "checkerboard"):
+    """Training pairs of the "Exact" ablation (Methods, Ablation Study;
+    Table 1), which needs the clean image.
+
+    The downsampling argument of the Theoretical Background writes a pair's
+    target as s_in + n_tgt + (s_tgt - s_in) and drops the last term as small
+    (the ODD approximation).  The ablation removes that term from the
+    target with the known signal, so the target becomes
+    x_tgt - (s_tgt - s_in) = s_in + n_tgt.  Reading: s_std is the clean image
+    under the same affine standardisation as the noisy input (the noisy
+    image's minimum and maximum), so that the term is in the target's units.
+    """
+    px = training_pairs(x_std, downsample)
+    ps = training_pairs(s_std, downsample)
+    return [(xa, xb - (sb - sa)) for (xa, xb), (sa, sb) in zip(px, ps)]
 
 
 # ---------------------------------------------------------------------------
@@ -376,20 +439,27 @@ class RunResult:
 
 
 def denoise(x: np.ndarray, theta0: np.ndarray, h: Hyper = Hyper(), pair_order=(0, 1, 2, 3),
-            trace=None) -> RunResult:
+            trace=None, downsample: str = "checkerboard", clean=None) -> RunResult:
     """The per-image loop of the paper, one network per output channel.
 
     x: noisy image (C, H, W); theta0: (C, n_params) initial weights.
     Each epoch feeds the four pairs one at a time (one Adam step each), then
     validates on the full image.  `trace`, if given, is called as
     trace(k, epoch, pair, state, grad, loss) after every step.
+    `downsample` picks the pairs (`training_pairs`); a clean image `clean`
+    (C, H, W) switches to the targets of the "Exact" ablation
+    (`exact_pairs`).  Validation is the same in every variant.
     """
     x = np.asarray(x, np.float64)
     C, H, W = x.shape
     x_std, lo, hi = standardize(x)
     if x_std is None:
         return RunResult(x.copy(), x.copy(), [0] * C, [0] * C, [[] for _ in range(C)], [False] * C, True)
-    pairs = training_pairs(x_std)
+    if clean is None:
+        pairs = training_pairs(x_std, downsample)
+    else:
+        s_std = (np.asarray(clean, np.float64) - lo) / (hi - lo)
+        pairs = exact_pairs(x_std, s_std, downsample)
     ys = np.empty((C, H, W))
     epochs, best_e, hist, capped = [], [], [], []
     for k in range(C):

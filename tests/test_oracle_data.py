@@ -171,3 +171,86 @@ def test_init_params_bounds():
             assert np.abs(seg).max() > 0.9 * bound
         o += n
     assert synth.n_params(3) == 260353
+
+
+# ---------------------------------------------------------------------------
+# Ablations (Methods, Ablation Study; Table 1): 2x2-block downsampling and
+# the "Exact" targets
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", json.load(open(os.path.join(GOLDEN, "quad_worked.json")))["cases"])
+def test_quad_worked_example(case):
+    tl, tr, bl, br = O.quad_downsample(_grid(case["H"], case["W"]))
+    np.testing.assert_array_equal(tl[0], case["tl"])
+    np.testing.assert_array_equal(tr[0], case["tr"])
+    np.testing.assert_array_equal(bl[0], case["bl"])
+    np.testing.assert_array_equal(br[0], case["br"])
+
+
+@pytest.mark.parametrize("H,W", [(4, 4), (6, 8), (3, 5), (5, 4), (7, 9), (2, 2), (64, 64), (33, 17)])
+def test_quad_partition_and_neighbours(H, W):
+    """The four images take every pixel of the even extent once; on an index
+    image the block neighbours differ by fixed offsets; TL and BR hold the
+    checkerboard's even class, TR and BL its odd class."""
+    C = 2
+    x = synth.index_image(C, H, W).astype(np.float64)
+    Hc, Wc = O.even_extent(H, W)
+    tl, tr, bl, br = O.quad_downsample(x)
+    for a in (tl, tr, bl, br):
+        assert a.shape == (C, Hc // 2, Wc // 2)
+    ids = np.concatenate([a.ravel() for a in (tl, tr, bl, br)]).astype(np.int64)
+    np.testing.assert_array_equal(np.sort(ids), np.sort(x[:, :Hc, :Wc].ravel().astype(np.int64)))
+    # index = c*H*W + row*W + col: right neighbour +1, lower neighbour +W
+    np.testing.assert_array_equal(tr - tl, np.ones_like(tl))
+    np.testing.assert_array_equal(bl - tl, np.full_like(tl, W))
+    np.testing.assert_array_equal(br - tl, np.full_like(tl, W + 1))
+    # block (i, j) starts at pixel (2i, 2j)
+    i, j = np.meshgrid(np.arange(Hc // 2), np.arange(Wc // 2), indexing="ij")
+    for c in range(C):
+        np.testing.assert_array_equal(tl[c], c * H * W + 2 * i * W + 2 * j)
+    ue, uo = O.checkerboard_up(x)
+    np.testing.assert_array_equal(np.sort(np.concatenate([tl.ravel(), br.ravel()])), np.sort(ue.ravel()))
+    np.testing.assert_array_equal(np.sort(np.concatenate([tr.ravel(), bl.ravel()])), np.sort(uo.ravel()))
+
+
+def test_quad_training_pairs_are_block_diagonals():
+    H, W = 6, 8
+    x = synth.index_image(1, H, W).astype(np.float64)
+    pairs = O.training_pairs(x, "quad")
+    # target minus input on an index image: +-(W+1) along the main diagonal,
+    # +-(W-1) along the other one
+    offs = [W + 1, -(W + 1), W - 1, -(W - 1)]
+    for (a, b), d in zip(pairs, offs):
+        assert a.shape == b.shape == (1, H // 2, W // 2)
+        np.testing.assert_array_equal(b - a, np.full_like(a, d))
+    with pytest.raises(ValueError):
+        O.training_pairs(x, "hexagonal")
+
+
+@pytest.mark.parametrize("downsample", O.DOWNSAMPLES)
+def test_exact_targets_are_signal_plus_target_noise(downsample):
+    """With x = s + n, the Exact target of a pair is s_in + n_tgt (in the
+    standardised units), built here from the parts instead of from x."""
+    rng = np.random.default_rng(7)
+    C, H, W = 2, 10, 12
+    s = rng.uniform(0.0, 1.0, (C, H, W))
+    n = 0.1 * rng.standard_normal((C, H, W))
+    x = s + n
+    x_std, lo, hi = O.standardize(x)
+    pairs = O.exact_pairs(x_std, (s - lo) / (hi - lo), downsample)
+    s_pairs = O.training_pairs(s, downsample)
+    n_pairs = O.training_pairs(n, downsample)
+    for (inp, tgt), (s_in, _), (_, n_tgt) in zip(pairs, s_pairs, n_pairs):
+        np.testing.assert_allclose(tgt, (s_in - lo) / (hi - lo) + n_tgt / (hi - lo), rtol=0, atol=1e-14)
+    # inputs are the noisy image's, untouched
+    for (inp, _), (xa, _) in zip(pairs, O.training_pairs(x_std, downsample)):
+        np.testing.assert_array_equal(inp, xa)
+
+
+def test_exact_targets_without_noise_equal_inputs():
+    """Noise-free image: the signal difference is all there is, so every
+    Exact target is its input."""
+    x = synth.index_image(1, 8, 6).astype(np.float64)
+    x_std, lo, hi = O.standardize(x)
+    for downsample in O.DOWNSAMPLES:
+        for a, b in O.exact_pairs(x_std, x_std, downsample):
+            np.testing.assert_allclose(b, a, rtol=0, atol=1e-15)

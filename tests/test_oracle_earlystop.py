@@ -123,3 +123,33 @@ def test_denoise_small_image_improves_psnr():
     assert r.epochs == [8]
     assert synth.psnr(r.y, clean) > synth.psnr(noisy, clean) + 0.5
     assert all(b < a for a, b in zip(r.history[0][:3], r.history[0][1:4]))
+
+
+@pytest.mark.parametrize("downsample,exact", [("quad", False), ("checkerboard", True), ("quad", True)])
+def test_denoise_ablation_variants_train_on_their_pairs(downsample, exact):
+    """The ablation switches of `denoise` change the training pairs only:
+    the same run rebuilt step by step from `training_pairs` / `exact_pairs`
+    gives the same output."""
+    h = O.Hyper(width=4, n_layers=2, fixed_epochs=2)
+    x, th = _tiny_run(h, 5)
+    rng = np.random.default_rng(11)
+    clean = x - 0.05 * rng.standard_normal(x.shape) if exact else None
+    r = O.denoise(x, th, h, downsample=downsample, clean=clean)
+    xs, lo, hi = O.standardize(x)
+    pairs = O.exact_pairs(xs, (clean - lo) / (hi - lo), downsample) if exact else O.training_pairs(xs, downsample)
+    st = O.new_state(th[0])
+    for _ in range(2):
+        for inp, tgt in pairs:
+            st, _, _, _ = O.train_step(st, 1, inp, tgt[0], h)
+    y, _ = O.validate(st.theta, 1, xs, 0, h)
+    np.testing.assert_allclose(r.y[0], lo + (hi - lo) * y, rtol=0, atol=1e-14)
+    plain = O.denoise(x, th, h)
+    assert not np.allclose(plain.y, r.y)
+
+
+def test_denoise_small_image_quad_improves_psnr():
+    """The 2x2-block variant also denoises the 64x64 scene in eight epochs."""
+    from paper_2108_10209_amd import synth
+    clean, noisy = synth.small_64(0)
+    r = O.denoise(noisy, synth.init_params(1, 0), O.Hyper(fixed_epochs=8), downsample="quad")
+    assert synth.psnr(r.y, clean) > synth.psnr(noisy, clean) + 0.5
