@@ -60,6 +60,9 @@ typedef int n2f_status;
 #define N2F_FP32 0            /* convolutions on FP32 MFMA */
 #define N2F_BF16 1            /* convolutions on BF16 MFMA, FP32 accumulate, FP32 master weights */
 
+#define N2F_DS_CHECKERBOARD 0 /* the paper's checkerboard downsamples (Fig. 1) */
+#define N2F_DS_QUAD         1 /* ablation (Methods, Ablation Study; Table 1 "Quad"): 2x2 blocks */
+
 typedef struct n2f_config {
     int    n_layers;          /* 3x3 conv layers; only 8 is supported */
     int    width;             /* channels per conv layer; only 64 is supported */
@@ -73,13 +76,16 @@ typedef struct n2f_config {
     int    precision;         /* N2F_FP32 or N2F_BF16 */
     unsigned long long init_seed; /* SplitMix64 seed of the initial weights */
     int    use_graph;         /* n2f_run_epochs replays one recorded HIP graph per epoch */
+    int    downsample;        /* N2F_DS_CHECKERBOARD or N2F_DS_QUAD (training pairs only) */
+    int    exact_targets;     /* 1: "Exact" ablation; the run waits for n2f_run_set_clean() */
 } n2f_config;
 
 typedef struct n2f_run n2f_run;
 
 /* Fill *cfg with the paper's settings: 8 layers of width 64, Adam lr 1e-3,
  * betas 0.9/0.999, eps 1e-8, patience 100, max_epochs 2000, early stopping,
- * pairs in table order, FP32, seed 0, epochs replayed as HIP graphs. */
+ * pairs in table order, FP32, seed 0, epochs replayed as HIP graphs,
+ * checkerboard downsampling, plain targets. */
 void n2f_config_default(n2f_config* cfg);
 
 /* Message describing the calling thread's most recent error ("" if none). */
@@ -98,12 +104,13 @@ n2f_status n2f_init_params(int C, const n2f_config* cfg, unsigned long long seed
 
 /* Device workspace bytes a run on an H x W x C image needs (H, W >= 2,
  * 1 <= C <= 3).  This figure is also the unit of HBM admission when runs
- * share a GPU. */
+ * share a GPU.  cfg->exact_targets adds room for four target images. */
 n2f_status n2f_workspace_bytes(int H, int W, int C, const n2f_config* cfg, size_t* bytes);
 
 /* Create a run: validates arguments, standardises the image (per-image
- * min-max to [0, 1], no clipping), builds the four checkerboard downsamples
- * (even sizes; an odd last row/column is left out of them only) and draws
+ * min-max to [0, 1], no clipping), builds the four downsamples (checkerboard
+ * or, with cfg->downsample = N2F_DS_QUAD, the 2x2-block images; even sizes,
+ * an odd last row/column is left out of them only) and draws
  * the initial weights from cfg->init_seed.  d_in: device CHW image, read
  * during this call only.  Synchronises.  Returns N2F_WCONSTANT for a
  * constant image (the run then only supports n2f_result, which copies the
@@ -118,7 +125,10 @@ n2f_status n2f_run_destroy(n2f_run* run);
 /* One training step of network `net` (0 <= net < C) on pair `pair`
  * (0: up-even -> up-odd, 1: up-odd -> up-even, 2: left-even -> left-odd,
  * 3: left-odd -> left-even; the Methods table): forward pass, BCE against
- * channel `net` of the target, backward pass, one Adam step.  Queued. */
+ * channel `net` of the target, backward pass, one Adam step.  Queued.
+ * With N2F_DS_QUAD the pairs are the 2x2 blocks' diagonals (the paper does
+ * not state them): 0: TL -> BR, 1: BR -> TL, 2: TR -> BL, 3: BL -> TR.
+ * N2F_ESTATE for an exact-target run before n2f_run_set_clean(). */
 n2f_status n2f_train_step(n2f_run* run, int net, int pair);
 
 /* Validation of network `net` after an epoch: full-image forward pass, MSE
@@ -143,10 +153,22 @@ n2f_status n2f_run_epochs(n2f_run* run, int net, int max_epochs_now, int* done);
 n2f_status n2f_result(n2f_run* run, float* d_out);
 
 /* One-shot denoise: create, train every network to its stopping rule,
- * write d_out, destroy.  Synchronises. */
+ * write d_out, destroy.  Synchronises.  N2F_EINVAL with
+ * cfg->exact_targets (that ablation needs the clean image). */
 n2f_status n2f_denoise(const float* d_in, float* d_out, int H, int W, int C,
                        const n2f_config* cfg, void* d_ws, size_t ws_bytes,
                        hipStream_t stream);
+
+/* "Exact" ablation (Methods, Ablation Study; Table 1 "Exact"; the ODD
+ * approximation of the Theoretical Background): with the clean image known,
+ * the target of pair (a -> b) becomes x_b - (s_b - s_a), i.e. the input's
+ * signal plus the target's noise.  d_clean: device CHW image of the run's
+ * size, read during this call only, standardised with the noisy image's
+ * minimum and maximum; it must be finite (N2F_EINVAL otherwise).  Needs
+ * cfg->exact_targets at creation (N2F_ESTATE otherwise); may be called again
+ * to replace the targets.  Validation and the output are unchanged.
+ * Synchronises. */
+n2f_status n2f_run_set_clean(n2f_run* run, const float* d_clean);
 
 /* ---- state exchange (checkpoint/resume and teacher-forced testing) ---- */
 
@@ -182,9 +204,11 @@ n2f_status n2f_get_lohi(n2f_run* run, float* lo, float* hi);
 
 /* Copy an intermediate image to device buffer d_out (CHW, FP32):
  * which = 0..3: the downsamples up-even (C x H' x W'/2), up-odd,
- * left-even (C x H'/2 x W'), left-odd; 4: the standardised image
+ * left-even (C x H'/2 x W'), left-odd (N2F_DS_QUAD: TL, BR, TR, BL, each
+ * C x H'/2 x W'/2; pair p trains on image p); 4: the standardised image
  * (C x H x W); 5 + k: the last validation output of network k
- * (H x W, standardised units).  Queued. */
+ * (H x W, standardised units); 8 + p: the target image of pair p (the
+ * partner downsample, or the "Exact" target; shape of image p).  Queued. */
 n2f_status n2f_get_image(n2f_run* run, int which, float* d_out);
 
 /* Queue `n_epochs` whole epochs of network `net` on the run's stream (the
@@ -212,7 +236,8 @@ n2f_status n2f_batch_workspace_bytes(int n, const int* H, const int* W, const in
                                      size_t* bytes);
 
 /* Create the runs (each reads its device CHW input d_in[i] during this
- * call).  Synchronises.  Constant images are finished at once. */
+ * call).  Synchronises.  Constant images are finished at once.
+ * cfg->exact_targets is refused (N2F_EINVAL), here and by the server. */
 n2f_status n2f_batch_create(n2f_batch** batch, int n, const float* const* d_in, const int* H, const int* W,
                             const int* C, const n2f_config* cfg, void* d_ws, size_t ws_bytes, int n_streams);
 

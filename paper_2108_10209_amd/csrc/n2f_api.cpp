@@ -123,10 +123,11 @@ void internal_to_canon(const float* src, float* dst, int C, const ParamTable& pt
 // Workspace carve-out of one run.
 struct Plan {
     int H, W, C, Hc, Wc, P, bf;
-    int hu, wu, hl, wl;       // up and left training image shapes
+    int quad, exact;          // 2x2-block downsampling; separate "Exact" target images
+    int hu, wu, hl, wl;       // training image shapes of pairs 0-1 and 2-3
     int n1split, nsplit, hsplit, vblk, mmblk, max_trace;
     ParamTable pt;
-    size_t o_misc, o_xs, o_ds[4], o_net[3], net_bytes;
+    size_t o_misc, o_xs, o_ds[4], o_tg[4], o_net[3], net_bytes;
     size_t n_state, n_theta, n_pack32, n_pack16, n_trace, n_img;
     size_t o_act, o_mbits, o_dlt, o_part, o_lpart, o_vpart, bytes;
     size_t act_elems, dlt_elems;
@@ -144,6 +145,9 @@ n2f_status check_cfg(const n2f_config* cfg) {
     if (cfg->patience < 1 || cfg->max_epochs < 1 || cfg->fixed_epochs < 0)
         return fail(N2F_EINVAL, "patience and max_epochs must be >= 1, fixed_epochs >= 0");
     if (cfg->precision != N2F_FP32 && cfg->precision != N2F_BF16) return fail(N2F_EINVAL, "unknown precision");
+    if (cfg->downsample != N2F_DS_CHECKERBOARD && cfg->downsample != N2F_DS_QUAD)
+        return fail(N2F_EINVAL, "unknown downsample");
+    if (cfg->exact_targets != 0 && cfg->exact_targets != 1) return fail(N2F_EINVAL, "exact_targets must be 0 or 1");
     int seen[4] = {0, 0, 0, 0};
     for (int i = 0; i < 4; ++i) {
         if (cfg->pair_order[i] < 0 || cfg->pair_order[i] > 3 || seen[cfg->pair_order[i]]++)
@@ -162,13 +166,20 @@ n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
     q.W = W;
     q.C = C;
     q.bf = cfg->precision == N2F_BF16;
+    q.quad = cfg->downsample == N2F_DS_QUAD;
+    q.exact = cfg->exact_targets;
     q.Hc = H & ~1;
     q.Wc = W & ~1;
-    q.hu = q.Hc;
-    q.wu = q.Wc / 2;
-    q.hl = q.Hc / 2;
-    q.wl = q.Wc;
-    q.P = q.Hc * q.Wc / 2;
+    if (q.quad) {
+        q.hu = q.hl = q.Hc / 2;
+        q.wu = q.wl = q.Wc / 2;
+    } else {
+        q.hu = q.Hc;
+        q.wu = q.Wc / 2;
+        q.hl = q.Hc / 2;
+        q.wl = q.Wc;
+    }
+    q.P = q.hu * q.wu;
     q.nsplit = std::max(wgrad_splits(q.hu, q.wu, q.bf), wgrad_splits(q.hl, q.wl, q.bf));
     q.n1split = (int)std::max(1LL, std::min((long long)kMaxSplit, ((long long)q.P + 511) / 512));
     // BF16: the head runs in the last forward convolution's epilogue, one
@@ -188,6 +199,10 @@ n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
     for (int i = 0; i < 4; ++i) {
         q.o_ds[i] = o;
         o += align_up(sizeof(float) * (size_t)q.P * C);
+    }
+    for (int i = 0; i < 4; ++i) {
+        q.o_tg[i] = o;
+        if (q.exact) o += align_up(sizeof(float) * (size_t)q.P * C);
     }
     // one network's block
     size_t n = 0;
@@ -303,6 +318,8 @@ struct n2f_run {
     int* nonfinite;
     float* xs;
     float* ds[4];
+    float* tg[4];      // target image of pair p: ds of its partner, or the "Exact" targets
+    bool clean_set;    // exact-target runs: targets built by n2f_run_set_clean
     struct Net {
         DevState* st;
         float *theta, *m, *v, *g, *fwd, *bwd;
@@ -337,6 +354,12 @@ n2f_status check_run(n2f_run* r, int net) {
     return N2F_OK;
 }
 
+// Training calls of an exact-target run need its targets first.
+n2f_status check_targets(n2f_run* r) {
+    if (r->pl.exact && !r->clean_set) return fail(N2F_ESTATE, "exact-target run: call n2f_run_set_clean first");
+    return N2F_OK;
+}
+
 void* act_layer(n2f_run* r, int i, size_t npix) {
     const size_t es = r->pl.bf ? 2 : 4;
     return r->act + es * (size_t)i * npix * kWidth;
@@ -348,11 +371,13 @@ uint16_t* mask_layer(n2f_run* r, int i, size_t npix) {
     return reinterpret_cast<uint16_t*>(r->mbits) + (size_t)i * npix * 4;
 }
 
+// Pair p trains image p towards image kPartner[p] (or its exact target).
+constexpr int kPartner[4] = {1, 0, 3, 2};
+
 // Images and shapes of training pair `pair`.
 void pair_io(n2f_run* r, int pair, const float** in, const float** tgt, int* h, int* w) {
-    static const int src[4] = {0, 1, 2, 3}, dst[4] = {1, 0, 3, 2};
-    *in = r->ds[src[pair]];
-    *tgt = r->ds[dst[pair]];
+    *in = r->ds[pair];
+    *tgt = r->tg[pair];
     if (pair < 2) {
         *h = r->pl.hu;
         *w = r->pl.wu;
@@ -544,6 +569,8 @@ void n2f_config_default(n2f_config* cfg) {
     cfg->precision = N2F_FP32;
     cfg->init_seed = 0;
     cfg->use_graph = 1;
+    cfg->downsample = N2F_DS_CHECKERBOARD;
+    cfg->exact_targets = 0;
 }
 
 const char* n2f_last_error(void) { return g_err.c_str(); }
@@ -625,6 +652,8 @@ n2f_status n2f_run_create(n2f_run** out, const float* d_in, int H, int W, int C,
     r->mmpart = at<float>(misc, 4096);
     r->xs = at<float>(b, pl.o_xs);
     for (int i = 0; i < 4; ++i) r->ds[i] = at<float>(b, pl.o_ds[i]);
+    for (int i = 0; i < 4; ++i) r->tg[i] = pl.exact ? at<float>(b, pl.o_tg[i]) : r->ds[kPartner[i]];
+    r->clean_set = false;
     for (int k = 0; k < C; ++k) {
         char* nb = b + pl.o_net[k];
         n2f_run::Net& N = r->net[k];
@@ -682,7 +711,8 @@ n2f_status n2f_run_create(n2f_run** out, const float* d_in, int H, int W, int C,
         g_err = "constant image";
         return N2F_WCONSTANT;
     }
-    if (launch_prepare(d_in, H, W, C, r->lohi, r->xs, r->ds[0], r->ds[1], r->ds[2], r->ds[3], sm) != hipSuccess)
+    if (launch_prepare(d_in, H, W, C, r->lohi, r->xs, r->ds[0], r->ds[1], r->ds[2], r->ds[3], pl.quad, sm) !=
+        hipSuccess)
         return bail(fail(N2F_EDEVICE, "prepare launch failed"));
     // initial weights, drawn on the host and copied once
     std::vector<float> th0((size_t)C * pl.pt.total), internal(pl.pt.total);
@@ -723,6 +753,8 @@ n2f_status n2f_train_step(n2f_run* r, int net, int pair) {
     if (s != N2F_OK) return s;
     if (pair < 0 || pair > 3) return fail(N2F_EINVAL, "pair must be 0..3");
     if (r->host_done[net]) return fail(N2F_ESTATE, "network already finished");
+    s = check_targets(r);
+    if (s != N2F_OK) return s;
     return enqueue_train_step(r, net, pair);
 }
 
@@ -748,6 +780,8 @@ n2f_status n2f_run_epochs(n2f_run* r, int net, int max_now, int* done) {
     n2f_status s = check_run(r, net);
     if (s != N2F_OK) return s;
     if (max_now < 1) return fail(N2F_EINVAL, "max_epochs_now must be >= 1");
+    s = check_targets(r);
+    if (s != N2F_OK) return s;
     if (r->cfg.use_graph && !r->graph_exec[net]) {
         s = capture_epoch(r, net);
         if (s != N2F_OK) return s;
@@ -784,6 +818,8 @@ n2f_status n2f_run_launch_epochs(n2f_run* r, int net, int n_epochs) {
     n2f_status s = check_run(r, net);
     if (s != N2F_OK) return s;
     if (n_epochs < 1) return fail(N2F_EINVAL, "n_epochs must be >= 1");
+    s = check_targets(r);
+    if (s != N2F_OK) return s;
     if (r->host_done[net]) return N2F_OK;
     if (r->cfg.use_graph && !r->graph_exec[net]) {
         s = capture_epoch(r, net);
@@ -832,6 +868,7 @@ n2f_status n2f_result(n2f_run* r, float* d_out) {
 
 n2f_status n2f_denoise(const float* d_in, float* d_out, int H, int W, int C, const n2f_config* cfg, void* d_ws,
                        size_t ws_bytes, hipStream_t stream) {
+    if (cfg && cfg->exact_targets) return fail(N2F_EINVAL, "exact targets need the clean image: use a run");
     n2f_run* r = nullptr;
     n2f_status s = n2f_run_create(&r, d_in, H, W, C, cfg, d_ws, ws_bytes, stream);
     if (s < 0) return s;
@@ -853,6 +890,39 @@ n2f_status n2f_denoise(const float* d_in, float* d_out, int H, int W, int C, con
     n2f_run_destroy(r);
     if (s < 0) return s;
     return s == N2F_WCONSTANT ? s : warn;
+}
+
+n2f_status n2f_run_set_clean(n2f_run* r, const float* d_clean) {
+    if (!r || !d_clean) return fail(N2F_EINVAL, "run or clean image is NULL");
+    if (r->constant) return fail(N2F_ESTATE, "constant image: nothing to train");
+    if (!r->pl.exact) return fail(N2F_ESTATE, "run was not created with exact_targets");
+    const Plan& pl = r->pl;
+    hipStream_t sm = r->stream;
+    const long long n = (long long)pl.H * pl.W * pl.C;
+    // finiteness check with the run's min/max kernel, into spare words of
+    // the misc block (the run's own extremes stay untouched)
+    char* misc = r->ws + pl.o_misc;
+    float* lohi2 = at<float>(misc, 256);
+    int nonfin = 0;
+    N2F_HIP(launch_minmax(d_clean, n, r->mmpart, pl.mmblk, r->mmcnt, lohi2, r->nonfinite, sm));
+    N2F_HIP(hipMemcpyAsync(&nonfin, r->nonfinite, sizeof(int), hipMemcpyDeviceToHost, sm));
+    N2F_HIP(hipStreamSynchronize(sm));
+    if (nonfin) {
+        N2F_HIP(hipMemsetAsync(r->nonfinite, 0, sizeof(int), sm));
+        N2F_HIP(hipStreamSynchronize(sm));
+        return fail(N2F_EINVAL, "clean image holds NaN or infinite values");
+    }
+    // the clean downsamples, standardised with the noisy extremes, into the
+    // target images (the activation stash holds the unused full image),
+    // then the targets in place
+    float* scratch = reinterpret_cast<float*>(r->act);
+    N2F_HIP(launch_prepare(d_clean, pl.H, pl.W, pl.C, r->lohi, scratch, r->tg[0], r->tg[1], r->tg[2], r->tg[3],
+                           pl.quad, sm));
+    const float* x[4] = {r->ds[0], r->ds[1], r->ds[2], r->ds[3]};
+    N2F_HIP(launch_exact_targets(x, r->tg, (long long)pl.P * pl.C, sm));
+    N2F_HIP(hipStreamSynchronize(sm));
+    r->clean_set = true;
+    return N2F_OK;
 }
 
 n2f_status n2f_get_state(n2f_run* r, int net, float* theta, float* m, float* v, long long* t) {
@@ -988,6 +1058,10 @@ n2f_status n2f_get_image(n2f_run* r, int which, float* d_out) {
     } else if (which >= 5 && which < 5 + pl.C) {
         N2F_HIP(hipMemcpyAsync(d_out, r->net[which - 5].y, sizeof(float) * pl.H * pl.W, hipMemcpyDeviceToDevice,
                                r->stream));
+    } else if (which >= 8 && which < 12) {
+        const int p = which - 8;
+        const int h = p < 2 ? pl.hu : pl.hl, w = p < 2 ? pl.wu : pl.wl;
+        N2F_HIP(launch_extract(r->tg[p], h, w, pl.C, d_out, r->stream));
     } else {
         return fail(N2F_EINVAL, "unknown image index");
     }

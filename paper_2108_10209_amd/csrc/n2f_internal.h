@@ -67,7 +67,10 @@ constexpr int kPackN = kTaps * kWidth * kWidth;
 hipError_t launch_minmax(const float* x, long long n, float* part, int nblk, unsigned* counter,
                          float* lohi, int* nonfinite, hipStream_t s);
 hipError_t launch_prepare(const float* x, int H, int W, int C, const float* lohi,
-                          float* xs, float* ue, float* uo, float* le, float* lo, hipStream_t s);
+                          float* xs, float* ue, float* uo, float* le, float* lo, int quad, hipStream_t s);
+// x[0..3]: the noisy downsamples; t[0..3]: the clean ones on entry, the
+// pair targets on exit; n values per image.
+hipError_t launch_exact_targets(const float* const* x, float* const* t, long long n, hipStream_t s);
 hipError_t launch_init_state(DevState* st, int patience, int max_epochs, int fixed_epochs, hipStream_t s);
 hipError_t launch_pack(const float* theta, const ParamTable& pt, float* fwd, float* bwd,
                        uint16_t* fwd16, uint16_t* bwd16, hipStream_t s);

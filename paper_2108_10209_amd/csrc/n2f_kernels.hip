@@ -176,12 +176,15 @@ __global__ __launch_bounds__(kBlock) void k_minmax(const float* __restrict__ x, 
 // Standardise (x - lo) / (hi - lo) in FP64, rounded once to FP32, and scatter
 // each pixel of the even extent into its two checkerboard downsamples:
 // row+column even -> up-even[i][j/2] and left-even[i/2][j]; odd -> the odd
-// pair.  Input CHW; outputs channels-last.
+// pair.  With `quad` (2x2-block ablation) the pixel goes to one image
+// instead, at [i/2][j/2]: ue <- top-left, uo <- bottom-right, le <- top-right,
+// lo <- bottom-left, so that the pairs (0,1) and (2,3) are the two block
+// diagonals.  Input CHW; outputs channels-last.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_prepare(const float* __restrict__ x, int H, int W, int C,
                                                     const float* __restrict__ lohi, float* __restrict__ xs,
                                                     float* __restrict__ ue, float* __restrict__ uo,
-                                                    float* __restrict__ le, float* __restrict__ lo) {
+                                                    float* __restrict__ le, float* __restrict__ lo, int quad) {
     const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long hw = (long long)H * W;
     if (idx >= hw * C) return;
@@ -192,7 +195,13 @@ __global__ __launch_bounds__(kBlock) void k_prepare(const float* __restrict__ x,
     const float v = (float)(((double)x[idx] - l) / (hgh - l));
     xs[rem * C + c] = v;
     const int Hc = H & ~1, Wc = W & ~1;
-    if (i < Hc && j < Wc) {
+    if (quad) {
+        if (i < Hc && j < Wc) {
+            const long long pq = (long long)(i >> 1) * (Wc >> 1) + (j >> 1);
+            float* d = (i & 1) ? ((j & 1) ? uo : lo) : ((j & 1) ? le : ue);
+            d[pq * C + c] = v;
+        }
+    } else if (i < Hc && j < Wc) {
         const long long pu = (long long)i * (Wc >> 1) + (j >> 1);
         const long long pl = (long long)(i >> 1) * Wc + j;
         if (((i + j) & 1) == 0) {
@@ -203,6 +212,24 @@ __global__ __launch_bounds__(kBlock) void k_prepare(const float* __restrict__ x,
             lo[pl * C + c] = v;
         }
     }
+}
+
+// "Exact" ablation targets.  On entry t0..t3 hold the clean image's four
+// downsamples (standardised like the noisy ones, same order); on exit the
+// target of pair p = (a -> b), x_b - (s_b - s_a), with pairs 0: 0 -> 1,
+// 1: 1 -> 0, 2: 2 -> 3, 3: 3 -> 2.  n = values per image (pixels x C).
+__global__ __launch_bounds__(kBlock) void k_exact_targets(const float* __restrict__ x0,
+                                                          const float* __restrict__ x1,
+                                                          const float* __restrict__ x2,
+                                                          const float* __restrict__ x3, float* t0, float* t1,
+                                                          float* t2, float* t3, long long n) {
+    const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= n) return;
+    const float s0 = t0[e], s1 = t1[e], s2 = t2[e], s3 = t3[e];
+    t0[e] = x1[e] - (s1 - s0);
+    t1[e] = x0[e] - (s0 - s1);
+    t2[e] = x3[e] - (s3 - s2);
+    t3[e] = x2[e] - (s2 - s3);
 }
 
 __global__ void k_init_state(DevState* st, int patience, int max_epochs, int fixed_epochs) {
@@ -862,9 +889,16 @@ hipError_t launch_minmax(const float* x, long long n, float* part, int nblk, uns
 }
 
 hipError_t launch_prepare(const float* x, int H, int W, int C, const float* lohi, float* xs, float* ue,
-                          float* uo, float* le, float* lo, hipStream_t s) {
+                          float* uo, float* le, float* lo, int quad, hipStream_t s) {
     hipLaunchKernelGGL(k_prepare, dim3(nblocks((long long)H * W * C, kBlock)), dim3(kBlock), 0, s, x, H, W, C,
-                       lohi, xs, ue, uo, le, lo);
+                       lohi, xs, ue, uo, le, lo, quad);
+    return hipGetLastError();
+}
+
+hipError_t launch_exact_targets(const float* const* x, float* const* t, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_exact_targets, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, s, x[0], x[1], x[2], x[3], t[0],
+                       t[1], t[2], t[3], n);
     return hipGetLastError();
 }
 

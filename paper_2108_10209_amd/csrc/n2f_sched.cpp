@@ -126,6 +126,7 @@ n2f_status n2f_batch_create(n2f_batch** out, int n, const float* const* d_in, co
                             const int* C, const n2f_config* cfg, void* d_ws, size_t ws_bytes, int n_streams) {
     if (!out || !d_in || !d_ws || !cfg || n < 1 || n_streams < 1) return sfail(N2F_EINVAL, "bad batch arguments");
     *out = nullptr;
+    if (cfg->exact_targets) return sfail(N2F_EINVAL, "exact targets need a clean image per run: not in a batch");
     size_t need = 0;
     n2f_status s = n2f_batch_workspace_bytes(n, H, W, C, cfg, &need);
     if (s != N2F_OK) return s;
@@ -279,6 +280,7 @@ extern "C" {
 n2f_status n2f_server_create(n2f_server** out, const n2f_config* cfg, void* d_arena, size_t arena_bytes,
                              int n_streams, int max_active, int flags) {
     if (!out || !cfg || n_streams < 1 || max_active < 1) return sfail(N2F_EINVAL, "bad server arguments");
+    if (cfg->exact_targets) return sfail(N2F_EINVAL, "exact targets need a clean image per run: not served");
     const bool sim = (flags & N2F_SERVER_SIMULATE) != 0;
     if (!sim && !d_arena) return sfail(N2F_EINVAL, "arena is NULL");
     if (reinterpret_cast<uintptr_t>(d_arena) % kAlign) return sfail(N2F_EINVAL, "arena must be 256-byte aligned");

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libn2f.so")
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
 WCONSTANT, WCAPPED = 1, 2
 FP32, BF16 = 0, 1
+DS_CHECKERBOARD, DS_QUAD = 0, 1
 
 SYMBOLS = [
     "n2f_config_default", "n2f_last_error", "n2f_param_count", "n2f_init_params", "n2f_workspace_bytes",
@@ -27,6 +28,7 @@ SYMBOLS = [
     "n2f_profile_end", "n2f_run_launch_epochs", "n2f_run_poll", "n2f_batch_workspace_bytes", "n2f_batch_create",
     "n2f_batch_run", "n2f_batch_result", "n2f_batch_progress", "n2f_batch_destroy", "n2f_server_create",
     "n2f_server_submit", "n2f_server_step", "n2f_server_poll", "n2f_server_memory", "n2f_server_destroy",
+    "n2f_run_set_clean",
 ]
 SERVER_SIMULATE = 1
 K_CONV_FWD, K_BACKWARD, K_ADAM = 0, 1, 2
@@ -44,7 +46,7 @@ class Config(ctypes.Structure):
         ("lr", c_float), ("eps", c_float), ("beta1", c_double), ("beta2", c_double),
         ("patience", c_int), ("max_epochs", c_int), ("fixed_epochs", c_int),
         ("pair_order", c_int * 4), ("precision", c_int), ("init_seed", c_ulonglong),
-        ("use_graph", c_int),
+        ("use_graph", c_int), ("downsample", c_int), ("exact_targets", c_int),
     ]
 
 
@@ -101,6 +103,7 @@ def lib():
             "n2f_server_poll": [c_void_p, c_void_p, c_void_p, c_int, POINTER(c_int)],
             "n2f_server_memory": [c_void_p, POINTER(c_size_t), POINTER(c_size_t)],
             "n2f_server_destroy": [c_void_p],
+            "n2f_run_set_clean": [c_void_p, c_void_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -183,6 +186,14 @@ class Run:
         except Exception:
             pass
 
+    def set_clean(self, clean):
+        """Targets of the "Exact" ablation from the clean image (same shape as
+        the input, FP32 CUDA, contiguous); needs exact_targets=1."""
+        import torch
+        assert clean.is_cuda and clean.dtype == torch.float32 and clean.is_contiguous()
+        assert tuple(clean.shape) == (self.C, self.H, self.W)
+        _check(lib().n2f_run_set_clean(self._ptr, c_void_p(clean.data_ptr())))
+
     def train_step(self, net: int, pair: int):
         _check(lib().n2f_train_step(self._ptr, net, pair))
 
@@ -247,8 +258,14 @@ class Run:
     def image(self, which: int):
         import torch
         Hc, Wc = self.H - self.H % 2, self.W - self.W % 2
-        shapes = {0: (self.C, Hc, Wc // 2), 1: (self.C, Hc, Wc // 2), 2: (self.C, Hc // 2, Wc),
-                  3: (self.C, Hc // 2, Wc), 4: (self.C, self.H, self.W)}
+        if self.cfg.downsample == DS_QUAD:
+            shapes = {i: (self.C, Hc // 2, Wc // 2) for i in range(4)}
+        else:
+            shapes = {0: (self.C, Hc, Wc // 2), 1: (self.C, Hc, Wc // 2), 2: (self.C, Hc // 2, Wc),
+                      3: (self.C, Hc // 2, Wc)}
+        shapes[4] = (self.C, self.H, self.W)
+        for p in range(4):
+            shapes[8 + p] = shapes[p]
         shape = shapes.get(which, (self.H, self.W))
         out = torch.empty(shape, dtype=torch.float32, device=self.device)
         _check(lib().n2f_get_image(self._ptr, which, c_void_p(out.data_ptr())))

@@ -68,7 +68,8 @@ def test_workspace_bytes_scales_and_rejects():
 
 def test_config_validation():
     for kw in [dict(n_layers=7), dict(width=32), dict(lr=0.0), dict(beta1=1.0), dict(patience=0),
-               dict(max_epochs=0), dict(pair_order=(0, 0, 1, 2)), dict(precision=7)]:
+               dict(max_epochs=0), dict(pair_order=(0, 0, 1, 2)), dict(precision=7), dict(downsample=2),
+               dict(exact_targets=2)]:
         with pytest.raises(n2f.N2FError) as e:
             n2f.workspace_bytes(8, 8, 1, n2f.default_config(**kw))
         assert e.value.code == n2f.EINVAL
@@ -82,3 +83,32 @@ def test_null_arguments_rejected_without_device():
     assert st == n2f.EINVAL and b"NULL" in L.n2f_last_error()
     assert L.n2f_train_step(None, 0, 0) == n2f.EINVAL
     assert L.n2f_result(None, None) == n2f.EINVAL
+
+
+def test_ablation_workspaces():
+    """2x2 blocks halve the training pixels (so the stash); exact targets add
+    four target images of C x P floats."""
+    base = n2f.workspace_bytes(512, 512, 1)
+    quad = n2f.workspace_bytes(512, 512, 1, n2f.default_config(downsample=n2f.DS_QUAD))
+    assert quad < base and quad >= 8 * 64 * (256 * 256) * 4
+    ex = n2f.workspace_bytes(512, 512, 3, n2f.default_config(exact_targets=1))
+    assert ex - n2f.workspace_bytes(512, 512, 3) >= 4 * 3 * (512 * 256) * 4
+    # smallest images still plan: 2x2 gives 1x1 block images
+    assert n2f.workspace_bytes(2, 2, 1, n2f.default_config(downsample=n2f.DS_QUAD)) > 0
+    assert n2f.workspace_bytes(3, 3, 2, n2f.default_config(downsample=n2f.DS_QUAD, exact_targets=1)) > 0
+
+
+def test_exact_targets_refused_where_no_clean_image_fits():
+    L = n2f.lib()
+    cfg = n2f.default_config(exact_targets=1)
+    assert L.n2f_denoise(None, None, 8, 8, 1, ctypes.byref(cfg), None, 0, None) == n2f.EINVAL
+    assert b"clean" in L.n2f_last_error()
+    srv = ctypes.c_void_p()
+    assert L.n2f_server_create(ctypes.byref(srv), ctypes.byref(cfg), None, 1 << 30, 1, 4,
+                               n2f.SERVER_SIMULATE) == n2f.EINVAL
+    b = ctypes.c_void_p()
+    one = (ctypes.c_int * 1)(8)
+    ptrs = (ctypes.c_void_p * 1)(None)
+    assert L.n2f_batch_create(ctypes.byref(b), 1, ptrs, one, one, (ctypes.c_int * 1)(1), ctypes.byref(cfg),
+                              ctypes.c_void_p(256), 1 << 20, 1) == n2f.EINVAL
+    assert L.n2f_run_set_clean(None, None) == n2f.EINVAL
