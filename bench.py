@@ -118,6 +118,75 @@ def bench_batch(args):
     }
 
 
+# Table 1 of the paper (BSD68, PSNR dB): normal, 2x2 blocks ("Quad"), exact
+# targets ("Exact"); context for the synthetic comparison below
+PAPER_TABLE1 = {"sigma25": {"normal": 28.12, "quad": 27.56, "exact": 28.12},
+                "sigma50": {"normal": 25.23, "quad": 24.97, "exact": 25.24}}
+
+
+def bench_ablation(args):
+    """The ablation study (Methods, Ablation Study; Table 1) on synthetic
+    512x512 scenes: the checkerboard method, 2x2-block downsampling, and
+    exact targets (known signal difference removed), each trained to its
+    own early stop on the same noisy images.  Reports PSNR per variant and
+    its difference from the checkerboard run, and images/s per variant."""
+    import numpy as np
+    import torch
+    from paper_2108_10209_amd import n2f, synth
+    dev = torch.device("cuda:0")
+    prec = n2f.BF16 if args.precision == "bf16" else n2f.FP32
+    variants = {"normal": dict(), "quad": dict(downsample=n2f.DS_QUAD), "exact": dict(exact_targets=1)}
+    S = args.size
+    scenes = {"blobs": synth.blobs(S, S, 0), "microscopy": synth.microscopy(S, S, 4)}
+    seeds = list(range(1, args.ablation_seeds + 1))
+    rows, wall = {}, {v: 0.0 for v in variants}
+    nimg = {v: 0 for v in variants}
+    for scene, clean in scenes.items():
+        for sg in (25, 50):
+            cell = {}
+            for name, kw in variants.items():
+                cfg = n2f.default_config(precision=prec, max_epochs=args.max_epochs, **kw)
+                ps, eps = [], []
+                for sd in seeds:
+                    noisy = synth.add_gaussian(clean, sg / 255.0, 1000 * sg + sd)
+                    x = torch.from_numpy(noisy).to(dev)
+                    c = torch.from_numpy(np.ascontiguousarray(clean, np.float32)).to(dev)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    run = n2f.Run(x, cfg)
+                    if kw.get("exact_targets"):
+                        run.set_clean(c)
+                    run.run_epochs(0, args.max_epochs)
+                    y = run.result()
+                    torch.cuda.synchronize()
+                    wall[name] += time.perf_counter() - t0
+                    nimg[name] += 1
+                    eps.append(run.progress(0)[0])
+                    run.close()
+                    ps.append(synth.psnr(y.cpu().numpy(), clean))
+                cell[name] = {"psnr": round(float(np.mean(ps)), 3),
+                              "psnr_sd": round(float(np.std(ps, ddof=1)), 3) if len(ps) > 1 else None,
+                              "epochs_mean": round(float(np.mean(eps)), 1)}
+                print(f"{scene} sigma {sg} {name}: {cell[name]}", file=sys.stderr, flush=True)
+            for name in ("quad", "exact"):
+                cell[name]["delta_db"] = round(cell[name]["psnr"] - cell["normal"]["psnr"], 3)
+            cell["noisy_psnr"] = round(float(np.mean([synth.psnr(synth.add_gaussian(clean, sg / 255.0, 1000 * sg + sd),
+                                                                  clean) for sd in seeds])), 3)
+            rows[f"{scene}_sigma{sg}"] = cell
+    ips = {v: round(nimg[v] / wall[v], 4) for v in variants}
+    total = sum(nimg.values()) / sum(wall.values())
+    return {
+        "metric": "images/s denoised to convergence, ablation variants (512x512, sigma 25/50, early stopping)",
+        "value": round(total, 4), "unit": "images/s", "n_gpus": 1, "steps": sum(nimg.values()), "warmup": 0,
+        "ms_per_step": round(1e3 * sum(wall.values()) / sum(nimg.values()), 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"ablation: checkerboard vs 2x2 blocks vs exact targets, {S}x{S} blobs and "
+                               f"microscopy scenes, Gaussian sigma 25 and 50, {len(seeds)} noise seeds each",
+                   "precision": args.precision},
+        "images_per_s": ips, "psnr": rows, "paper_table1_bsd68_context": PAPER_TABLE1,
+    }
+
+
 def bench_serve(args):
     """Poisson-arrival stream (log-uniform sides in [128, 2048], 30% RGB,
     Gaussian or Poisson noise per request) served by the continuous-batching
@@ -200,7 +269,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-every", type=int, default=8,
                     help="time the kernels of one epoch in N with HIP events")
-    ap.add_argument("--workload", choices=["single", "batch", "serve"], default="single")
+    ap.add_argument("--workload", choices=["single", "batch", "serve", "ablation"], default="single")
+    ap.add_argument("--ablation-seeds", type=int, default=3)
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--fp32-sample", type=int, default=8)
@@ -228,7 +298,7 @@ def main():
         sys.exit(2)
 
     if args.workload != "single":
-        res = bench_batch(args) if args.workload == "batch" else bench_serve(args)
+        res = {"batch": bench_batch, "serve": bench_serve, "ablation": bench_ablation}[args.workload](args)
         print(json.dumps(res), flush=True)
         return
 
