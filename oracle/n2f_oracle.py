@@ -34,7 +34,9 @@ self-contradictory the reading taken here is stated in the function:
   downsamples, paired along the block diagonals in both directions (the
   pairing is not stated), and the "Exact" targets, from which the known
   signal difference between target and input is removed (the clean image
-  standardised with the noisy image's extremes).
+  standardised with the noisy image's extremes);
+* volumes (Methods, Fluorescence Microscopy Images): every z-slice is
+  denoised on its own, then the stack is max projected.
 
 Parity pins for every function live in tests/test_oracle_*.py.
 """
@@ -494,3 +496,30 @@ def denoise(x: np.ndarray, theta0: np.ndarray, h: Hyper = Hyper(), pair_order=(0
         best_e.append(es.best_epoch)
         hist.append(list(es.history))
     return RunResult(destandardize(ys, lo, hi), ys, epochs, best_e, hist, capped, False)
+
+
+# ---------------------------------------------------------------------------
+# Volumes (Methods, Fluorescence Microscopy Images: live-cell volumes are
+# denoised as individual z-slices and then max projected)
+# ---------------------------------------------------------------------------
+def max_projection(stack: np.ndarray) -> np.ndarray:
+    """Maximum-intensity projection along the first axis (z).
+
+    stack: (Z, ...) with Z >= 1.  A NaN is skipped where another slice holds
+    a number (fmax), so only an all-NaN column projects to NaN.
+    """
+    stack = np.asarray(stack)
+    if stack.shape[0] < 1:
+        raise ValueError("need at least one slice")
+    out = stack[0].copy()
+    for z in range(1, stack.shape[0]):
+        out = np.fmax(out, stack[z])
+    return out
+
+
+def denoise_volume(stack: np.ndarray, theta0: np.ndarray, h: Hyper = Hyper()):
+    """Denoise every z-slice of a (Z, H, W) single-channel stack on its own
+    (each with the same initial weights theta0 of shape (1, n_params)), then
+    max-project.  Returns (projection, denoised stack)."""
+    den = np.stack([denoise(stack[z][None], theta0, h).y[0] for z in range(stack.shape[0])])
+    return max_projection(den), den

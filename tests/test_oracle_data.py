@@ -254,3 +254,47 @@ def test_exact_targets_without_noise_equal_inputs():
     for downsample in O.DOWNSAMPLES:
         for a, b in O.exact_pairs(x_std, x_std, downsample):
             np.testing.assert_allclose(b, a, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Volumes: z-slices denoised one by one, then max projected (Methods,
+# Fluorescence Microscopy Images)
+# ---------------------------------------------------------------------------
+def _nan(a):
+    return np.array([[[np.nan if v is None else v for v in row] for row in sl] for sl in a], dtype=np.float64)
+
+
+@pytest.mark.parametrize("case", json.load(open(os.path.join(GOLDEN, "max_projection_worked.json")))["cases"])
+def test_max_projection_worked_example(case):
+    got = O.max_projection(_nan(case["stack"]))
+    np.testing.assert_array_equal(got, _nan([case["projection"]])[0])
+
+
+@pytest.mark.parametrize("Z,H,W", [(1, 3, 4), (2, 5, 5), (41, 6, 7), (5, 1, 9)])
+def test_max_projection_properties(Z, H, W):
+    """The projection bounds every slice from above and is attained at
+    every pixel; it does not depend on the slice order."""
+    rng = np.random.default_rng(Z * 100 + H + W)
+    st = rng.standard_normal((Z, H, W))
+    p = O.max_projection(st)
+    assert p.shape == (H, W)
+    assert np.all(p[None] >= st)
+    assert np.all(np.any(p[None] == st, axis=0))
+    np.testing.assert_array_equal(O.max_projection(st[rng.permutation(Z)]), p)
+    if Z == 1:
+        np.testing.assert_array_equal(p, st[0])
+    with pytest.raises(ValueError):
+        O.max_projection(np.empty((0, H, W)))
+
+
+def test_denoise_volume_is_slice_by_slice():
+    """Each slice of the denoised stack is that slice denoised alone."""
+    h = O.Hyper(width=4, n_layers=2, fixed_epochs=2)
+    rng = np.random.default_rng(3)
+    st = rng.uniform(0, 1, (3, 6, 8))
+    spec = O.param_spec(1, h.width, h.n_layers)
+    th = np.concatenate([rng.uniform(-0.5, 0.5, int(np.prod(s))) for _, s in spec])[None]
+    proj, den = O.denoise_volume(st, th, h)
+    for z in range(3):
+        np.testing.assert_array_equal(den[z], O.denoise(st[z][None], th, h).y[0])
+    np.testing.assert_array_equal(proj, np.max(den, axis=0))
