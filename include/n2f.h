@@ -170,6 +170,18 @@ n2f_status n2f_denoise(const float* d_in, float* d_out, int H, int W, int C,
  * Synchronises. */
 n2f_status n2f_run_set_clean(n2f_run* run, const float* d_clean);
 
+/* Maximum-intensity projection along z (Methods, Fluorescence Microscopy
+ * Images: the live-cell volumes are denoised as individual z-slices and
+ * then max projected).  d_stack: device FP32, n_slices (>= 1) images of npix
+ * (>= 1) values each, slice z at d_stack + z * npix (e.g. the per-slice
+ * results of a batch, one channel, copied into one buffer); d_out: device
+ * FP32, npix values, not overlapping the stack:
+ * d_out[p] = max_z d_stack[z * npix + p].  A NaN loses to any number (fmax),
+ * so only a pixel that is NaN in every slice projects to NaN.  N2F_EINVAL
+ * for NULL pointers, sizes below 1 or overlapping buffers.  Queued. */
+n2f_status n2f_max_project(const float* d_stack, int n_slices, long long npix, float* d_out,
+                           hipStream_t stream);
+
 /* ---- state exchange (checkpoint/resume and teacher-forced testing) ---- */
 
 /* Copy network `net`'s parameters, Adam moments and step count to host

@@ -925,6 +925,17 @@ n2f_status n2f_run_set_clean(n2f_run* r, const float* d_clean) {
     return N2F_OK;
 }
 
+n2f_status n2f_max_project(const float* d_stack, int n_slices, long long npix, float* d_out, hipStream_t stream) {
+    if (!d_stack || !d_out) return fail(N2F_EINVAL, "stack or output is NULL");
+    if (n_slices < 1 || npix < 1) return fail(N2F_EINVAL, "need n_slices >= 1 and npix >= 1");
+    if (npix > (1LL << 40) / n_slices) return fail(N2F_EINVAL, "stack too large");
+    const char *a = reinterpret_cast<const char*>(d_stack), *b = reinterpret_cast<const char*>(d_out);
+    if (b < a + sizeof(float) * n_slices * npix && a < b + sizeof(float) * npix)
+        return fail(N2F_EINVAL, "output overlaps the stack");
+    N2F_HIP(launch_max_project(d_stack, n_slices, npix, d_out, stream));
+    return N2F_OK;
+}
+
 n2f_status n2f_get_state(n2f_run* r, int net, float* theta, float* m, float* v, long long* t) {
     n2f_status s = check_run(r, net);
     if (s != N2F_OK) return s;

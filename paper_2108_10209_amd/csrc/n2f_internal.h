@@ -71,6 +71,8 @@ hipError_t launch_prepare(const float* x, int H, int W, int C, const float* lohi
 // x[0..3]: the noisy downsamples; t[0..3]: the clean ones on entry, the
 // pair targets on exit; n values per image.
 hipError_t launch_exact_targets(const float* const* x, float* const* t, long long n, hipStream_t s);
+// out[p] = max over z < nz of stack[z * npix + p]; nz >= 1, npix >= 1.
+hipError_t launch_max_project(const float* stack, int nz, long long npix, float* out, hipStream_t s);
 hipError_t launch_init_state(DevState* st, int patience, int max_epochs, int fixed_epochs, hipStream_t s);
 hipError_t launch_pack(const float* theta, const ParamTable& pt, float* fwd, float* bwd,
                        uint16_t* fwd16, uint16_t* bwd16, hipStream_t s);

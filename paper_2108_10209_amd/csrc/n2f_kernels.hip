@@ -232,6 +232,38 @@ __global__ __launch_bounds__(kBlock) void k_exact_targets(const float* __restric
     t3[e] = x2[e] - (s2 - s3);
 }
 
+// Maximum-intensity projection along z: out[p] = fmax over z of
+// st[z * npix + p] (a NaN loses to any number).  V = 4: one thread owns four
+// consecutive pixels and reads 16 bytes per slice (npix % 4 == 0, 16-byte
+// aligned pointers); V = 1: one pixel per thread.  Consecutive threads read
+// consecutive addresses of each slice.
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_max_project(const float* __restrict__ st, int nz, long long npix,
+                                                        float* __restrict__ out) {
+    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if constexpr (V == 4) {
+        const long long n4 = npix >> 2;
+        if (q >= n4) return;
+        const float4* s4 = reinterpret_cast<const float4*>(st);
+        float4 m = s4[q];
+#pragma unroll 4
+        for (int z = 1; z < nz; ++z) {
+            const float4 v = s4[(long long)z * n4 + q];
+            m.x = fmaxf(m.x, v.x);
+            m.y = fmaxf(m.y, v.y);
+            m.z = fmaxf(m.z, v.z);
+            m.w = fmaxf(m.w, v.w);
+        }
+        reinterpret_cast<float4*>(out)[q] = m;
+    } else {
+        if (q >= npix) return;
+        float m = st[q];
+#pragma unroll 4
+        for (int z = 1; z < nz; ++z) m = fmaxf(m, st[(long long)z * npix + q]);
+        out[q] = m;
+    }
+}
+
 __global__ void k_init_state(DevState* st, int patience, int max_epochs, int fixed_epochs) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     DevState s = {};
@@ -892,6 +924,18 @@ hipError_t launch_prepare(const float* x, int H, int W, int C, const float* lohi
                           float* uo, float* le, float* lo, int quad, hipStream_t s) {
     hipLaunchKernelGGL(k_prepare, dim3(nblocks((long long)H * W * C, kBlock)), dim3(kBlock), 0, s, x, H, W, C,
                        lohi, xs, ue, uo, le, lo, quad);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_project(const float* stack, int nz, long long npix, float* out, hipStream_t s) {
+    const bool vec = (npix % 4) == 0 && (reinterpret_cast<uintptr_t>(stack) % 16) == 0 &&
+                     (reinterpret_cast<uintptr_t>(out) % 16) == 0;
+    if (vec) {
+        hipLaunchKernelGGL(k_max_project<4>, dim3(nblocks(npix / 4, kBlock)), dim3(kBlock), 0, s, stack, nz, npix,
+                           out);
+    } else {
+        hipLaunchKernelGGL(k_max_project<1>, dim3(nblocks(npix, kBlock)), dim3(kBlock), 0, s, stack, nz, npix, out);
+    }
     return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ SYMBOLS = [
     "n2f_profile_end", "n2f_run_launch_epochs", "n2f_run_poll", "n2f_batch_workspace_bytes", "n2f_batch_create",
     "n2f_batch_run", "n2f_batch_result", "n2f_batch_progress", "n2f_batch_destroy", "n2f_server_create",
     "n2f_server_submit", "n2f_server_step", "n2f_server_poll", "n2f_server_memory", "n2f_server_destroy",
-    "n2f_run_set_clean",
+    "n2f_run_set_clean", "n2f_max_project",
 ]
 SERVER_SIMULATE = 1
 K_CONV_FWD, K_BACKWARD, K_ADAM = 0, 1, 2
@@ -104,6 +104,7 @@ def lib():
             "n2f_server_memory": [c_void_p, POINTER(c_size_t), POINTER(c_size_t)],
             "n2f_server_destroy": [c_void_p],
             "n2f_run_set_clean": [c_void_p, c_void_p],
+            "n2f_max_project": [c_void_p, c_int, c_longlong, c_void_p, c_void_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -283,6 +284,20 @@ def denoise(x, cfg: Config | None = None, ws=None):
     st = _check(lib().n2f_denoise(c_void_p(x.data_ptr()), c_void_p(out.data_ptr()), H, W, C, byref(cfg),
                                   c_void_p(ws.data_ptr()), nbytes, _stream_of(x)))
     return out, st
+
+
+def max_project(stack, out=None):
+    """Maximum-intensity projection along the first axis of a (Z, ...) FP32
+    contiguous CUDA tensor; returns a tensor of the remaining shape."""
+    import torch
+    assert stack.is_cuda and stack.dtype == torch.float32 and stack.is_contiguous() and stack.dim() >= 2
+    nz = int(stack.shape[0])
+    npix = stack[0].numel()
+    if out is None:
+        out = torch.empty(stack.shape[1:], dtype=torch.float32, device=stack.device)
+    assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous() and out.numel() == npix
+    _check(lib().n2f_max_project(c_void_p(stack.data_ptr()), nz, npix, c_void_p(out.data_ptr()), _stream_of(stack)))
+    return out
 
 
 def profile_begin(every: int = 1):

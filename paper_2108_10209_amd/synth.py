@@ -200,6 +200,88 @@ def microscopy(H: int, W: int, seed: int, n_spots: int = 2000, n_fil: int = 30) 
     return q.astype(np.float32)[None]
 
 
+def _add_patch(vol: np.ndarray, patch: np.ndarray, y0: int, x0: int, zw: np.ndarray) -> None:
+    """vol[z, y0:, x0:] += zw[z] * patch for the planes where zw is not tiny."""
+    h, w = patch.shape
+    for z in np.nonzero(zw > 1e-4)[0]:
+        vol[z, y0:y0 + h, x0:x0 + w] += zw[z] * patch
+
+
+def cell_volume(Z: int, H: int, W: int, seed: int) -> np.ndarray:
+    """Two-channel live-cell z-stack, a stand-in for the confocal volumes of
+    the paper's time-lapse (1024x1024 slices, 41 planes 0.5 um apart, a
+    nuclear and an actin channel).
+
+    round(H*W / 40000) cells (at least 1), centres uniform in x and y and in
+    the middle half of z.  Nuclear channel: per cell a Gaussian nucleus
+    (sigma_xy U(12, 24) px, sigma_z U(3, 6) planes, amplitude U(0.4, 1)) and
+    40 chromatin spots (sigma_xy 2 px, sigma_z 1.5 planes, amplitude
+    U(0.2, 0.6)) scattered around its centre with the nucleus' sigmas.  Actin
+    channel: per cell 6 cubic Bezier filaments with control points within
+    +-3 sigma_xy of the centre, lying in a plane U(-4, 4) planes from it
+    (Gaussian z-profile, sigma 1.5 planes), cross-section sigma 1 px,
+    intensity U(0.2, 0.6).  Each channel is scaled by its maximum to
+    [0, 1].  Returns FP32 (2, Z, H, W).
+    """
+    rng = _rng(seed, 505)
+    vol = np.zeros((2, Z, H, W), dtype=np.float64)
+    zz = np.arange(Z, dtype=np.float64)
+    n_cells = max(1, int(round(H * W / 40000.0)))
+
+    def gauss_patch(cy, cx, sg):
+        r = int(3 * sg) + 1
+        y0, y1 = max(0, int(cy) - r), min(H, int(cy) + r + 1)
+        x0, x1 = max(0, int(cx) - r), min(W, int(cx) + r + 1)
+        if y0 >= y1 or x0 >= x1:
+            return None, 0, 0
+        yy, xx = np.meshgrid(np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
+        return np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * sg * sg)), y0, x0
+
+    for _ in range(n_cells):
+        cy, cx = rng.uniform(0, H), rng.uniform(0, W)
+        cz = rng.uniform(0.25 * (Z - 1), 0.75 * (Z - 1))
+        sxy, sz = rng.uniform(12, 24), rng.uniform(3, 6)
+        amp = rng.uniform(0.4, 1.0)
+        pt, y0, x0 = gauss_patch(cy, cx, sxy)
+        if pt is not None:
+            _add_patch(vol[0], amp * pt, y0, x0, np.exp(-(zz - cz) ** 2 / (2 * sz * sz)))
+        for _ in range(40):
+            py, px, pz = rng.normal(cy, sxy), rng.normal(cx, sxy), rng.normal(cz, sz)
+            a = rng.uniform(0.2, 0.6)
+            pt, y0, x0 = gauss_patch(py, px, 2.0)
+            if pt is not None:
+                _add_patch(vol[0], a * pt, y0, x0, np.exp(-(zz - pz) ** 2 / (2 * 1.5 * 1.5)))
+        for _ in range(6):
+            P = np.stack([rng.uniform(cy - 3 * sxy, cy + 3 * sxy, 4), rng.uniform(cx - 3 * sxy, cx + 3 * sxy, 4)],
+                         axis=1)
+            fz = cz + rng.uniform(-4, 4)
+            inten = rng.uniform(0.2, 0.6)
+            length = np.sum(np.hypot(*(np.diff(P, axis=0).T)))
+            ts = np.linspace(0.0, 1.0, max(8, int(2 * length)))
+            B = ((1 - ts) ** 3)[:, None] * P[0] + (3 * (1 - ts) ** 2 * ts)[:, None] * P[1] \
+                + (3 * (1 - ts) * ts ** 2)[:, None] * P[2] + (ts ** 3)[:, None] * P[3]
+            ylo = max(0, int(np.floor(B[:, 0].min())) - 4)
+            yhi = min(H, int(np.ceil(B[:, 0].max())) + 5)
+            xlo = max(0, int(np.floor(B[:, 1].min())) - 4)
+            xhi = min(W, int(np.ceil(B[:, 1].max())) + 5)
+            if ylo >= yhi or xlo >= xhi:
+                continue
+            patch = np.zeros((yhi - ylo, xhi - xlo))
+            d = np.arange(-4, 5)
+            dy, dx = np.meshgrid(d, d, indexing="ij")
+            ys = np.rint(B[:, 0])[:, None, None].astype(np.int64) + dy[None]
+            xs = np.rint(B[:, 1])[:, None, None].astype(np.int64) + dx[None]
+            val = inten * np.exp(-((ys - B[:, 0, None, None]) ** 2 + (xs - B[:, 1, None, None]) ** 2) / 2.0)
+            ok = (ys >= ylo) & (ys < yhi) & (xs >= xlo) & (xs < xhi)
+            np.maximum.at(patch, (ys[ok] - ylo, xs[ok] - xlo), val[ok])
+            _add_patch(vol[1], patch, ylo, xlo, np.exp(-(zz - fz) ** 2 / (2 * 1.5 * 1.5)))
+    for c in range(2):
+        m = vol[c].max()
+        if m > 0:
+            vol[c] /= m
+    return vol.astype(np.float32)
+
+
 def index_image(C: int, H: int, W: int) -> np.ndarray:
     """Pixel value = its linear CHW index (exact in FP32 below 2**24 pixels)."""
     assert C * H * W < (1 << 24)

@@ -112,3 +112,14 @@ def test_exact_targets_refused_where_no_clean_image_fits():
     assert L.n2f_batch_create(ctypes.byref(b), 1, ptrs, one, one, (ctypes.c_int * 1)(1), ctypes.byref(cfg),
                               ctypes.c_void_p(256), 1 << 20, 1) == n2f.EINVAL
     assert L.n2f_run_set_clean(None, None) == n2f.EINVAL
+
+
+def test_max_project_argument_checks_without_device():
+    L = n2f.lib()
+    assert L.n2f_max_project(None, 3, 16, None, None) == n2f.EINVAL
+    p = ctypes.c_void_p(1 << 20)
+    assert L.n2f_max_project(p, 0, 16, ctypes.c_void_p(1 << 24), None) == n2f.EINVAL
+    assert L.n2f_max_project(p, 2, 0, ctypes.c_void_p(1 << 24), None) == n2f.EINVAL
+    # output inside the stack
+    assert L.n2f_max_project(p, 2, 16, ctypes.c_void_p((1 << 20) + 64), None) == n2f.EINVAL
+    assert b"overlaps" in L.n2f_last_error()

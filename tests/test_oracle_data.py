@@ -147,6 +147,11 @@ def test_generators_are_seeded_and_in_range():
     assert m.shape == (1, 96, 80) and m.min() >= 0 and m.max() == 1.0
     q = np.round(m.astype(np.float64) * 65535.0)
     np.testing.assert_allclose(q, m.astype(np.float64) * 65535.0, atol=2e-3)
+    v = synth.cell_volume(9, 120, 100, 2)
+    assert v.shape == (2, 9, 120, 100) and v.dtype == np.float32
+    assert v.min() >= 0.0 and v[0].max() == 1.0 and v[1].max() == 1.0
+    np.testing.assert_array_equal(v, synth.cell_volume(9, 120, 100, 2))
+    assert not np.array_equal(v, synth.cell_volume(9, 120, 100, 3))
 
 
 def test_splitmix64_published_values():
