@@ -6,7 +6,7 @@ teacher-forced step within norm-wise relative error 1e-5 (FP32) or 2e-2
 (BF16) per tensor; fixed-epoch PSNR within 0.1 dB of the oracle's.  For
 BF16 the per-tensor bar is raised to twice the change that rounding the
 weights alone to BF16 makes to the exact gradient, where that is larger
-(an ill-conditioned tensor, see `bf16_sensitivity`)."""
+(an ill-conditioned tensor, see `bf16_bar`)."""
 import sys
 
 import numpy as np
@@ -15,6 +15,7 @@ import torch
 
 from oracle import n2f_oracle as O
 from paper_2108_10209_amd import n2f, synth
+from bf16_bar import bf16_bars
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -41,28 +42,6 @@ def split(vec, C):
         out[name] = np.asarray(vec[o:o + n])
         o += n
     return out
-
-
-def bf16_round(a):
-    """Round to the nearest BF16 value, ties to even (test-side estimate of
-    the BF16 path's operand rounding, not part of the oracle)."""
-    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
-    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return r.astype(np.uint32).view(np.float32).astype(np.float64)
-
-
-def bf16_sensitivity(theta, C, inp, tgt):
-    """Per-tensor relative change of the exact FP64 gradient when only the
-    64->64 weights (layers 2..8) are rounded to BF16.  A BF16 convolution
-    path cannot be closer to FP64 than this on that tensor: where a gradient
-    tensor is a near-cancelling sum (a bias gradient late in training), this
-    alone can exceed the 2e-2 bar."""
-    _, g, _ = O.gradients(theta, C, inp, tgt, H0)
-    prm = O.unflatten(theta, C)
-    for l in range(2, O.N_LAYERS + 1):
-        prm[f"W{l}"] = bf16_round(prm[f"W{l}"])
-    _, gb, _ = O.gradients(O.flatten(prm, C), C, inp, tgt, H0)
-    return {nm: rel(a, b) for (nm, a), b in zip(split(gb, C).items(), split(g, C).values())}
 
 
 def library_order(tl, tr, bl, br):
@@ -145,8 +124,7 @@ def test_quad_train_step_teacher_forced(prec, C, H, W, pre):
             tol = {nm: 1e-5 for nm, _ in O.param_spec(C)}
         else:
             inp, tgt = pairs[pre % 4]
-            sens = bf16_sensitivity(st.theta.astype(np.float32).astype(np.float64), C, inp, tgt[k])
-            tol = {nm: max(2e-2, 2 * v) for nm, v in sens.items()}
+            tol = bf16_bars(st.theta.astype(np.float32).astype(np.float64), C, inp, tgt[k])
         errs, lerr = step_errors(r, C, k, st, pairs, pre % 4)
         worst = max(errs, key=lambda nm: errs[nm] / tol[nm])
         say("  worst grad err", worst, errs[worst], "bar", tol[worst], "loss err", lerr)
