@@ -220,7 +220,8 @@ n2f_status n2f_get_lohi(n2f_run* run, float* lo, float* hi);
  * C x H'/2 x W'/2; pair p trains on image p); 4: the standardised image
  * (C x H x W); 5 + k: the last validation output of network k
  * (H x W, standardised units); 8 + p: the target image of pair p (the
- * partner downsample, or the "Exact" target; shape of image p).  Queued. */
+ * partner downsample, or the "Exact" target, N2F_ESTATE before
+ * n2f_run_set_clean; shape of image p).  Queued. */
 n2f_status n2f_get_image(n2f_run* run, int which, float* d_out);
 
 /* Queue `n_epochs` whole epochs of network `net` on the run's stream (the
@@ -255,11 +256,19 @@ n2f_status n2f_batch_create(n2f_batch** batch, int n, const float* const* d_in, 
 
 /* Run epochs of every unfinished image until all are finished or each has
  * run `max_epochs_now` more epochs; *n_active (may be NULL) reports the
- * images still training.  Synchronises. */
+ * images still training.  An image whose validation score turns non-finite
+ * is finished as failed (its n2f_batch_result returns N2F_ENUMERIC) and the
+ * others go on.  Synchronises. */
 n2f_status n2f_batch_run(n2f_batch* batch, int max_epochs_now, int* n_active);
 
-/* Write image i's result (CHW, input units) to d_out.  Synchronises. */
+/* Write image i's result (CHW, input units) to d_out.  Synchronises.
+ * N2F_ENUMERIC, writing nothing, for an image that failed. */
 n2f_status n2f_batch_result(n2f_batch* batch, int i, float* d_out);
+
+/* The run of image i, owned by the batch (never destroy it), for state
+ * exchange between n2f_batch_run calls: n2f_get_state / n2f_set_state,
+ * n2f_get_progress, n2f_get_history (checkpoint and resume of one image). */
+n2f_status n2f_batch_run_of(n2f_batch* batch, int i, n2f_run** run);
 
 /* Epochs run (all networks together) and finished flag of image i. */
 n2f_status n2f_batch_progress(n2f_batch* batch, int i, int* epochs, int* finished);

@@ -1070,6 +1070,7 @@ n2f_status n2f_get_image(n2f_run* r, int which, float* d_out) {
         N2F_HIP(hipMemcpyAsync(d_out, r->net[which - 5].y, sizeof(float) * pl.H * pl.W, hipMemcpyDeviceToDevice,
                                r->stream));
     } else if (which >= 8 && which < 12) {
+        if (pl.exact && !r->clean_set) return fail(N2F_ESTATE, "exact-target run: targets not built yet");
         const int p = which - 8;
         const int h = p < 2 ? pl.hu : pl.hl, w = p < 2 ? pl.wu : pl.wl;
         N2F_HIP(launch_extract(r->tg[p], h, w, pl.C, d_out, r->stream));

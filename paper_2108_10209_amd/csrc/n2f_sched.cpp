@@ -98,6 +98,7 @@ struct n2f_batch {
     int n = 0;
     std::vector<n2f_run*> runs;
     std::vector<int> C, net, finished, epochs, stream_of;
+    std::vector<int> status;   // N2F_ENUMERIC once a network of the image failed
     std::vector<hipStream_t> streams;
     ~n2f_batch() {
         for (n2f_run* r : runs)
@@ -158,6 +159,7 @@ n2f_status n2f_batch_create(n2f_batch** out, int n, const float* const* d_in, co
         b->finished.push_back(s == N2F_WCONSTANT ? 1 : 0);
         b->epochs.push_back(0);
         b->stream_of.push_back(si);
+        b->status.push_back(N2F_OK);
         off += align_up(wb);
     }
     *out = b;
@@ -184,6 +186,13 @@ n2f_status n2f_batch_run(n2f_batch* b, int max_now, int* n_active) {
             if (b->finished[i]) continue;
             int done = 0, ep = 0;
             n2f_status s = n2f_run_poll(b->runs[i], b->net[i], &done, &ep);
+            if (s == N2F_ENUMERIC) {
+                // this image alone fails; the others keep training
+                b->epochs[i] += ep;
+                b->status[i] = s;
+                b->finished[i] = 1;
+                continue;
+            }
             if (s < 0) return s;
             if (done) {
                 b->epochs[i] += ep;
@@ -201,10 +210,17 @@ n2f_status n2f_batch_run(n2f_batch* b, int max_now, int* n_active) {
 
 n2f_status n2f_batch_result(n2f_batch* b, int i, float* d_out) {
     if (!b || i < 0 || i >= b->n || !d_out) return sfail(N2F_EINVAL, "bad batch arguments");
+    if (b->status[i] < 0) return sfail(b->status[i], "image " + std::to_string(i) + ": validation score not finite");
     n2f_status s = n2f_result(b->runs[i], d_out);
     if (s < 0) return s;
     if (hipStreamSynchronize(b->streams[b->stream_of[i]]) != hipSuccess) return sfail(N2F_EDEVICE, "sync failed");
     return s;
+}
+
+n2f_status n2f_batch_run_of(n2f_batch* b, int i, n2f_run** run) {
+    if (!b || i < 0 || i >= b->n || !run) return sfail(N2F_EINVAL, "bad batch arguments");
+    *run = b->runs[i];
+    return N2F_OK;
 }
 
 n2f_status n2f_batch_progress(n2f_batch* b, int i, int* epochs, int* finished) {

@@ -28,7 +28,7 @@ SYMBOLS = [
     "n2f_profile_end", "n2f_run_launch_epochs", "n2f_run_poll", "n2f_batch_workspace_bytes", "n2f_batch_create",
     "n2f_batch_run", "n2f_batch_result", "n2f_batch_progress", "n2f_batch_destroy", "n2f_server_create",
     "n2f_server_submit", "n2f_server_step", "n2f_server_poll", "n2f_server_memory", "n2f_server_destroy",
-    "n2f_run_set_clean", "n2f_max_project",
+    "n2f_run_set_clean", "n2f_max_project", "n2f_batch_run_of",
 ]
 SERVER_SIMULATE = 1
 K_CONV_FWD, K_BACKWARD, K_ADAM = 0, 1, 2
@@ -105,6 +105,7 @@ def lib():
             "n2f_server_destroy": [c_void_p],
             "n2f_run_set_clean": [c_void_p, c_void_p],
             "n2f_max_project": [c_void_p, c_int, c_longlong, c_void_p, c_void_p],
+            "n2f_batch_run_of": [c_void_p, c_int, POINTER(c_void_p)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -171,15 +172,27 @@ class Run:
         self.ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device=x.device)
         assert self.ws.numel() >= nbytes
         self.nparams = param_count(self.C, self.cfg)
+        self._owned = True
         self._ptr = c_void_p()
         self.status = _check(lib().n2f_run_create(byref(self._ptr), c_void_p(x.data_ptr()), self.H, self.W, self.C,
                                                   byref(self.cfg), c_void_p(self.ws.data_ptr()), nbytes,
                                                   _stream_of(x)))
 
+    @classmethod
+    def _view(cls, ptr, shape, cfg, device):
+        """A handle on a run owned elsewhere (a batch image): state calls
+        only, never destroyed from here."""
+        r = cls.__new__(cls)
+        r.cfg, r.device, r._ptr, r._owned = cfg, device, ptr, False
+        r.C, r.H, r.W = shape
+        r.nparams = param_count(r.C, cfg)
+        r.status = OK
+        return r
+
     def close(self):
-        if self._ptr:
+        if self._ptr and self._owned:
             lib().n2f_run_destroy(self._ptr)
-            self._ptr = c_void_p()
+        self._ptr = c_void_p()
 
     def __del__(self):
         try:
@@ -357,6 +370,12 @@ class Batch:
         e, f = c_int(), c_int()
         _check(lib().n2f_batch_progress(self._ptr, i, byref(e), byref(f)))
         return e.value, bool(f.value)
+
+    def run_of(self, i: int) -> Run:
+        """State-exchange handle on image i's run (valid while the batch lives)."""
+        p = c_void_p()
+        _check(lib().n2f_batch_run_of(self._ptr, i, byref(p)))
+        return Run._view(p, self.shapes[i], self.cfg, self.images[i].device)
 
     def close(self):
         if self._ptr:

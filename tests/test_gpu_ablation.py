@@ -200,6 +200,9 @@ def test_exact_clean_image_errors_and_replacement():
     with pytest.raises(n2f.N2FError) as e:
         r.run_epochs(0, 1)
     assert e.value.code == n2f.ESTATE
+    with pytest.raises(n2f.N2FError) as e:
+        r.image(8)
+    assert e.value.code == n2f.ESTATE
     # a clean image equal to the noisy one makes every target its input
     r.set_clean(dev(noisy))
     for p in range(4):
