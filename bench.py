@@ -335,7 +335,7 @@ def main():
     ap.add_argument("--volume-z", type=int, default=41)
     ap.add_argument("--volume-size", type=int, default=1024)
     ap.add_argument("--batch-n", type=int, default=64)
-    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--fp32-sample", type=int, default=8)
     ap.add_argument("--serve-n", type=int, default=24)
     ap.add_argument("--serve-fp32-n", type=int, default=24)

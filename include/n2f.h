@@ -239,9 +239,12 @@ n2f_status n2f_run_poll(n2f_run* run, int net, int* done, int* epochs);
  * A batch trains one run per image, each with its own weights, Adam state,
  * stopping rule and workspace slice, all inside one caller workspace.  Each
  * run replays its own recorded epoch graph on one of `n_streams` HIP streams
- * (created by the batch, default priority), so the epochs of different
- * images overlap on the device; networks of a multi-channel image run one
- * after the other.  Images may differ in size and channel count. */
+ * (created by the batch, default priority; images are spread over them
+ * largest first onto the least loaded), so the epochs of different images
+ * overlap on the device; networks of a multi-channel image run one after
+ * the other.  The host serves the streams in turn (waits for one, reads its
+ * images' stopping rules, queues their next epochs) while the others run.
+ * Images may differ in size and channel count. */
 typedef struct n2f_batch n2f_batch;
 
 /* Workspace for a batch: the 256-byte aligned sum of the images' needs. */

@@ -141,12 +141,25 @@ n2f_status n2f_batch_create(n2f_batch** out, int n, const float* const* d_in, co
         delete b;
         return s;
     }
+    // streams by work, largest image first onto the least loaded stream
+    // (pixels x channels: each channel is one network trained in turn)
+    const int ns = (int)b->streams.size();
+    std::vector<int> order(n), stream_of(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    auto work = [&](int i) { return (long long)H[i] * W[i] * C[i]; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work(a) > work(c); });
+    std::vector<long long> load(ns, 0);
+    for (int i : order) {
+        const int si = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        stream_of[i] = si;
+        load[si] += work(i);
+    }
     char* ws = static_cast<char*>(d_ws);
     size_t off = 0;
     for (int i = 0; i < n; ++i) {
         size_t wb = 0;
         n2f_workspace_bytes(H[i], W[i], C[i], cfg, &wb);
-        const int si = i % (int)b->streams.size();
+        const int si = stream_of[i];
         n2f_run* r = nullptr;
         s = n2f_run_create(&r, d_in[i], H[i], W[i], C[i], cfg, ws + off, wb, b->streams[si]);
         if (s < 0) {
@@ -169,35 +182,66 @@ n2f_status n2f_batch_create(n2f_batch** out, int n, const float* const* d_in, co
 n2f_status n2f_batch_run(n2f_batch* b, int max_now, int* n_active) {
     if (!b || max_now < 1) return sfail(N2F_EINVAL, "bad batch arguments");
     std::vector<int> ran(b->n, 0);
-    for (;;) {
-        int active = 0;
-        // queue a few epochs for every image still training ...
-        for (int i = 0; i < b->n; ++i) {
+    const int ns = (int)b->streams.size();
+    std::vector<std::vector<int>> on(ns);   // images of each stream
+    for (int i = 0; i < b->n; ++i) on[b->stream_of[i]].push_back(i);
+    // queue a few epochs for every image of stream s still training; the
+    // number of images queued, or an error
+    auto feed = [&](int s, int* queued) -> n2f_status {
+        *queued = 0;
+        for (int i : on[s]) {
             if (b->finished[i] || ran[i] >= max_now) continue;
             const int k = std::min(kPollEpochs, max_now - ran[i]);
-            n2f_status s = n2f_run_launch_epochs(b->runs[i], b->net[i], k);
-            if (s < 0) return s;
+            n2f_status st = n2f_run_launch_epochs(b->runs[i], b->net[i], k);
+            if (st < 0) return st;
             ran[i] += k;
-            ++active;
+            ++*queued;
         }
-        if (!active) break;
-        // ... then read each one's stopping rule
-        for (int i = 0; i < b->n; ++i) {
+        return N2F_OK;
+    };
+    // read the stopping rule of every image of stream s (waits for the
+    // stream's queued epochs); an image whose score turned non-finite fails
+    // alone, the others go on
+    auto drain = [&](int s) -> n2f_status {
+        for (int i : on[s]) {
             if (b->finished[i]) continue;
             int done = 0, ep = 0;
-            n2f_status s = n2f_run_poll(b->runs[i], b->net[i], &done, &ep);
-            if (s == N2F_ENUMERIC) {
-                // this image alone fails; the others keep training
+            n2f_status st = n2f_run_poll(b->runs[i], b->net[i], &done, &ep);
+            if (st == N2F_ENUMERIC) {
                 b->epochs[i] += ep;
-                b->status[i] = s;
+                b->status[i] = st;
                 b->finished[i] = 1;
                 continue;
             }
-            if (s < 0) return s;
+            if (st < 0) return st;
             if (done) {
                 b->epochs[i] += ep;
                 if (++b->net[i] >= b->C[i]) b->finished[i] = 1;
             }
+        }
+        return N2F_OK;
+    };
+    // every stream gets work, then the streams are served in turn: while
+    // the host waits for one and queues its next epochs, the others run, so
+    // no stream waits for the slowest one as it would with a common round
+    std::vector<char> busy(ns, 0);
+    for (int s = 0; s < ns; ++s) {
+        int q = 0;
+        n2f_status st = feed(s, &q);
+        if (st < 0) return st;
+        busy[s] = q > 0;
+    }
+    for (bool any = true; any;) {
+        any = false;
+        for (int s = 0; s < ns; ++s) {
+            if (!busy[s]) continue;
+            any = true;
+            n2f_status st = drain(s);
+            if (st < 0) return st;
+            int q = 0;
+            st = feed(s, &q);
+            if (st < 0) return st;
+            busy[s] = q > 0;
         }
     }
     if (n_active) {
