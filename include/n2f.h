@@ -194,6 +194,22 @@ n2f_status n2f_get_state(n2f_run* run, int net, float* theta, float* m, float* v
 n2f_status n2f_set_state(n2f_run* run, int net, const float* theta, const float* m,
                          const float* v, long long t);
 
+/* Whole-network checkpoints (resume, or moving a run between processes):
+ * everything network `net` carries from epoch to epoch -- parameters, Adam
+ * moments and step, the stopping-rule state and validation history, the
+ * running output sum and the best and last outputs -- as an opaque host blob
+ * of n2f_checkpoint_bytes() bytes.  A run created from the same image with
+ * the same configuration and loaded from it continues exactly as the saved
+ * run would have (bit-identical results).  Loading checks the image size,
+ * channel count, precision, downsampling, target mode and epoch cap of the
+ * blob against the run (N2F_EINVAL on a mismatch or a short buffer); the
+ * other settings (learning rate, pair order) are the loading run's.  An
+ * exact-target run needs n2f_run_set_clean again.  Save and load
+ * synchronise. */
+n2f_status n2f_checkpoint_bytes(n2f_run* run, size_t* bytes);
+n2f_status n2f_save_checkpoint(n2f_run* run, int net, void* host_buf, size_t bytes);
+n2f_status n2f_load_checkpoint(n2f_run* run, int net, const void* host_buf, size_t bytes);
+
 /* Gradient (canonical layout, host buffer) that the last Adam step of
  * network `net` used, and that step's mean BCE loss.  Synchronises. */
 n2f_status n2f_get_grad(n2f_run* run, int net, float* g, double* loss);

@@ -987,6 +987,80 @@ n2f_status n2f_set_state(n2f_run* r, int net, const float* theta, const float* m
     return N2F_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Checkpoint blob: this header, then a copy of the network's workspace block
+// (state struct, parameters, moments, packed weights, validation history,
+// running output sum, best and last outputs).  The fields below fix that
+// block's layout, so a checkpoint loads only into a run that matches them.
+struct CkptHeader {
+    unsigned long long magic;
+    int H, W, C, precision, downsample, exact, max_trace, reserved;
+    unsigned long long net_bytes;
+};
+constexpr unsigned long long kCkptMagic = 0x31544b4350463248ULL;   // "H2FPCKT1"
+
+CkptHeader ckpt_header(const n2f_run* r) {
+    CkptHeader h{};
+    h.magic = kCkptMagic;
+    h.H = r->pl.H;
+    h.W = r->pl.W;
+    h.C = r->pl.C;
+    h.precision = r->pl.bf;
+    h.downsample = r->pl.quad;
+    h.exact = r->pl.exact;
+    h.max_trace = r->pl.max_trace;
+    h.net_bytes = r->pl.net_bytes;
+    return h;
+}
+}  // namespace
+
+extern "C" {
+
+n2f_status n2f_checkpoint_bytes(n2f_run* r, size_t* bytes) {
+    if (!r || !bytes) return fail(N2F_EINVAL, "run or bytes is NULL");
+    if (r->constant) return fail(N2F_ESTATE, "constant image: nothing to checkpoint");
+    *bytes = sizeof(CkptHeader) + r->pl.net_bytes;
+    return N2F_OK;
+}
+
+n2f_status n2f_save_checkpoint(n2f_run* r, int net, void* buf, size_t bytes) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    if (!buf || bytes < sizeof(CkptHeader) + r->pl.net_bytes) return fail(N2F_EINVAL, "checkpoint buffer too small");
+    const CkptHeader h = ckpt_header(r);
+    std::memcpy(buf, &h, sizeof(h));
+    N2F_HIP(hipMemcpyAsync(static_cast<char*>(buf) + sizeof(h), r->ws + r->pl.o_net[net], r->pl.net_bytes,
+                           hipMemcpyDeviceToHost, r->stream));
+    N2F_HIP(hipStreamSynchronize(r->stream));
+    return N2F_OK;
+}
+
+n2f_status n2f_load_checkpoint(n2f_run* r, int net, const void* buf, size_t bytes) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    if (!buf || bytes < sizeof(CkptHeader)) return fail(N2F_EINVAL, "checkpoint buffer too small");
+    CkptHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    const CkptHeader mine = ckpt_header(r);
+    if (h.magic != kCkptMagic) return fail(N2F_EINVAL, "not a checkpoint");
+    if (h.H != mine.H || h.W != mine.W || h.C != mine.C || h.precision != mine.precision ||
+        h.downsample != mine.downsample || h.exact != mine.exact || h.max_trace != mine.max_trace ||
+        h.net_bytes != mine.net_bytes)
+        return fail(N2F_EINVAL, "checkpoint of a different image size or configuration");
+    if (bytes < sizeof(h) + h.net_bytes) return fail(N2F_EINVAL, "checkpoint buffer too small");
+    N2F_HIP(hipMemcpyAsync(r->ws + r->pl.o_net[net], static_cast<const char*>(buf) + sizeof(h), r->pl.net_bytes,
+                           hipMemcpyHostToDevice, r->stream));
+    N2F_HIP(hipStreamSynchronize(r->stream));
+    DevState st;
+    s = read_state(r, net, &st);
+    if (s != N2F_OK) return s;
+    r->host_done[net] = st.done != 0;
+    r->host_epochs[net] = st.epoch;
+    return N2F_OK;
+}
+
 n2f_status n2f_get_grad(n2f_run* r, int net, float* g, double* loss) {
     n2f_status s = check_run(r, net);
     if (s != N2F_OK) return s;

@@ -28,7 +28,8 @@ SYMBOLS = [
     "n2f_profile_end", "n2f_run_launch_epochs", "n2f_run_poll", "n2f_batch_workspace_bytes", "n2f_batch_create",
     "n2f_batch_run", "n2f_batch_result", "n2f_batch_progress", "n2f_batch_destroy", "n2f_server_create",
     "n2f_server_submit", "n2f_server_step", "n2f_server_poll", "n2f_server_memory", "n2f_server_destroy",
-    "n2f_run_set_clean", "n2f_max_project", "n2f_batch_run_of",
+    "n2f_run_set_clean", "n2f_max_project", "n2f_batch_run_of", "n2f_checkpoint_bytes", "n2f_save_checkpoint",
+    "n2f_load_checkpoint",
 ]
 SERVER_SIMULATE = 1
 K_CONV_FWD, K_BACKWARD, K_ADAM = 0, 1, 2
@@ -106,6 +107,9 @@ def lib():
             "n2f_run_set_clean": [c_void_p, c_void_p],
             "n2f_max_project": [c_void_p, c_int, c_longlong, c_void_p, c_void_p],
             "n2f_batch_run_of": [c_void_p, c_int, POINTER(c_void_p)],
+            "n2f_checkpoint_bytes": [c_void_p, POINTER(c_size_t)],
+            "n2f_save_checkpoint": [c_void_p, c_int, c_void_p, c_size_t],
+            "n2f_load_checkpoint": [c_void_p, c_int, c_void_p, c_size_t],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -242,6 +246,18 @@ class Run:
         assert th.size == self.nparams
         _check(lib().n2f_set_state(self._ptr, net, th.ctypes.data, None if mm is None else mm.ctypes.data,
                                    None if vv is None else vv.ctypes.data, int(t)))
+
+    def save_checkpoint(self, net: int = 0) -> np.ndarray:
+        """Opaque checkpoint of network `net` (uint8 host array)."""
+        nb = c_size_t()
+        _check(lib().n2f_checkpoint_bytes(self._ptr, byref(nb)))
+        buf = np.empty(nb.value, np.uint8)
+        _check(lib().n2f_save_checkpoint(self._ptr, net, buf.ctypes.data, nb.value))
+        return buf
+
+    def load_checkpoint(self, net: int, buf) -> None:
+        b = np.ascontiguousarray(buf, np.uint8)
+        _check(lib().n2f_load_checkpoint(self._ptr, net, b.ctypes.data, b.size))
 
     def get_grad(self, net: int = 0):
         g = np.empty(self.nparams, np.float32)

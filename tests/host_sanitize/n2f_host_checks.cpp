@@ -179,6 +179,10 @@ static int argument_checks() {
     CHECK(n2f_get_lohi(nullptr, nullptr, nullptr) == N2F_EINVAL);
     CHECK(n2f_get_image(nullptr, 0, nullptr) == N2F_EINVAL);
     CHECK(n2f_run_set_clean(nullptr, nullptr) == N2F_EINVAL);
+    size_t cb = 0;
+    CHECK(n2f_checkpoint_bytes(nullptr, &cb) == N2F_EINVAL);
+    CHECK(n2f_save_checkpoint(nullptr, 0, nullptr, 0) == N2F_EINVAL);
+    CHECK(n2f_load_checkpoint(nullptr, 0, nullptr, 0) == N2F_EINVAL);
     CHECK(n2f_run_destroy(nullptr) == N2F_EINVAL);
     CHECK(n2f_denoise(nullptr, nullptr, 8, 8, 1, &d, nullptr, 0, nullptr) == N2F_EINVAL);
     CHECK(n2f_max_project(nullptr, 1, 1, nullptr, nullptr) == N2F_EINVAL);
