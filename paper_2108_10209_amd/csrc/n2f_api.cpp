@@ -929,8 +929,8 @@ n2f_status n2f_max_project(const float* d_stack, int n_slices, long long npix, f
     if (!d_stack || !d_out) return fail(N2F_EINVAL, "stack or output is NULL");
     if (n_slices < 1 || npix < 1) return fail(N2F_EINVAL, "need n_slices >= 1 and npix >= 1");
     if (npix > (1LL << 40) / n_slices) return fail(N2F_EINVAL, "stack too large");
-    const char *a = reinterpret_cast<const char*>(d_stack), *b = reinterpret_cast<const char*>(d_out);
-    if (b < a + sizeof(float) * n_slices * npix && a < b + sizeof(float) * npix)
+    const uintptr_t a = reinterpret_cast<uintptr_t>(d_stack), b = reinterpret_cast<uintptr_t>(d_out);
+    if (b < a + sizeof(float) * (uintptr_t)n_slices * (uintptr_t)npix && a < b + sizeof(float) * (uintptr_t)npix)
         return fail(N2F_EINVAL, "output overlaps the stack");
     N2F_HIP(launch_max_project(d_stack, n_slices, npix, d_out, stream));
     return N2F_OK;
