@@ -8,9 +8,11 @@ quantity compared.  Runs the CPU FP64 reference (oracle/n2f_oracle.py) on the
 1), early stopping with patience 100, initial weights from SplitMix64 seeds
 0..n-1, and stores per-seed PSNR, epochs and best epochs.
 
-    python tests/golden/make_seed_golden.py --seeds 32 --workers 4
+    python tests/golden/make_seed_golden.py --seeds 128 --workers 7
 
-Calls only the oracle and the input generators.
+Seeds already stored in the output file are kept and only the missing ones
+are run (each worker single-threaded).  Calls only the oracle and the input
+generators.
 """
 import argparse
 import json
@@ -18,6 +20,9 @@ import os
 import sys
 import time
 from multiprocessing import Pool
+
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
@@ -37,12 +42,18 @@ def run_one(seed):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--seeds", type=int, default=32)
-    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--seeds", type=int, default=128)
+    ap.add_argument("--workers", type=int, default=7)
     ap.add_argument("--out", default=os.path.join(HERE, "oracle_psnr_64_sigma25_seeds.json"))
     a = ap.parse_args()
+    have = {}
+    if os.path.exists(a.out):
+        have = {r["seed"]: r for r in json.load(open(a.out))["runs"]}
+    todo = [s for s in range(a.seeds) if s not in have]
     with Pool(a.workers) as pool:
-        runs = pool.map(run_one, range(a.seeds))
+        for r in pool.imap_unordered(run_one, todo):
+            have[r["seed"]] = r
+    runs = [have[s] for s in range(a.seeds)]
     import numpy as np
     from paper_2108_10209_amd import synth
     clean, noisy = synth.small_64(0)

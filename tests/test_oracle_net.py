@@ -264,3 +264,71 @@ def test_validation_mse_fp64():
     x = np.random.default_rng(1).uniform(0, 1, (1, 12, 10))
     y, v = O.validate(theta, C, x, 0, O.Hyper())
     assert abs(v - math.fsum(((y - x[0]) ** 2).ravel()) / y.size) < 1e-16
+
+
+def _cb_pairs_by_loops(xs):
+    """The four checkerboard pairs written as plain loops (0-based; the
+    complementary parity class of each row/column packed in order), for the
+    routing check below."""
+    C, H, W = xs.shape
+    ue = np.empty((C, H, W // 2)); uo = np.empty_like(ue)
+    le = np.empty((C, H // 2, W)); lo_ = np.empty_like(le)
+    for c in range(C):
+        for i in range(H):
+            for j in range(W // 2):
+                ue[c, i, j] = xs[c, i, 2 * j + (i % 2)]
+                uo[c, i, j] = xs[c, i, 2 * j + 1 - (i % 2)]
+        for i in range(H // 2):
+            for j in range(W):
+                le[c, i, j] = xs[c, 2 * i + (j % 2), j]
+                lo_[c, i, j] = xs[c, 2 * i + 1 - (j % 2), j]
+    return [(ue, uo), (uo, ue), (le, lo_), (lo_, le)]
+
+
+def test_rgb_routing_matches_torch_per_channel_nets():
+    """Multi-channel images (Fig. 2a caption: RGB predicted one channel at a
+    time; Methods, validation paragraph).  A PyTorch FP64 run of two fixed
+    epochs with three independent networks: network k sees all three input
+    channels, trains on target channel k, is validated by MSE against
+    channel k of the standardised input and writes output channel k.  The
+    oracle's per-network scores, its validate() for every k and its output
+    channels must all agree with it; training every network on channel 0, or
+    scoring against channel 0, fails here because the channels differ."""
+    C, H, W, width, n_layers, E = 3, 8, 10, 6, 3, 2
+    h = O.Hyper(width=width, n_layers=n_layers, fixed_epochs=E)
+    rng = np.random.default_rng(77)
+    spec = O.param_spec(C, width, n_layers)
+    theta0 = np.stack([np.concatenate([rng.uniform(-0.4, 0.4, int(np.prod(s))) for _, s in spec])
+                       for _ in range(C)])
+    x = rng.uniform(0, 1, (C, H, W)) * np.array([1.0, 0.6, 0.3])[:, None, None] + np.array([0, 0.3, 0.5])[:, None,
+                                                                                                        None]
+    xs = (x - x.min()) / (x.max() - x.min())
+    pairs = _cb_pairs_by_loops(xs)
+    ref_y, ref_hist, ref_theta = [], [], []
+    for k in range(C):
+        net = _torch_net(C, width, n_layers)
+        _load(net, theta0[k], C, width, n_layers)
+        opt = torch.optim.Adam(net.parameters(), lr=1e-3)
+        hist = []
+        for _ in range(E):
+            for inp, tgt in pairs:
+                opt.zero_grad()
+                z = net(torch.tensor(inp)[None])[0, 0]
+                torch.nn.functional.binary_cross_entropy_with_logits(z, torch.tensor(tgt[k])).backward()
+                opt.step()
+            with torch.no_grad():
+                y = torch.sigmoid(net(torch.tensor(xs)[None])[0, 0]).numpy()
+            hist.append(float(np.mean((y - xs[k]) ** 2)))
+        ref_y.append(y)
+        ref_hist.append(hist)
+        ref_theta.append(_read(net))
+    r = O.denoise(x, theta0, h)
+    for k in range(C):
+        np.testing.assert_allclose(r.history[k], ref_hist[k], rtol=1e-10, atol=0)
+        np.testing.assert_allclose(r.y_std[k], ref_y[k], rtol=0, atol=1e-12)
+        yk, vk = O.validate(ref_theta[k], C, xs, k, h)
+        np.testing.assert_allclose(yk, ref_y[k], rtol=0, atol=1e-12)
+        assert abs(vk - ref_hist[k][-1]) <= 1e-12 * ref_hist[k][-1]
+    # the routing is visible: networks and their scores differ per channel
+    assert min(abs(ref_hist[0][-1] - ref_hist[1][-1]), abs(ref_hist[1][-1] - ref_hist[2][-1])) > 1e-4
+    np.testing.assert_allclose(r.y, O.destandardize(r.y_std, x.min(), x.max()), rtol=0, atol=1e-12)
