@@ -54,6 +54,7 @@ typedef int n2f_status;
 #define N2F_EDEVICE    (-3)   /* a HIP runtime call failed */
 #define N2F_ESTATE     (-4)   /* call not valid in the run's current state */
 #define N2F_ENUMERIC   (-5)   /* a validation score became NaN or infinite */
+#define N2F_ECANCELED  (-6)   /* a served request was cancelled before it finished */
 #define N2F_WCONSTANT   1     /* constant image: returned unchanged, nothing trained */
 #define N2F_WCAPPED     2     /* max_epochs reached before the stopping rule fired */
 
@@ -253,31 +254,57 @@ n2f_status n2f_run_poll(n2f_run* run, int net, int* done, int* epochs);
 
 /* ---- many independent images ----
  * A batch trains one run per image, each with its own weights, Adam state,
- * stopping rule and workspace slice, all inside one caller workspace.  Each
- * run replays its own recorded epoch graph on one of `n_streams` HIP streams
- * (created by the batch, default priority; images are spread over them
- * largest first onto the least loaded), so the epochs of different images
- * overlap on the device; networks of a multi-channel image run one after
- * the other.  The host serves the streams in turn (waits for one, reads its
- * images' stopping rules, queues their next epochs) while the others run.
- * Images may differ in size and channel count. */
+ * stopping rule and workspace slice.  Each run replays its own recorded
+ * epoch graph on one of the batch's streams (images spread largest first
+ * onto the least loaded), so the epochs of different images overlap on the
+ * device; networks of a multi-channel image run one after the other.  The
+ * host serves the streams in turn (waits for one, reads its images'
+ * stopping rules, queues their next epochs) while the others run.  Images
+ * may differ in size and channel count.  Every batch call is made between
+ * epochs, so images join (n2f_batch_add) and leave (n2f_batch_remove) at
+ * epoch boundaries while the others keep their state. */
 typedef struct n2f_batch n2f_batch;
 
 /* Workspace for a batch: the 256-byte aligned sum of the images' needs. */
 n2f_status n2f_batch_workspace_bytes(int n, const int* H, const int* W, const int* C, const n2f_config* cfg,
                                      size_t* bytes);
 
-/* Create the runs (each reads its device CHW input d_in[i] during this
- * call).  Synchronises.  Constant images are finished at once.
- * cfg->exact_targets is refused (N2F_EINVAL), here and by the server. */
+/* Create the runs; image i reads its device CHW input d_in[i] during this
+ * call, after the work already queued on the caller's `stream` (the batch's
+ * streams wait for it, so inputs produced there are complete).  d_ws: 256-byte
+ * aligned device workspace of n2f_batch_workspace_bytes(), image i's slice
+ * at the aligned prefix sum of the sizes before it; kept until destroy.
+ * n_streams >= 1: the batch creates that many streams (default priority),
+ * at most one per image; n_streams = 0: everything runs on `stream` itself,
+ * one image after another.  Synchronises.  Constant images are finished at
+ * once.  cfg->exact_targets is refused (N2F_EINVAL), here and by the
+ * server. */
 n2f_status n2f_batch_create(n2f_batch** batch, int n, const float* const* d_in, const int* H, const int* W,
-                            const int* C, const n2f_config* cfg, void* d_ws, size_t ws_bytes, int n_streams);
+                            const int* C, const n2f_config* cfg, void* d_ws, size_t ws_bytes, int n_streams,
+                            hipStream_t stream);
+
+/* Join a new image between n2f_batch_run calls (an epoch boundary): its run
+ * is created on the least loaded batch stream, reading the device CHW image
+ * d_in after the work queued on the batch's caller stream, with its own
+ * 256-byte aligned workspace d_ws of at least n2f_workspace_bytes(H, W, C)
+ * bytes (owned by the caller, kept until the image is removed or the batch
+ * destroyed).  *index (may be NULL) receives the image's index (n so far).
+ * Synchronises.  N2F_ENOMEM for a workspace that is too small. */
+n2f_status n2f_batch_add(n2f_batch* batch, const float* d_in, int H, int W, int C, void* d_ws, size_t ws_bytes,
+                         int* index);
+
+/* Image i leaves the batch between n2f_batch_run calls: its queued work
+ * ends, its run is destroyed and its workspace slice is the caller's again;
+ * the other images keep training unchanged.  Later calls on image i return
+ * N2F_ESTATE (result, run_of, remove); n2f_batch_progress reports it
+ * finished.  Synchronises image i's stream. */
+n2f_status n2f_batch_remove(n2f_batch* batch, int i);
 
 /* Run epochs of every unfinished image until all are finished or each has
  * run `max_epochs_now` more epochs; *n_active (may be NULL) reports the
  * images still training.  An image whose validation score turns non-finite
  * is finished as failed (its n2f_batch_result returns N2F_ENUMERIC) and the
- * others go on.  Synchronises. */
+ * others go on.  Synchronises every batch stream. */
 n2f_status n2f_batch_run(n2f_batch* batch, int max_epochs_now, int* n_active);
 
 /* Write image i's result (CHW, input units) to d_out.  Synchronises.
@@ -313,11 +340,22 @@ typedef struct n2f_server n2f_server;
 n2f_status n2f_server_create(n2f_server** srv, const n2f_config* cfg, void* d_arena, size_t arena_bytes,
                              int n_streams, int max_active, int flags);
 
-/* Queue a request (d_in and d_out: device CHW images owned by the caller,
- * kept until the id is reported finished).  N2F_ENOMEM if it could never
- * fit in the arena. */
+/* Queue a request.  d_in and d_out: device CHW images owned by the caller,
+ * kept alive and untouched until the id is reported by n2f_server_poll.
+ * `stream`: the caller's stream on which d_in is produced; admission reads
+ * d_in only after the work queued there before this call (an event recorded
+ * now).  When the id is reported, d_out is complete on the device.  The id
+ * must not be queued or active already (N2F_EINVAL).  N2F_ENOMEM if the
+ * request could never fit in the arena. */
 n2f_status n2f_server_submit(n2f_server* srv, long long id, const float* d_in, float* d_out, int H, int W, int C,
-                             int sim_epochs);
+                             int sim_epochs, hipStream_t stream);
+
+/* Cancel a queued or active request: it leaves at once (an active run's
+ * queued epochs end first, then its arena range is freed), d_out is not
+ * written, and n2f_server_poll reports the id with N2F_ECANCELED.
+ * N2F_EINVAL for an id that is neither queued nor active (e.g. finished).
+ * Synchronises the request's stream if it is active. */
+n2f_status n2f_server_cancel(n2f_server* srv, long long id);
 
 /* One scheduling round as described above.  Synchronises the active
  * streams.  Reports active and queued request counts (pointers may be NULL). */

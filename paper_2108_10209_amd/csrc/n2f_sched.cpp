@@ -97,15 +97,62 @@ struct n2f_batch {
     n2f_config cfg;
     int n = 0;
     std::vector<n2f_run*> runs;
-    std::vector<int> C, net, finished, epochs, stream_of;
+    std::vector<int> C, net, finished, epochs, stream_of, removed;
+    std::vector<long long> work;   // pixels x channels of each image
     std::vector<int> status;   // N2F_ENUMERIC once a network of the image failed
     std::vector<hipStream_t> streams;
+    bool own_streams = true;   // false: the batch runs on the caller's stream alone
+    hipStream_t caller = nullptr;
     ~n2f_batch() {
         for (n2f_run* r : runs)
             if (r) n2f_run_destroy(r);
-        for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+        if (own_streams)
+            for (hipStream_t s : streams) (void)hipStreamDestroy(s);
     }
 };
+
+namespace {
+
+// Make stream `s` wait for the work queued on `caller` so far.
+n2f_status order_after(hipStream_t s, hipStream_t caller) {
+    if (s == caller) return N2F_OK;
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+        return sfail(N2F_EDEVICE, "event creation failed");
+    hipError_t e = hipEventRecord(ev, caller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+    (void)hipEventDestroy(ev);   // released once the wait has been satisfied
+    return e == hipSuccess ? N2F_OK : sfail(N2F_EDEVICE, "stream ordering failed");
+}
+
+// Create the run of a new batch image on the least loaded stream (by work)
+// and append it; *index receives its index.
+n2f_status batch_append(n2f_batch* b, const float* d_in, int H, int W, int C, void* ws, size_t wb, int* index) {
+    const int ns = (int)b->streams.size();
+    std::vector<long long> load(ns, 0);
+    for (int i = 0; i < b->n; ++i)
+        if (!b->removed[i] && !b->finished[i]) load[b->stream_of[i]] += b->work[i];
+    const int si = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    n2f_status s = order_after(b->streams[si], b->caller);
+    if (s != N2F_OK) return s;
+    n2f_run* r = nullptr;
+    s = n2f_run_create(&r, d_in, H, W, C, &b->cfg, ws, wb, b->streams[si]);
+    if (s < 0) return s;
+    b->runs.push_back(r);
+    b->C.push_back(C);
+    b->net.push_back(0);
+    b->finished.push_back(s == N2F_WCONSTANT ? 1 : 0);
+    b->epochs.push_back(0);
+    b->stream_of.push_back(si);
+    b->removed.push_back(0);
+    b->work.push_back((long long)H * W * C);
+    b->status.push_back(N2F_OK);
+    if (index) *index = b->n;
+    b->n++;
+    return N2F_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -124,10 +171,12 @@ n2f_status n2f_batch_workspace_bytes(int n, const int* H, const int* W, const in
 }
 
 n2f_status n2f_batch_create(n2f_batch** out, int n, const float* const* d_in, const int* H, const int* W,
-                            const int* C, const n2f_config* cfg, void* d_ws, size_t ws_bytes, int n_streams) {
-    if (!out || !d_in || !d_ws || !cfg || n < 1 || n_streams < 1) return sfail(N2F_EINVAL, "bad batch arguments");
+                            const int* C, const n2f_config* cfg, void* d_ws, size_t ws_bytes, int n_streams,
+                            hipStream_t stream) {
+    if (!out || !d_in || !d_ws || !cfg || n < 1 || n_streams < 0) return sfail(N2F_EINVAL, "bad batch arguments");
     *out = nullptr;
     if (cfg->exact_targets) return sfail(N2F_EINVAL, "exact targets need a clean image per run: not in a batch");
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return sfail(N2F_EINVAL, "workspace must be 256-byte aligned");
     size_t need = 0;
     n2f_status s = n2f_batch_workspace_bytes(n, H, W, C, cfg, &need);
     if (s != N2F_OK) return s;
@@ -135,33 +184,55 @@ n2f_status n2f_batch_create(n2f_batch** out, int n, const float* const* d_in, co
     n2f_batch* b = new (std::nothrow) n2f_batch();
     if (!b) return sfail(N2F_ENOMEM, "host allocation failed");
     b->cfg = *cfg;
-    b->n = n;
-    s = make_streams(b->streams, std::min(n, n_streams));
-    if (s != N2F_OK) {
-        delete b;
-        return s;
+    b->caller = stream;
+    if (n_streams == 0) {
+        b->own_streams = false;
+        b->streams.push_back(stream);
+    } else {
+        s = make_streams(b->streams, std::min(n, n_streams));
+        if (s != N2F_OK) {
+            delete b;
+            return s;
+        }
     }
-    // streams by work, largest image first onto the least loaded stream
-    // (pixels x channels: each channel is one network trained in turn)
-    const int ns = (int)b->streams.size();
-    std::vector<int> order(n), stream_of(n);
+    // images largest first onto the least loaded stream (pixels x channels:
+    // each channel is one network trained in turn); indices keep the
+    // caller's order
+    std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     auto work = [&](int i) { return (long long)H[i] * W[i] * C[i]; };
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work(a) > work(c); });
+    std::vector<size_t> off(n);
+    size_t o = 0;
+    for (int i = 0; i < n; ++i) {
+        size_t wb = 0;
+        n2f_workspace_bytes(H[i], W[i], C[i], cfg, &wb);
+        off[i] = o;
+        o += align_up(wb);
+    }
+    // create in the caller's order, with the stream chosen by the sorted pass
+    const int ns = (int)b->streams.size();
+    std::vector<int> stream_of(n);
     std::vector<long long> load(ns, 0);
     for (int i : order) {
         const int si = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         stream_of[i] = si;
         load[si] += work(i);
     }
+    for (int si = 0; si < ns; ++si) {
+        s = order_after(b->streams[si], stream);
+        if (s != N2F_OK) {
+            delete b;
+            return s;
+        }
+    }
     char* ws = static_cast<char*>(d_ws);
-    size_t off = 0;
     for (int i = 0; i < n; ++i) {
         size_t wb = 0;
         n2f_workspace_bytes(H[i], W[i], C[i], cfg, &wb);
         const int si = stream_of[i];
         n2f_run* r = nullptr;
-        s = n2f_run_create(&r, d_in[i], H[i], W[i], C[i], cfg, ws + off, wb, b->streams[si]);
+        s = n2f_run_create(&r, d_in[i], H[i], W[i], C[i], cfg, ws + off[i], wb, b->streams[si]);
         if (s < 0) {
             delete b;
             return s;
@@ -172,10 +243,34 @@ n2f_status n2f_batch_create(n2f_batch** out, int n, const float* const* d_in, co
         b->finished.push_back(s == N2F_WCONSTANT ? 1 : 0);
         b->epochs.push_back(0);
         b->stream_of.push_back(si);
+        b->removed.push_back(0);
+        b->work.push_back(work(i));
         b->status.push_back(N2F_OK);
-        off += align_up(wb);
+        b->n++;
     }
     *out = b;
+    return N2F_OK;
+}
+
+n2f_status n2f_batch_add(n2f_batch* b, const float* d_in, int H, int W, int C, void* d_ws, size_t ws_bytes,
+                         int* index) {
+    if (!b || !d_in || !d_ws) return sfail(N2F_EINVAL, "bad batch arguments");
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return sfail(N2F_EINVAL, "workspace must be 256-byte aligned");
+    size_t wb = 0;
+    n2f_status s = n2f_workspace_bytes(H, W, C, &b->cfg, &wb);
+    if (s != N2F_OK) return s;
+    if (ws_bytes < wb) return sfail(N2F_ENOMEM, "workspace too small: need " + std::to_string(wb) + " bytes");
+    return batch_append(b, d_in, H, W, C, d_ws, wb, index);
+}
+
+n2f_status n2f_batch_remove(n2f_batch* b, int i) {
+    if (!b || i < 0 || i >= b->n) return sfail(N2F_EINVAL, "bad batch arguments");
+    if (b->removed[i]) return sfail(N2F_ESTATE, "image " + std::to_string(i) + " already removed");
+    if (hipStreamSynchronize(b->streams[b->stream_of[i]]) != hipSuccess) return sfail(N2F_EDEVICE, "sync failed");
+    n2f_run_destroy(b->runs[i]);
+    b->runs[i] = nullptr;
+    b->removed[i] = 1;
+    b->finished[i] = 1;
     return N2F_OK;
 }
 
@@ -254,6 +349,7 @@ n2f_status n2f_batch_run(n2f_batch* b, int max_now, int* n_active) {
 
 n2f_status n2f_batch_result(n2f_batch* b, int i, float* d_out) {
     if (!b || i < 0 || i >= b->n || !d_out) return sfail(N2F_EINVAL, "bad batch arguments");
+    if (b->removed[i]) return sfail(N2F_ESTATE, "image " + std::to_string(i) + " was removed");
     if (b->status[i] < 0) return sfail(b->status[i], "image " + std::to_string(i) + ": validation score not finite");
     n2f_status s = n2f_result(b->runs[i], d_out);
     if (s < 0) return s;
@@ -263,6 +359,7 @@ n2f_status n2f_batch_result(n2f_batch* b, int i, float* d_out) {
 
 n2f_status n2f_batch_run_of(n2f_batch* b, int i, n2f_run** run) {
     if (!b || i < 0 || i >= b->n || !run) return sfail(N2F_EINVAL, "bad batch arguments");
+    if (b->removed[i]) return sfail(N2F_ESTATE, "image " + std::to_string(i) + " was removed");
     *run = b->runs[i];
     return N2F_OK;
 }
@@ -270,7 +367,7 @@ n2f_status n2f_batch_run_of(n2f_batch* b, int i, n2f_run** run) {
 n2f_status n2f_batch_progress(n2f_batch* b, int i, int* epochs, int* finished) {
     if (!b || i < 0 || i >= b->n) return sfail(N2F_EINVAL, "bad batch arguments");
     int ep = b->epochs[i];
-    if (!b->finished[i] && b->net[i] < b->C[i]) {
+    if (!b->finished[i] && !b->removed[i] && b->net[i] < b->C[i]) {
         int cur = 0;
         if (n2f_get_progress(b->runs[i], b->net[i], &cur, nullptr, nullptr, nullptr) == N2F_OK) ep += cur;
     }
@@ -297,6 +394,7 @@ struct n2f_server {
         float* out;
         int H, W, C, sim_epochs;
         size_t bytes;
+        hipEvent_t ready;   // recorded on the submitter's stream: the input is complete
     };
     struct Active {
         Req q;
@@ -316,14 +414,19 @@ struct n2f_server {
     std::deque<std::pair<long long, int>> finished;
     explicit n2f_server(size_t bytes) : arena(bytes) {}
     ~n2f_server() {
+        for (hipStream_t s : streams) (void)hipStreamSynchronize(s);   // queued epochs end first
         for (Active& a : active)
             if (a.run) n2f_run_destroy(a.run);
+        for (Req& q : queue)
+            if (q.ready) (void)hipEventDestroy(q.ready);
         for (hipStream_t s : streams) (void)hipStreamDestroy(s);
     }
 };
 
 namespace {
 
+// Finish active request idx with `status`: destroy its run, free its arena
+// range, report its id.
 void retire(n2f_server* v, size_t idx, int status) {
     n2f_server::Active& a = v->active[idx];
     if (a.run) n2f_run_destroy(a.run);
@@ -366,15 +469,48 @@ n2f_status n2f_server_create(n2f_server** out, const n2f_config* cfg, void* d_ar
 }
 
 n2f_status n2f_server_submit(n2f_server* v, long long id, const float* d_in, float* d_out, int H, int W, int C,
-                             int sim_epochs) {
+                             int sim_epochs, hipStream_t stream) {
     if (!v) return sfail(N2F_EINVAL, "server is NULL");
     if (!v->simulate && (!d_in || !d_out)) return sfail(N2F_EINVAL, "input or output is NULL");
     size_t bytes = 0;
     n2f_status s = n2f_workspace_bytes(H, W, C, &v->cfg, &bytes);
     if (s != N2F_OK) return s;
     if (align_up(bytes) > v->arena.size()) return sfail(N2F_ENOMEM, "request can never fit in the arena");
-    v->queue.push_back({id, d_in, d_out, H, W, C, std::max(1, sim_epochs), bytes});
+    for (const n2f_server::Req& q : v->queue)
+        if (q.id == id) return sfail(N2F_EINVAL, "id " + std::to_string(id) + " is already queued");
+    for (const n2f_server::Active& a : v->active)
+        if (a.q.id == id) return sfail(N2F_EINVAL, "id " + std::to_string(id) + " is already active");
+    hipEvent_t ev = nullptr;
+    if (!v->simulate) {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+            return sfail(N2F_EDEVICE, "event creation failed");
+        if (hipEventRecord(ev, stream) != hipSuccess) {
+            (void)hipEventDestroy(ev);
+            return sfail(N2F_EDEVICE, "event record failed");
+        }
+    }
+    v->queue.push_back({id, d_in, d_out, H, W, C, std::max(1, sim_epochs), bytes, ev});
     return N2F_OK;
+}
+
+n2f_status n2f_server_cancel(n2f_server* v, long long id) {
+    if (!v) return sfail(N2F_EINVAL, "server is NULL");
+    for (auto it = v->queue.begin(); it != v->queue.end(); ++it) {
+        if (it->id != id) continue;
+        if (it->ready) (void)hipEventDestroy(it->ready);
+        v->queue.erase(it);
+        v->finished.emplace_back(id, N2F_ECANCELED);
+        return N2F_OK;
+    }
+    for (size_t i = 0; i < v->active.size(); ++i) {
+        if (v->active[i].q.id != id) continue;
+        // the run's queued epochs finish before its arena range is reused
+        if (!v->simulate && hipStreamSynchronize(v->streams[v->active[i].stream]) != hipSuccess)
+            return sfail(N2F_EDEVICE, "sync failed");
+        retire(v, i, N2F_ECANCELED);
+        return N2F_OK;
+    }
+    return sfail(N2F_EINVAL, "no queued or active request with id " + std::to_string(id));
 }
 
 n2f_status n2f_server_step(n2f_server* v, int epochs, int* n_active, int* n_queued) {
@@ -389,6 +525,13 @@ n2f_status n2f_server_step(n2f_server* v, int epochs, int* n_active, int* n_queu
         if (!v->simulate) {
             a.stream = (int)(std::min_element(v->stream_load.begin(), v->stream_load.end()) - v->stream_load.begin());
             v->stream_load[a.stream]++;
+            hipError_t e = hipStreamWaitEvent(v->streams[a.stream], q.ready, 0);
+            (void)hipEventDestroy(q.ready);
+            if (e != hipSuccess) {
+                v->active.push_back(a);
+                retire(v, v->active.size() - 1, sfail(N2F_EDEVICE, "stream ordering failed"));
+                continue;
+            }
             n2f_status s = n2f_run_create(&a.run, q.in, q.H, q.W, q.C, &v->cfg, v->arena_base + off, q.bytes,
                                           v->streams[a.stream]);
             if (s < 0 || s == N2F_WCONSTANT) {

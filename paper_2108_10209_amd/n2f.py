@@ -15,7 +15,7 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libn2f.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC, ECANCELED = 0, -1, -2, -3, -4, -5, -6
 WCONSTANT, WCAPPED = 1, 2
 FP32, BF16 = 0, 1
 DS_CHECKERBOARD, DS_QUAD = 0, 1
@@ -29,7 +29,7 @@ SYMBOLS = [
     "n2f_batch_run", "n2f_batch_result", "n2f_batch_progress", "n2f_batch_destroy", "n2f_server_create",
     "n2f_server_submit", "n2f_server_step", "n2f_server_poll", "n2f_server_memory", "n2f_server_destroy",
     "n2f_run_set_clean", "n2f_max_project", "n2f_batch_run_of", "n2f_checkpoint_bytes", "n2f_save_checkpoint",
-    "n2f_load_checkpoint",
+    "n2f_load_checkpoint", "n2f_batch_add", "n2f_batch_remove", "n2f_server_cancel",
 ]
 SERVER_SIMULATE = 1
 K_CONV_FWD, K_BACKWARD, K_ADAM = 0, 1, 2
@@ -93,13 +93,16 @@ def lib():
             "n2f_run_poll": [c_void_p, c_int, POINTER(c_int), POINTER(c_int)],
             "n2f_batch_workspace_bytes": [c_int, c_void_p, c_void_p, c_void_p, POINTER(Config), POINTER(c_size_t)],
             "n2f_batch_create": [POINTER(c_void_p), c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(Config),
-                                 c_void_p, c_size_t, c_int],
+                                 c_void_p, c_size_t, c_int, c_void_p],
+            "n2f_batch_add": [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_size_t, POINTER(c_int)],
+            "n2f_batch_remove": [c_void_p, c_int],
             "n2f_batch_run": [c_void_p, c_int, POINTER(c_int)],
             "n2f_batch_result": [c_void_p, c_int, c_void_p],
             "n2f_batch_progress": [c_void_p, c_int, POINTER(c_int), POINTER(c_int)],
             "n2f_batch_destroy": [c_void_p],
             "n2f_server_create": [POINTER(c_void_p), POINTER(Config), c_void_p, c_size_t, c_int, c_int, c_int],
-            "n2f_server_submit": [c_void_p, c_longlong, c_void_p, c_void_p, c_int, c_int, c_int, c_int],
+            "n2f_server_submit": [c_void_p, c_longlong, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p],
+            "n2f_server_cancel": [c_void_p, c_longlong],
             "n2f_server_step": [c_void_p, c_int, POINTER(c_int), POINTER(c_int)],
             "n2f_server_poll": [c_void_p, c_void_p, c_void_p, c_int, POINTER(c_int)],
             "n2f_server_memory": [c_void_p, POINTER(c_size_t), POINTER(c_size_t)],
@@ -163,12 +166,22 @@ def _stream_of(t):
     return c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
 
+def _check_image(x, name="image"):
+    """A (C, H, W) FP32 contiguous CUDA tensor, checked on the host before
+    any pointer reaches the library (a host pointer read by a kernel faults
+    the device)."""
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.dim() == 3
+            and x.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of shape (C, H, W)")
+
+
 class Run:
     """One image's run: create, step, validate, read results and state."""
 
     def __init__(self, x, cfg: Config | None = None, ws=None):
         import torch
-        assert x.is_cuda and x.dtype == torch.float32 and x.dim() == 3 and x.is_contiguous()
+        _check_image(x)
         self.cfg = cfg or default_config()
         self.C, self.H, self.W = (int(s) for s in x.shape)
         self.device = x.device
@@ -305,10 +318,13 @@ class Run:
 def denoise(x, cfg: Config | None = None, ws=None):
     """One-shot denoise of a (C, H, W) FP32 CUDA tensor; returns (y, status)."""
     import torch
+    _check_image(x)
     cfg = cfg or default_config()
     C, H, W = (int(s) for s in x.shape)
     nbytes = workspace_bytes(H, W, C, cfg)
     ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    if not (ws.is_cuda and ws.device == x.device and ws.numel() * ws.element_size() >= nbytes):
+        raise ValueError("workspace must be a CUDA tensor on the image's device of at least workspace_bytes()")
     out = torch.empty_like(x)
     st = _check(lib().n2f_denoise(c_void_p(x.data_ptr()), c_void_p(out.data_ptr()), H, W, C, byref(cfg),
                                   c_void_p(ws.data_ptr()), nbytes, _stream_of(x)))
@@ -349,13 +365,18 @@ def _ints(v):
 
 
 class Batch:
-    """Independent images of uneven sizes trained together (see n2f.h)."""
+    """Independent images of uneven sizes trained together (see n2f.h).
+
+    n_streams = 0 runs every image on the caller's current stream."""
 
     def __init__(self, images, cfg: Config | None = None, n_streams: int = 4):
         import torch
         self.cfg = cfg or default_config()
         self.images = [x.contiguous() for x in images]
+        for x in self.images:
+            _check_image(x)
         self.shapes = [tuple(int(d) for d in x.shape) for x in self.images]
+        self.extra_ws = {}   # workspaces of images joined by add(), kept until removed
         n = len(self.images)
         C = _ints([s[0] for s in self.shapes])
         H = _ints([s[1] for s in self.shapes])
@@ -364,12 +385,35 @@ class Batch:
         _check(lib().n2f_batch_workspace_bytes(n, H.ctypes.data, W.ctypes.data, C.ctypes.data, byref(self.cfg),
                                                byref(nb)))
         dev = self.images[0].device
+        if any(x.device != dev for x in self.images):
+            raise ValueError("all images of a batch must be on one device")
         self.ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
         ptrs = (c_void_p * n)(*[x.data_ptr() for x in self.images])
         self._ptr = c_void_p()
-        torch.cuda.synchronize(dev)
         _check(lib().n2f_batch_create(byref(self._ptr), n, ptrs, H.ctypes.data, W.ctypes.data, C.ctypes.data,
-                                      byref(self.cfg), c_void_p(self.ws.data_ptr()), nb.value, n_streams))
+                                      byref(self.cfg), c_void_p(self.ws.data_ptr()), nb.value, n_streams,
+                                      _stream_of(self.images[0])))
+
+    def add(self, x) -> int:
+        """Join image x (C, H, W) at the next epoch boundary; returns its index."""
+        import torch
+        x = x.contiguous()
+        _check_image(x)
+        C, H, W = (int(d) for d in x.shape)
+        nbytes = workspace_bytes(H, W, C, self.cfg)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        idx = c_int()
+        _check(lib().n2f_batch_add(self._ptr, c_void_p(x.data_ptr()), H, W, C, c_void_p(ws.data_ptr()), nbytes,
+                                   byref(idx)))
+        self.images.append(x)
+        self.shapes.append((C, H, W))
+        self.extra_ws[idx.value] = ws
+        return idx.value
+
+    def remove(self, i: int):
+        """Image i leaves the batch; its workspace is released."""
+        _check(lib().n2f_batch_remove(self._ptr, i))
+        self.extra_ws.pop(i, None)
 
     def run(self, max_epochs: int = 100000):
         a = c_int()
@@ -412,6 +456,7 @@ class Server:
                  simulate: bool = False, device="cuda:0"):
         self.cfg = cfg or default_config()
         self.arena = None
+        self._keep = {}   # request id -> (x, out), alive until reported finished
         ptr = None
         if not simulate:
             import torch
@@ -422,11 +467,28 @@ class Server:
                                        SERVER_SIMULATE if simulate else 0))
 
     def submit(self, rid: int, x=None, out=None, H: int = 0, W: int = 0, C: int = 1, sim_epochs: int = 0):
-        if x is not None:
+        """Queue request rid.  A real server takes x and out, (C, H, W) FP32
+        contiguous CUDA tensors of one shape; both are kept referenced here
+        until poll() reports rid, and x is read only after the work already
+        queued on the current stream."""
+        stream = None
+        if x is not None or out is not None:
+            _check_image(x, "x")
+            _check_image(out, "out")
+            if tuple(x.shape) != tuple(out.shape) or x.device != out.device:
+                raise ValueError("x and out must have the same shape and device")
             C, H, W = (int(d) for d in x.shape)
-        return _check(lib().n2f_server_submit(self._ptr, rid, None if x is None else c_void_p(x.data_ptr()),
-                                              None if out is None else c_void_p(out.data_ptr()), H, W, C,
-                                              sim_epochs))
+            stream = _stream_of(x)
+        st = _check(lib().n2f_server_submit(self._ptr, rid, None if x is None else c_void_p(x.data_ptr()),
+                                            None if out is None else c_void_p(out.data_ptr()), H, W, C, sim_epochs,
+                                            stream))
+        if x is not None:
+            self._keep[rid] = (x, out)
+        return st
+
+    def cancel(self, rid: int):
+        """Cancel a queued or active request; poll() reports it as ECANCELED."""
+        _check(lib().n2f_server_cancel(self._ptr, rid))
 
     def step(self, epochs: int = 1):
         a, q = c_int(), c_int()
@@ -438,7 +500,10 @@ class Server:
         st = np.empty(max_n, np.int32)
         n = c_int()
         _check(lib().n2f_server_poll(self._ptr, ids.ctypes.data, st.ctypes.data, max_n, byref(n)))
-        return list(zip(ids[:n.value].tolist(), st[:n.value].tolist()))
+        done = list(zip(ids[:n.value].tolist(), st[:n.value].tolist()))
+        for rid, _ in done:
+            self._keep.pop(rid, None)
+        return done
 
     def memory(self):
         u, l = c_size_t(), c_size_t()
@@ -449,6 +514,7 @@ class Server:
         if self._ptr:
             lib().n2f_server_destroy(self._ptr)
             self._ptr = c_void_p()
+        self._keep.clear()
 
     def __del__(self):
         try:

@@ -125,15 +125,25 @@ static int server_checks() {
     std::set<long long> seen;
     std::vector<long long> ids(64);
     std::vector<int> st(64);
+    std::set<long long> cancelled;
     for (int step = 0; step < 200000 && (int)seen.size() < n; ++step) {
         for (int k = 0; k < 3 && submitted < n; ++k, ++submitted) {
-            const n2f_status r =
-                n2f_server_submit(s, submitted, nullptr, nullptr, side(rng), side(rng), ch(rng), epochs(rng));
+            const n2f_status r = n2f_server_submit(s, submitted, nullptr, nullptr, side(rng), side(rng), ch(rng),
+                                                   epochs(rng), nullptr);
             if (r == N2F_ENOMEM) {   // could never fit: counted as done
                 seen.insert(submitted);
                 continue;
             }
             CHECK(r == N2F_OK);
+            CHECK(n2f_server_submit(s, submitted, nullptr, nullptr, 8, 8, 1, 1, nullptr) == N2F_EINVAL);  // id in use
+        }
+        // every 37th request is cancelled a little after its submission
+        // (queued or already active)
+        if (submitted > 5 && (submitted - 5) % 37 == 0 && !seen.count(submitted - 5) &&
+            !cancelled.count(submitted - 5)) {
+            const n2f_status r = n2f_server_cancel(s, submitted - 5);
+            CHECK(r == N2F_OK || r == N2F_EINVAL);   // EINVAL: it had already finished
+            if (r == N2F_OK) cancelled.insert(submitted - 5);
         }
         int active = 0, queued = 0, got = 0;
         CHECK(n2f_server_step(s, 1, &active, &queued) == N2F_OK);
@@ -143,11 +153,13 @@ static int server_checks() {
         CHECK(used <= arena && largest <= arena - used);
         CHECK(n2f_server_poll(s, ids.data(), st.data(), 64, &got) == N2F_OK);
         for (int i = 0; i < got; ++i) {
-            CHECK(st[i] == N2F_OK);
+            CHECK(st[i] == (cancelled.count(ids[i]) ? N2F_ECANCELED : N2F_OK));
             CHECK(seen.insert(ids[i]).second);   // reported once
         }
     }
     CHECK((int)seen.size() == n);
+    CHECK(!cancelled.empty());
+    CHECK(n2f_server_cancel(s, 0) == N2F_EINVAL);   // long finished
     size_t used = 1, largest = 0;
     CHECK(n2f_server_memory(s, &used, &largest) == N2F_OK && used == 0 && largest == arena);
     CHECK(n2f_server_destroy(s) == N2F_OK);
@@ -187,7 +199,10 @@ static int argument_checks() {
     CHECK(n2f_denoise(nullptr, nullptr, 8, 8, 1, &d, nullptr, 0, nullptr) == N2F_EINVAL);
     CHECK(n2f_max_project(nullptr, 1, 1, nullptr, nullptr) == N2F_EINVAL);
     n2f_batch* b = nullptr;
-    CHECK(n2f_batch_create(&b, 0, nullptr, nullptr, nullptr, nullptr, &d, nullptr, 0, 1) == N2F_EINVAL);
+    CHECK(n2f_batch_create(&b, 0, nullptr, nullptr, nullptr, nullptr, &d, nullptr, 0, 1, nullptr) == N2F_EINVAL);
+    CHECK(n2f_batch_add(nullptr, nullptr, 8, 8, 1, nullptr, 0, nullptr) == N2F_EINVAL);
+    CHECK(n2f_batch_remove(nullptr, 0) == N2F_EINVAL);
+    CHECK(n2f_server_cancel(nullptr, 0) == N2F_EINVAL);
     CHECK(n2f_batch_run(nullptr, 1, nullptr) == N2F_EINVAL);
     CHECK(n2f_batch_result(nullptr, 0, nullptr) == N2F_EINVAL);
     CHECK(n2f_batch_progress(nullptr, 0, nullptr, nullptr) == N2F_EINVAL);

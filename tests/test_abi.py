@@ -110,7 +110,7 @@ def test_exact_targets_refused_where_no_clean_image_fits():
     one = (ctypes.c_int * 1)(8)
     ptrs = (ctypes.c_void_p * 1)(None)
     assert L.n2f_batch_create(ctypes.byref(b), 1, ptrs, one, one, (ctypes.c_int * 1)(1), ctypes.byref(cfg),
-                              ctypes.c_void_p(256), 1 << 20, 1) == n2f.EINVAL
+                              ctypes.c_void_p(256), 1 << 20, 1, None) == n2f.EINVAL
     assert L.n2f_run_set_clean(None, None) == n2f.EINVAL
 
 

@@ -99,3 +99,53 @@ def test_serving_trace_generator():
     assert abs(np.mean([r.C == 3 for r in reqs]) - 0.3) < 0.08
     arr = np.array([r.arrival for r in reqs])
     assert np.all(np.diff(arr) > 0) and abs(arr[-1] / 400 - 0.5) < 0.1
+
+
+def test_cancel_queued_and_active_requests():
+    """Cancelling (the serving failure path): a queued request leaves the
+    queue, an active one leaves at once and frees its arena range; both are
+    reported once with ECANCELED, the others finish normally, and an id that
+    is no longer queued or active is refused."""
+    unit = n2f.workspace_bytes(128, 128, 1)
+    arena = 2 * unit
+    srv = n2f.Server(arena, simulate=True, max_active=2)
+    for i in range(4):
+        srv.submit(i, H=128, W=128, C=1, sim_epochs=5)
+    srv.step(1)                       # 0 and 1 active, 2 and 3 queued
+    assert srv.memory()[0] == 2 * unit
+    srv.cancel(1)                     # active
+    srv.cancel(3)                     # queued
+    assert dict(srv.poll()) == {1: n2f.ECANCELED, 3: n2f.ECANCELED}
+    assert srv.memory()[0] == unit    # 1's range is free again
+    with pytest.raises(n2f.N2FError):
+        srv.cancel(3)
+    with pytest.raises(n2f.N2FError):
+        srv.submit(0, H=8, W=8, C=1, sim_epochs=1)   # id 0 is active
+    done = {}
+    for _ in range(20):
+        srv.step(1)
+        done.update(srv.poll())
+    assert done == {0: n2f.OK, 2: n2f.OK}
+    assert srv.memory() == (0, arena)
+
+
+def test_cpu_tensors_refused_on_the_host():
+    """Host tensors never reach the library: every binding entry point that
+    takes images refuses them (and non-contiguous or non-FP32 ones) before
+    any call into it."""
+    import torch
+    x = torch.zeros((1, 16, 16), dtype=torch.float32)
+    with pytest.raises(ValueError):
+        n2f.denoise(x)
+    with pytest.raises(ValueError):
+        n2f.Run(x)
+    with pytest.raises(ValueError):
+        n2f.Batch([x])
+    srv = n2f.Server(1 << 30, simulate=True)
+    with pytest.raises(ValueError):
+        srv.submit(0, x, x.clone())
+    with pytest.raises(ValueError):
+        srv.submit(1, x.to(torch.float64), x.clone())
+    with pytest.raises(ValueError):
+        srv.submit(2, x.transpose(1, 2), x.clone())
+    assert srv.step(1) == (0, 0)      # nothing was queued
