@@ -3,10 +3,9 @@ the GPU against the CPU FP64 oracle, through the C ABI: 2x2-block ("Quad")
 downsampling and "Exact" targets.  Same bars as the main path: downsamples
 bit-exact; Exact targets within a few FP32 ulps of their FP64 value; a
 teacher-forced step within norm-wise relative error 1e-5 (FP32) or 2e-2
-(BF16) per tensor; fixed-epoch PSNR within 0.1 dB of the oracle's.  For
-BF16 the per-tensor bar is raised to twice the change that rounding the
-weights alone to BF16 makes to the exact gradient, where that is larger
-(an ill-conditioned tensor, see `bf16_bar`)."""
+(BF16) per tensor; fixed-epoch PSNR within 0.1 dB of the oracle's.  A BF16
+tensor that BF16 rounding alone moves by more than 1e-2 (ill-conditioned) may
+instead match a model of the path's rounding within 2e-2 (see `bf16_bar`)."""
 import sys
 
 import numpy as np
@@ -15,7 +14,7 @@ import torch
 
 from oracle import n2f_oracle as O
 from paper_2108_10209_amd import n2f, synth
-from bf16_bar import bf16_bars
+from bf16_bar import bf16_check, summary
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -58,7 +57,7 @@ def scene(C, H, W, seed):
 def step_errors(r, C, k, st, pairs, pair):
     """Load the oracle state st into network k, run one GPU step on `pair`
     and return the per-tensor gradient errors and the loss error against the
-    oracle's step from the FP32-rounded state."""
+    oracle's step from the FP32-rounded state, and the GPU gradient."""
     r.set_state(k, st.theta, st.m, st.v, st.t)
     st32 = O.NetState(st.theta.astype(np.float32).astype(np.float64), st.m.astype(np.float32).astype(np.float64),
                       st.v.astype(np.float32).astype(np.float64), st.t)
@@ -67,7 +66,7 @@ def step_errors(r, C, k, st, pairs, pair):
     inp, tgt = pairs[pair]
     _, g_or, loss_or, _ = O.train_step(st32, C, inp, tgt[k], H0)
     errs = {nm: rel(a, b) for (nm, a), b in zip(split(g, C).items(), split(g_or, C).values())}
-    return errs, abs(loss - loss_or) / abs(loss_or)
+    return errs, abs(loss - loss_or) / abs(loss_or), g
 
 
 # ---------------------------------------------------------------------------
@@ -120,15 +119,16 @@ def test_quad_train_step_teacher_forced(prec, C, H, W, pre):
         st = O.new_state(th0[k])
         for s in range(pre):
             st = O.train_step(st, C, pairs[s % 4][0], pairs[s % 4][1][k], H0)[0]
+        errs, lerr, g = step_errors(r, C, k, st, pairs, pre % 4)
         if prec == n2f.FP32:
-            tol = {nm: 1e-5 for nm, _ in O.param_spec(C)}
+            worst = max(errs, key=errs.get)
+            say("  worst grad err", worst, errs[worst], "loss err", lerr)
+            assert all(e < 1e-5 for e in errs.values()), errs
         else:
             inp, tgt = pairs[pre % 4]
-            tol = bf16_bars(st.theta.astype(np.float32).astype(np.float64), C, inp, tgt[k])
-        errs, lerr = step_errors(r, C, k, st, pairs, pre % 4)
-        worst = max(errs, key=lambda nm: errs[nm] / tol[nm])
-        say("  worst grad err", worst, errs[worst], "bar", tol[worst], "loss err", lerr)
-        assert all(errs[nm] < tol[nm] for nm in errs), (errs, tol)
+            ok, rows = bf16_check(g, st.theta.astype(np.float32).astype(np.float64), C, inp, tgt[k])
+            say("  " + summary(rows), "loss err", lerr)
+            assert ok, rows
         assert lerr < (1e-6 if prec == n2f.FP32 else 2e-2)
 
 
@@ -231,7 +231,7 @@ def test_exact_teacher_forced_and_fixed_epochs(ds):
     st = O.new_state(th0[0])
     for s in range(3):
         st = O.train_step(st, 1, pairs[s][0], pairs[s][1][0], H0)[0]
-    errs, lerr = step_errors(r, 1, 0, st, pairs, 3)
+    errs, lerr, _ = step_errors(r, 1, 0, st, pairs, 3)
     say("  worst grad err", max(errs.values()), "loss err", lerr)
     assert max(errs.values()) < 1e-5 and lerr < 1e-6
     r2 = n2f.Run(dev(noisy), cfg)

@@ -95,27 +95,31 @@ def test_bf16_deterministic_and_one_shot():
     assert sa == sb == n2f.OK and torch.equal(a, b)
 
 
+@pytest.mark.timeout(900)
 def test_bf16_mean_psnr_matches_fp32():
-    """Mean final PSNR over 12 initial-weight seeds (256x256 blobs scene,
-    sigma 25/255, full early-stopping runs): BF16 within 0.1 dB of FP32, up
-    to the sampling error of the two means.  A single run's PSNR moves by a
-    few tenths of a dB with the initial weights and with rounding noise (the
-    stopping epoch shifts), for either precision, so single runs are not
-    compared."""
+    """Mean final PSNR over 100 initial-weight seeds (256x256 blobs scene,
+    sigma 25/255, full early-stopping runs): BF16 within 0.1 dB of FP32 on
+    the point estimate; the standard error of the difference (about 0.05 dB
+    at the measured per-run spread) is printed beside it.  A single run's
+    PSNR moves by a few tenths of a dB with the initial weights and with
+    rounding noise (the stopping epoch shifts), for either precision, so
+    single runs are not compared."""
+    n = 100
     clean, noisy = synth.single_512(25, 2, size=256)
     x = dev(noisy)
-    res = {}
+    res, eps = {}, {}
     for name, prec in [("fp32", n2f.FP32), ("bf16", n2f.BF16)]:
-        ps = []
-        for seed in range(12):
+        ps, ep = [], []
+        for seed in range(n):
             r = n2f.Run(x, n2f.default_config(precision=prec, init_seed=seed))
             done, status = r.run_epochs(0, 2000)
             assert done and status == n2f.OK
             ps.append(synth.psnr(r.result().cpu().numpy(), clean))
-        res[name] = np.array(ps)
-        say(name, "mean %.3f std %.3f" % (res[name].mean(), res[name].std(ddof=1)))
+            ep.append(r.progress(0)[0])
+        res[name], eps[name] = np.array(ps), np.array(ep)
+        say(name, "mean %.3f std %.3f, epochs %.1f" % (res[name].mean(), res[name].std(ddof=1), eps[name].mean()))
     diff = res["bf16"].mean() - res["fp32"].mean()
-    se = np.sqrt(res["bf16"].var(ddof=1) / 12 + res["fp32"].var(ddof=1) / 12)
-    say("bf16 - fp32 %.3f dB, standard error %.3f" % (diff, se))
-    assert abs(diff) <= 0.1 + 2.5 * se
+    se = np.sqrt(res["bf16"].var(ddof=1) / n + res["fp32"].var(ddof=1) / n)
+    say("bf16 - fp32 %+.3f dB over %d seeds, standard error %.3f" % (diff, n, se))
+    assert abs(diff) <= 0.1
     assert res["bf16"].min() > synth.psnr(noisy, clean) + 10.0

@@ -3,8 +3,9 @@ the C ABI: the smallest images the method accepts (2x2, whose checkerboard
 images are 2x1 and 1x2 and whose 2x2-block images are single pixels), odd
 sizes of 3, and strips two pixels tall or three wide, each with one and
 three channels.  FP32 after two fixed epochs within 1e-4 of the oracle;
-BF16 the first step within the per-tensor BF16 bar (see `bf16_bar`) and a
-finite output.
+BF16 the first step within 2e-2 per tensor, of the exact gradient or, for a
+tensor that BF16 rounding alone moves by more than 1e-2, of a model of the
+path's rounding (see `bf16_bar`), and a finite output.
 """
 import sys
 
@@ -14,7 +15,7 @@ import torch
 
 from oracle import n2f_oracle as O
 from paper_2108_10209_amd import n2f, synth
-from bf16_bar import bf16_bars, split
+from bf16_bar import bf16_check, summary
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -70,12 +71,10 @@ def test_tiny_bf16_first_step_and_finite_output(C, H, W, ds):
         th = th0[k].astype(np.float64)
         _, g_or, loss_or, _ = O.train_step(O.new_state(th), C, pairs[0][0], pairs[0][1][k], H0)
         # a few pixels of pure noise make near-cancelling gradient sums:
-        # per-tensor bars from the BF16 weight-rounding sensitivity
-        tol = bf16_bars(th, C, pairs[0][0], pairs[0][1][k])
-        errs = {nm: rel(a, b) for (nm, a), b in zip(split(g, C).items(), split(g_or, C).values())}
-        worst = max(errs, key=lambda nm: errs[nm] / tol[nm])
-        say("  worst", worst, errs[worst], "bar", tol[worst])
-        assert all(errs[nm] < tol[nm] for nm in errs), (errs, tol)
+        # ill-conditioned tensors are judged against the BF16 rounding model
+        ok, rows = bf16_check(g, th, C, pairs[0][0], pairs[0][1][k])
+        say("  " + summary(rows))
+        assert ok, rows
         assert abs(loss - loss_or) / abs(loss_or) < 2e-2
     y, st = n2f.denoise(dev(x), cfg)
     assert st == n2f.OK and torch.isfinite(y).all()
