@@ -200,3 +200,39 @@ def test_served_results_match_the_oracle():
         err = float(np.linalg.norm(y - ref.y) / np.linalg.norm(ref.y))
         say("served", i, (C, H, W), "rel err vs oracle", err)
         assert err < 1e-4, (i, err)
+
+
+@pytest.mark.parametrize("n_streams,max_active", [(2, 2), (1, 4)])
+def test_served_results_match_oracle(n_streams, max_active):
+    """FP32 requests served in a mix (grayscale and RGB, uneven sizes, a few
+    admitted at a time so later ones join as earlier ones leave) against the
+    CPU FP64 oracle run on each request alone from the same initial weights,
+    three fixed epochs: every output channel within 1e-4 norm-wise.  (With
+    the stopping rule on, the stopping epoch of a tiny image can move with
+    rounding; the stopping rule is checked step by step elsewhere.)"""
+    from oracle import n2f_oracle as O
+    kw = dict(fixed_epochs=3)
+    shapes = [(1, 40, 48), (3, 24, 20), (1, 33, 50), (1, 64, 30)]
+    imgs = _images(shapes, seed=40)
+    cfg = n2f.default_config(**kw)
+    arena = max_active * max(n2f.workspace_bytes(H, W, C, cfg) for C, H, W in shapes)
+    srv = n2f.Server(arena, cfg, n_streams=n_streams, max_active=max_active)
+    xs = [dev(x) for x in imgs]
+    outs = [torch.empty_like(x) for x in xs]
+    for i in range(len(xs)):
+        srv.submit(i, xs[i], outs[i])
+    done, steps = {}, 0
+    while len(done) < len(xs):
+        srv.step(1)
+        done.update(dict(srv.poll()))
+        steps += 1
+        assert steps < 1000
+    hyp = O.Hyper(fixed_epochs=3)
+    for i, (x, (C, H, W)) in enumerate(zip(imgs, shapes)):
+        assert done[i] == n2f.OK, (i, done[i])
+        ref = O.denoise(x, synth.init_params(C, 0), hyp)
+        y = outs[i].cpu().numpy()
+        for k in range(C):
+            err = float(np.linalg.norm(y[k] - ref.y[k]) / np.linalg.norm(ref.y[k]))
+            say(f"  request {i} ({C}x{H}x{W}) channel {k}: rel err {err:.2e}, epochs {ref.epochs[k]}")
+            assert err < 1e-4, (i, k, err)
