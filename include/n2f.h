@@ -265,7 +265,8 @@ n2f_status n2f_run_poll(n2f_run* run, int net, int* done, int* epochs);
  * epoch boundaries while the others keep their state. */
 typedef struct n2f_batch n2f_batch;
 
-/* Workspace for a batch: the 256-byte aligned sum of the images' needs. */
+/* Workspace for a batch: the 256-byte aligned sum of the images' needs,
+ * plus the launch tables of grouped mode (a few MB). */
 n2f_status n2f_batch_workspace_bytes(int n, const int* H, const int* W, const int* C, const n2f_config* cfg,
                                      size_t* bytes);
 
@@ -273,12 +274,20 @@ n2f_status n2f_batch_workspace_bytes(int n, const int* H, const int* W, const in
  * call, after the work already queued on the caller's `stream` (the batch's
  * streams wait for it, so inputs produced there are complete).  d_ws: 256-byte
  * aligned device workspace of n2f_batch_workspace_bytes(), image i's slice
- * at the aligned prefix sum of the sizes before it; kept until destroy.
+ * at the aligned prefix sum of the sizes before it, then the launch tables
+ * of grouped mode; kept until destroy.
  * n_streams >= 1: the batch creates that many streams (default priority),
- * at most one per image; n_streams = 0: everything runs on `stream` itself,
- * one image after another.  Synchronises.  Constant images are finished at
+ * at most one per image, and each image replays its own epoch graph;
+ * n_streams = 0: everything runs on `stream` itself, one image after
+ * another; n_streams = N2F_BATCH_GROUPED (BF16 only): every launch of an
+ * epoch is one grouped launch over all images of the same channel count,
+ * whose blocks run each image's blocks exactly as its own launch would (the
+ * same bits as the image alone), and one recorded graph per epoch replays
+ * on `stream`; at most n + 64 images train at once (n2f_batch_add beyond
+ * that returns N2F_ENOMEM).  Synchronises.  Constant images are finished at
  * once.  cfg->exact_targets is refused (N2F_EINVAL), here and by the
  * server. */
+#define N2F_BATCH_GROUPED (-1)
 n2f_status n2f_batch_create(n2f_batch** batch, int n, const float* const* d_in, const int* H, const int* W,
                             const int* C, const n2f_config* cfg, void* d_ws, size_t ws_bytes, int n_streams,
                             hipStream_t stream);
@@ -388,6 +397,15 @@ n2f_status n2f_server_destroy(n2f_server* srv);
 #define N2F_K_CONV_FWD 0
 #define N2F_K_BACKWARD 1
 #define N2F_K_ADAM     2
+/* Grouped launches (a batch created with N2F_BATCH_GROUPED, or a server with
+ * N2F_SERVER_GROUPED): each launch covers every image of the group and is
+ * bracketed on its own; class N2F_K_GROUP + kind, pixels summed over the
+ * images.  Kinds: 0 64->64 forward, 1 data gradient, 2 last layer with the
+ * training head, 3 last layer with the validation head, 4 first layer fused
+ * into layer 2, 5 64->64 weight gradient, 6-8 first layer (C = 1, 2, 3),
+ * 9-11 first-layer weight gradient (C = 1, 2, 3), 12 Adam, 13 stopping rule,
+ * 14 running output sum. */
+#define N2F_K_GROUP   16
 n2f_status n2f_profile_begin(int every);
 n2f_status n2f_profile_read(int kernel_class, double* total_ms, long long* launches, long long* pixels);
 n2f_status n2f_profile_end(void);

@@ -1165,7 +1165,8 @@ n2f_status n2f_profile_begin(int every) {
 }
 
 n2f_status n2f_profile_read(int cls, double* total_ms, long long* launches, long long* pixels) {
-    if (cls < N2F_K_CONV_FWD || cls > N2F_K_ADAM) return fail(N2F_EINVAL, "unknown kernel class");
+    if (!(cls >= N2F_K_CONV_FWD && cls <= N2F_K_ADAM) && !(cls >= N2F_K_GROUP && cls < N2F_K_GROUP + KK_COUNT))
+        return fail(N2F_EINVAL, "unknown kernel class");
     double ms = 0.0;
     long long n = 0, px = 0;
     for (const ProfRec& rec : g_prof.recs) {
@@ -1189,3 +1190,211 @@ n2f_status n2f_profile_end(void) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Launch recording and grouped epochs
+// ---------------------------------------------------------------------------
+namespace n2f {
+
+Recorder*& launch_recorder() {
+    thread_local Recorder* r = nullptr;
+    return r;
+}
+
+hipError_t record_launch(int kind, const void* args, size_t bytes, int grid, long long npix) {
+    Recorder* r = launch_recorder();
+    if (!r || bytes > (size_t)kArgStride || kind < 0 || kind >= KK_COUNT || grid < 1) return hipErrorInvalidValue;
+    r->recs.emplace_back();
+    LaunchRec& rec = r->recs.back();
+    rec.kind = kind;
+    rec.grid = grid;
+    rec.npix = npix;
+    std::memset(rec.args, 0, sizeof(rec.args));
+    std::memcpy(rec.args, args, bytes);
+    return hipSuccess;
+}
+
+n2f_status record_epoch(n2f_run* r, int net, std::vector<LaunchRec>* out) {
+    n2f_status s = check_run(r, net);
+    if (s != N2F_OK) return s;
+    if (!r->pl.bf) return fail(N2F_EINVAL, "grouped launches need BF16 runs");
+    s = check_targets(r);
+    if (s != N2F_OK) return s;
+    Recorder rec;
+    launch_recorder() = &rec;
+    const bool cap = g_prof.capturing;
+    g_prof.capturing = true;   // no event brackets while recording
+    s = enqueue_epoch(r, net);
+    g_prof.capturing = cap;
+    launch_recorder() = nullptr;
+    if (s != N2F_OK) return s;
+    *out = std::move(rec.recs);
+    return N2F_OK;
+}
+
+hipStream_t run_stream(n2f_run* r) { return r->stream; }
+
+bool profiling_on() { return g_prof.on; }
+
+namespace {
+// Blocks per grouped launch: the 3x3 kernels hold most of a CU's shared
+// memory (one block per CU); the others are short memory-bound blocks.
+int g_group_grid[KK_COUNT] = {256, 256, 256, 256, 256, 256, 1024, 1024, 1024, 512, 512, 512, 1024, 256, 1024};
+}  // namespace
+
+int group_grid(int kind) { return (kind >= 0 && kind < KK_COUNT) ? g_group_grid[kind] : 1; }
+void set_group_grid(int kind, int grid) {
+    if (kind >= 0 && kind < KK_COUNT && grid >= 1) g_group_grid[kind] = grid;
+}
+
+size_t Group::table_bytes(int cap) {
+    const size_t pre = align_up(sizeof(int) * (size_t)(cap + 2));
+    return (size_t)kMaxPos * (pre + (size_t)cap * kArgStride);
+}
+
+size_t Group::pos_bytes() const { return align_up(sizeof(int) * (size_t)(cap_ + 2)) + (size_t)cap_ * kArgStride; }
+
+Group::~Group() {
+    if (exec_) (void)hipGraphExecDestroy(exec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
+}
+
+n2f_status Group::add(n2f_run* r, int net, int tag) {
+    if ((int)slots_.size() >= cap_) return fail(N2F_ENOMEM, "group is full (" + std::to_string(cap_) + " runs)");
+    if (run_stream(r) != stream_) return fail(N2F_EINVAL, "a grouped run must be created on the group's stream");
+    Slot sl{tag, r, net, {}};
+    n2f_status s = record_epoch(r, net, &sl.recs);
+    if (s != N2F_OK) return s;
+    if (sl.recs.size() > (size_t)kMaxPos) return fail(N2F_EINVAL, "epoch has too many launches for a group");
+    std::vector<int> kinds;
+    for (const LaunchRec& rec : sl.recs) kinds.push_back(rec.kind);
+    if (kinds_.empty()) {
+        kinds_ = kinds;
+    } else if (kinds != kinds_) {
+        return fail(N2F_EINVAL, "the runs of a group must have the same launch sequence (channel count)");
+    }
+    slots_.push_back(std::move(sl));
+    dirty_ = true;
+    return N2F_OK;
+}
+
+n2f_status Group::set_net(int tag, int net) {
+    for (Slot& sl : slots_) {
+        if (sl.tag != tag) continue;
+        std::vector<LaunchRec> recs;
+        n2f_status s = record_epoch(sl.run, net, &recs);
+        if (s != N2F_OK) return s;
+        if (recs.size() != kinds_.size()) return fail(N2F_EINVAL, "launch sequence changed");
+        sl.net = net;
+        sl.recs = std::move(recs);
+        dirty_ = true;
+        return N2F_OK;
+    }
+    return fail(N2F_EINVAL, "no run with that tag in the group");
+}
+
+void Group::remove(int tag) {
+    for (size_t i = 0; i < slots_.size(); ++i) {
+        if (slots_[i].tag != tag) continue;
+        slots_.erase(slots_.begin() + i);
+        dirty_ = true;
+        return;
+    }
+}
+
+// Lay the runs' records out as per-launch tables and copy them to the device
+// (on the stream, after the epochs already queued).  The host copy is only
+// rewritten once the previous upload has completed.
+n2f_status Group::upload() {
+    N2F_HIP(hipStreamSynchronize(stream_));
+    const int n = (int)slots_.size();
+    const size_t pb = pos_bytes(), pre = align_up(sizeof(int) * (size_t)(cap_ + 2));
+    const size_t npos = kinds_.size();
+    host_.assign(npos * pb, 0);
+    npix_.assign(npos, 0);
+    for (size_t j = 0; j < npos; ++j) {
+        unsigned char* base = host_.data() + j * pb;
+        int* pf = reinterpret_cast<int*>(base);
+        pf[0] = n;
+        pf[1] = 0;
+        for (int i = 0; i < n; ++i) {
+            const LaunchRec& rec = slots_[i].recs[j];
+            pf[2 + i] = pf[1 + i] + rec.grid;
+            std::memcpy(base + pre + (size_t)i * kArgStride, rec.args, kArgStride);
+            npix_[j] += rec.npix;
+        }
+    }
+    if (!host_.empty()) N2F_HIP(hipMemcpyAsync(d_tab_, host_.data(), host_.size(), hipMemcpyHostToDevice, stream_));
+    dirty_ = false;
+    return N2F_OK;
+}
+
+n2f_status Group::enqueue_all(hipStream_t s, bool with_timing) {
+    const size_t pb = pos_bytes(), pre = align_up(sizeof(int) * (size_t)(cap_ + 2));
+    for (size_t j = 0; j < kinds_.size(); ++j) {
+        const int kind = kinds_[j];
+        char* base = d_tab_ + j * pb;
+        const GroupView v{reinterpret_cast<const unsigned char*>(base + pre), reinterpret_cast<const int*>(base)};
+        const int grid = group_grid(kind);
+        if (with_timing) {
+            N2F_HIP(timed(N2F_K_GROUP + kind, 1, npix_[j], s, [&] { return launch_group(kind, v, grid, s); }));
+        } else {
+            N2F_HIP(launch_group(kind, v, grid, s));
+        }
+    }
+    return N2F_OK;
+}
+
+n2f_status Group::launch(int epochs) {
+    if (slots_.empty() || epochs < 1) return N2F_OK;
+    if (dirty_) {
+        n2f_status s = upload();
+        if (s != N2F_OK) return s;
+    }
+    bool stale = exec_ == nullptr;
+    for (int k = 0; k < KK_COUNT; ++k) stale = stale || exec_grid_[k] != group_grid(k);
+    if (stale) {
+        // record one epoch of grouped launches on a private stream; the
+        // tables it points at are rewritten in place, never moved
+        if (exec_) (void)hipGraphExecDestroy(exec_);
+        if (graph_) (void)hipGraphDestroy(graph_);
+        exec_ = nullptr;
+        graph_ = nullptr;
+        if (!cap_stream_) N2F_HIP(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
+        const bool capf = g_prof.capturing;
+        g_prof.capturing = true;
+        hipError_t e = hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeRelaxed);
+        n2f_status s = N2F_OK;
+        if (e == hipSuccess) s = enqueue_all(cap_stream_, false);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = (e == hipSuccess) ? hipStreamEndCapture(cap_stream_, &g) : e;
+        g_prof.capturing = capf;
+        if (e != hipSuccess || e2 != hipSuccess || s != N2F_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            if (s != N2F_OK) return s;
+            return fail(N2F_EDEVICE, std::string("group graph capture failed: ") +
+                                         hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiate(&exec_, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            exec_ = nullptr;
+            return fail(N2F_EDEVICE, std::string("group graph instantiate failed: ") + hipGetErrorString(e));
+        }
+        graph_ = g;
+        for (int k = 0; k < KK_COUNT; ++k) exec_grid_[k] = group_grid(k);
+    }
+    for (int e = 0; e < epochs; ++e) {
+        const bool direct = g_prof.on && (g_prof.epochs++ % g_prof.every) == 0;
+        if (direct) {
+            n2f_status s = enqueue_all(stream_, true);
+            if (s != N2F_OK) return s;
+        } else {
+            N2F_HIP(hipGraphLaunch(exec_, stream_));
+        }
+    }
+    return N2F_OK;
+}
+
+}  // namespace n2f

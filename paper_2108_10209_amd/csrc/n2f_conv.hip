@@ -369,11 +369,12 @@ __device__ __forceinline__ void first_layer_halo(uint16_t* halo, const float* sx
 // four lanes of the pixel add theirs by an xor butterfly, and the head
 // gradient sums over a row's 16 pixels by another, then over the waves in
 // order through LDS.
+// One block of the convolution grid: block `bid` of `nblk`.
 template <int MODE>
-__global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
-                                                   const float* __restrict__ bias, uint16_t* __restrict__ mbits,
-                                                   uint16_t* __restrict__ out, int h, int w, int nblk,
-                                                   const DevState* st, ConvHead hd, ConvFirst cf) {
+__device__ __forceinline__ void conv_bf16_block(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
+                                                const float* __restrict__ bias, uint16_t* __restrict__ mbits,
+                                                uint16_t* __restrict__ out, int h, int w, int nblk,
+                                                const DevState* st, ConvHead hd, ConvFirst cf, const int bid) {
     constexpr bool kHead = (MODE == 2 || MODE == 3);   // head in the epilogue
     constexpr bool kFirst = (MODE == 4);               // first layer computed into the halo
     constexpr bool kFwd = (MODE == 0 || MODE == 4);    // plain forward epilogue
@@ -407,7 +408,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
     const int tiles_x = (w + kTile - 1) / kTile, tiles_y = (h + kTile - 1) / kTile;
     const int ntiles = tiles_x * tiles_y;
     const int stride = 2 * nblk;
-    const int iters = (ntiles - 2 * (int)blockIdx.x + stride - 1) / stride;
+    const int iters = (ntiles - 2 * bid + stride - 1) / stride;
 
     uint4 pf[kPf];
     auto fetch = [&](int tile) {
@@ -440,8 +441,8 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
         }
     };
     if (iters > 0) {
-        if constexpr (kFirst) fetch_x(2 * blockIdx.x + grp);
-        else fetch(2 * blockIdx.x + grp);
+        if constexpr (kFirst) fetch_x(2 * bid + grp);
+        else fetch(2 * bid + grp);
     }
     float w1v[2] = {0.f, 0.f};
     if constexpr (kFirst) {
@@ -466,7 +467,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
     for (int k = 0; k < kWChunks; ++k) reinterpret_cast<uint4*>(sw)[tid + 512 * k] = wr[k];
 
     for (int k = 0; k < iters; ++k) {
-        const int tile = 2 * blockIdx.x + grp + k * stride;
+        const int tile = 2 * bid + grp + k * stride;
         const bool have = tile < ntiles;
         const int x0 = have ? (tile % tiles_x) * kTile : 0, y0 = have ? (tile / tiles_x) * kTile : 0;
         if constexpr (kFirst) {
@@ -690,7 +691,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
             double sum = 0.0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) sum += slred[q];
-            hd.lpart[blockIdx.x] = sum;
+            hd.lpart[bid] = sum;
         }
     }
     if (MODE == 2) {
@@ -699,17 +700,47 @@ __global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ 
             float sum = 0.f;
 #pragma unroll
             for (int q = 0; q < 8; ++q) sum += shred[q][tid];
-            hd.part[(long long)blockIdx.x * kHeadN + tid] = sum;
+            hd.part[(long long)bid * kHeadN + tid] = sum;
         }
         if (tid == 0) {
             double sum = 0.0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) sum += slred[q];
-            hd.lpart[blockIdx.x] = sum;
+            hd.lpart[bid] = sum;
             // one Adam step follows this head: count it (no other block reads t)
-            if (blockIdx.x == 0) hd.st->t += 1;
+            if (bid == 0) hd.st->t += 1;
         }
     }
+}
+
+// Arguments of one launch of k_conv_bf16 (also one run's entry of a grouped
+// launch).
+struct ConvArgs {
+    const uint16_t* in;
+    const uint16_t* wpk;
+    const float* bias;
+    uint16_t* mbits;
+    uint16_t* out;
+    int h, w, nblk;
+    const DevState* st;
+    ConvHead hd;
+    ConvFirst cf;
+};
+static_assert(sizeof(ConvArgs) <= kArgStride, "argument table stride");
+inline long long npix_of(const ConvArgs& a) { return (long long)a.h * a.w; }
+
+template <int MODE>
+__global__ __launch_bounds__(512) void k_conv_bf16(ConvArgs a) {
+    conv_bf16_block<MODE>(a.in, a.wpk, a.bias, a.mbits, a.out, a.h, a.w, a.nblk, a.st, a.hd, a.cf, blockIdx.x);
+}
+
+// The same convolution over a group of runs (see GroupView).
+template <int MODE>
+__global__ __launch_bounds__(512) void k_conv_bf16_group(GroupView g) {
+    for_group_blocks(g, [&](int s, int vb, int) {
+        const ConvArgs& a = *reinterpret_cast<const ConvArgs*>(g.args + (size_t)s * kArgStride);
+        conv_bf16_block<MODE>(a.in, a.wpk, a.bias, a.mbits, a.out, a.h, a.w, a.nblk, a.st, a.hd, a.cf, vb);
+    });
 }
 
 // Grid of the BF16 convolution: one block (two tiles in flight) per CU at most.
@@ -812,8 +843,10 @@ __device__ __forceinline__ void wg_store(const uint4 (&pf)[kWgPf], uint16_t* buf
     }
 }
 
-__global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__ src, const uint16_t* __restrict__ dlt,
-                                                    float* __restrict__ part, int h, int w, const DevState* st) {
+// One block of the weight-gradient grid: block `b` of `nb` = 4 x nsplit.
+__device__ __forceinline__ void wgrad_bf16_block(const uint16_t* __restrict__ src, const uint16_t* __restrict__ dlt,
+                                                 float* __restrict__ part, int h, int w, const DevState* st,
+                                                 const int b, const int nb) {
     const int stop = st->done;   // tested once the first tiles' loads are in flight
     __shared__ __attribute__((aligned(16))) unsigned char lds[kWgLdsBytes];
     __shared__ float dbs[256][16];     // bias gradient: per-thread sums of this block's 16 channels
@@ -824,8 +857,7 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
     // wave wv: pixels 64 (wv / 2) .. + 63 of each tile (two K steps) and
     // output-channel blocks 2 (wv % 2), 2 (wv % 2) + 1
     const int pr = wv >> 1, oh = wv & 1;
-    const int nsplit = gridDim.x / 4;
-    const int b = blockIdx.x;
+    const int nsplit = nb / 4;
     int sp, q;
     if ((nsplit & 7) == 0) {
         q = (b >> 3) & 3;
@@ -963,6 +995,35 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(const uint16_t* __restrict__
     }
 }
 
+struct WgradArgs {
+    const uint16_t* src;
+    const uint16_t* dlt;
+    float* part;
+    int h, w;
+    const DevState* st;
+};
+
+__global__ __launch_bounds__(512) void k_wgrad_bf16(WgradArgs a) {
+    wgrad_bf16_block(a.src, a.dlt, a.part, a.h, a.w, a.st, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(512) void k_wgrad_bf16_group(GroupView g) {
+    for_group_blocks(g, [&](int s, int vb, int nvb) {
+        const WgradArgs& a = *reinterpret_cast<const WgradArgs*>(g.args + (size_t)s * kArgStride);
+        wgrad_bf16_block(a.src, a.dlt, a.part, a.h, a.w, a.st, vb, nvb);
+    });
+}
+
+// Launch one run's kernel directly, or record it for a grouped launch.
+template <int MODE>
+hipError_t dispatch_conv(const ConvArgs& a, int grid, hipStream_t s) {
+    constexpr int kind = MODE == 0 ? KK_CONV_FWD : MODE == 1 ? KK_CONV_DGRAD : MODE == 2 ? KK_CONV_HEAD
+                                   : MODE == 3 ? KK_CONV_VAL : KK_CONV_FIRST;
+    if (launch_recorder()) return record_launch(kind, &a, sizeof(a), grid, npix_of(a));
+    hipLaunchKernelGGL(k_conv_bf16<MODE>, dim3(grid), dim3(512), 0, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, void* out, uint16_t* mbits, int bf16,
@@ -970,10 +1031,11 @@ hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, v
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
     if (bf16) {
         const int nb = conv_bf16_blocks(h, w);
-        hipLaunchKernelGGL(k_conv_bf16<0>, dim3(nb), dim3(512), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
-                           mbits, (uint16_t*)out, h, w, nb, st, ConvHead{}, ConvFirst{});
-        return hipGetLastError();
+        return dispatch_conv<0>(ConvArgs{(const uint16_t*)in, (const uint16_t*)wpk, bias, mbits, (uint16_t*)out, h, w,
+                                         nb, st, ConvHead{}, ConvFirst{}},
+                                nb, s);
     }
+    if (launch_recorder()) return hipErrorNotSupported;   // grouped launches are BF16 only
     hipLaunchKernelGGL(k_conv_f32<0>, grid, dim3(256), 0, s, (const float*)in, (const float*)wpk, bias,
                        (const float*)nullptr, (float*)out, h, w, st);
     return hipGetLastError();
@@ -982,25 +1044,25 @@ hipError_t launch_conv_fwd(const void* in, const void* wpk, const float* bias, v
 hipError_t launch_conv_fwd_head(const void* in, const void* wpk, const float* bias, void* d8, const ConvHead& hd,
                                 int nblk, int h, int w, const DevState* st, hipStream_t s) {
     if (nblk < conv_bf16_blocks(h, w) || nblk > 256) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_conv_bf16<2>, dim3(nblk), dim3(512), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
-                       (uint16_t*)nullptr, (uint16_t*)d8, h, w, nblk, st, hd, ConvFirst{});
-    return hipGetLastError();
+    return dispatch_conv<2>(ConvArgs{(const uint16_t*)in, (const uint16_t*)wpk, bias, nullptr, (uint16_t*)d8, h, w,
+                                     nblk, st, hd, ConvFirst{}},
+                            nblk, s);
 }
 
 hipError_t launch_conv_fwd_first(const ConvFirst& cf, const void* wpk, const float* bias, void* out,
                                  uint16_t* mbits, int h, int w, const DevState* st, hipStream_t s) {
     const int nb = conv_bf16_blocks(h, w);
-    hipLaunchKernelGGL(k_conv_bf16<4>, dim3(nb), dim3(512), 0, s, (const uint16_t*)nullptr, (const uint16_t*)wpk, bias,
-                       mbits, (uint16_t*)out, h, w, nb, st, ConvHead{}, cf);
-    return hipGetLastError();
+    return dispatch_conv<4>(ConvArgs{nullptr, (const uint16_t*)wpk, bias, mbits, (uint16_t*)out, h, w, nb, st,
+                                     ConvHead{}, cf},
+                            nb, s);
 }
 
 hipError_t launch_conv_fwd_val(const void* in, const void* wpk, const float* bias, const ConvHead& hd, int h, int w,
                                DevState* st, double* vtrace, hipStream_t s) {
     const int nb = conv_bf16_blocks(h, w);
-    hipLaunchKernelGGL(k_conv_bf16<3>, dim3(nb), dim3(512), 0, s, (const uint16_t*)in, (const uint16_t*)wpk, bias,
-                       (uint16_t*)nullptr, (uint16_t*)nullptr, h, w, nb, (const DevState*)st, hd, ConvFirst{});
-    hipError_t e = hipGetLastError();
+    hipError_t e = dispatch_conv<3>(ConvArgs{(const uint16_t*)in, (const uint16_t*)wpk, bias, nullptr, nullptr, h, w,
+                                             nb, (const DevState*)st, hd, ConvFirst{}},
+                                    nb, s);
     if (e != hipSuccess) return e;
     return launch_decide(hd.lpart, nb, (long long)h * w, st, vtrace, s);
 }
@@ -1010,11 +1072,12 @@ hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, v
     dim3 grid((w + kTile - 1) / kTile, (h + kTile - 1) / kTile);
     if (bf16) {
         const int nb = conv_bf16_blocks(h, w);
-        hipLaunchKernelGGL(k_conv_bf16<1>, dim3(nb), dim3(512), 0, s, (const uint16_t*)dlt, (const uint16_t*)wpk,
-                           (const float*)nullptr, (uint16_t*)const_cast<void*>(mask), (uint16_t*)out, h, w, nb, st,
-                           ConvHead{}, ConvFirst{});
-        return hipGetLastError();
+        return dispatch_conv<1>(ConvArgs{(const uint16_t*)dlt, (const uint16_t*)wpk, nullptr,
+                                         (uint16_t*)const_cast<void*>(mask), (uint16_t*)out, h, w, nb, st, ConvHead{},
+                                         ConvFirst{}},
+                                nb, s);
     }
+    if (launch_recorder()) return hipErrorNotSupported;
     hipLaunchKernelGGL(k_conv_f32<1>, grid, dim3(256), 0, s, (const float*)dlt, (const float*)wpk,
                        (const float*)nullptr, (const float*)mask, (float*)out, h, w, st);
     return hipGetLastError();
@@ -1031,12 +1094,27 @@ int wgrad_splits(int h, int w, int bf16) {
 hipError_t launch_wgrad(const void* src, const void* dlt, float* part, int nsplit, int bf16, int h, int w,
                         const DevState* st, hipStream_t s) {
     if (bf16) {
-        hipLaunchKernelGGL(k_wgrad_bf16, dim3(4 * nsplit), dim3(512), 0, s, (const uint16_t*)src, (const uint16_t*)dlt,
-                           part, h, w, st);
+        const WgradArgs a{(const uint16_t*)src, (const uint16_t*)dlt, part, h, w, st};
+        if (launch_recorder()) return record_launch(KK_WGRAD, &a, sizeof(a), 4 * nsplit, (long long)h * w);
+        hipLaunchKernelGGL(k_wgrad_bf16, dim3(4 * nsplit), dim3(512), 0, s, a);
         return hipGetLastError();
     }
+    if (launch_recorder()) return hipErrorNotSupported;
     hipLaunchKernelGGL(k_wgrad_f32, dim3(nsplit), dim3(256), 0, s, (const float*)src, (const float*)dlt, part, h, w,
                        st);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_conv(int kind, GroupView v, int grid, hipStream_t s) {
+    switch (kind) {
+        case KK_CONV_FWD: hipLaunchKernelGGL(k_conv_bf16_group<0>, dim3(grid), dim3(512), 0, s, v); break;
+        case KK_CONV_DGRAD: hipLaunchKernelGGL(k_conv_bf16_group<1>, dim3(grid), dim3(512), 0, s, v); break;
+        case KK_CONV_HEAD: hipLaunchKernelGGL(k_conv_bf16_group<2>, dim3(grid), dim3(512), 0, s, v); break;
+        case KK_CONV_VAL: hipLaunchKernelGGL(k_conv_bf16_group<3>, dim3(grid), dim3(512), 0, s, v); break;
+        case KK_CONV_FIRST: hipLaunchKernelGGL(k_conv_bf16_group<4>, dim3(grid), dim3(512), 0, s, v); break;
+        case KK_WGRAD: hipLaunchKernelGGL(k_wgrad_bf16_group, dim3(grid), dim3(512), 0, s, v); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -7,6 +7,9 @@
 #include <stddef.h>
 
 #include <string>
+#include <vector>
+
+#include "n2f.h"
 
 namespace n2f {
 
@@ -146,6 +149,147 @@ hipError_t launch_adam(float* theta, float* m, float* v, float* g, const float* 
                        uint16_t* bwd16, const double* lpart, int nloss, long long loss_npix,
                        DevState* st, hipStream_t s);
 hipError_t launch_extract(const float* src, int h, int w, int C, float* out_chw, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Grouped launches: one launch of a kernel covers the same launch of many
+// runs (the images of a batch at the same step of their epochs).  Each run's
+// launch is a range of "virtual blocks", exactly the blocks its own launch
+// would have; a grouped kernel's blocks walk the virtual blocks of all runs
+// (block b takes b, b + grid, ...) and run each one as the run's own kernel
+// would, so a run's results are the same bits grouped or alone.
+//
+// While a Recorder is installed on the calling thread, the launchers below
+// record (kind, grid, arguments) instead of launching: the host runtime
+// records one epoch per run and lays the records out as per-run argument
+// tables in device memory.
+// ---------------------------------------------------------------------------
+enum KernelKind : int {
+    KK_CONV_FWD = 0,   // k_conv_bf16<0>: 64->64 forward
+    KK_CONV_DGRAD,     // k_conv_bf16<1>: data gradient
+    KK_CONV_HEAD,      // k_conv_bf16<2>: last forward layer + training head
+    KK_CONV_VAL,       // k_conv_bf16<3>: last validation layer + head
+    KK_CONV_FIRST,     // k_conv_bf16<4>: first layer (one channel) fused into layer 2
+    KK_WGRAD,          // k_wgrad_bf16
+    KK_CONV1_C1,       // k_conv1<C, BF16>, C = 1, 2, 3
+    KK_CONV1_C2,
+    KK_CONV1_C3,
+    KK_WGRAD1_C1,      // k_wgrad1<C, BF16>, C = 1, 2, 3
+    KK_WGRAD1_C2,
+    KK_WGRAD1_C3,
+    KK_ADAM,           // k_adam
+    KK_DECIDE,         // k_decide
+    KK_ACCUM,          // k_accumulate
+    KK_COUNT
+};
+constexpr int kArgStride = 512;   // bytes per run of a grouped launch's argument table
+
+struct LaunchRec {
+    int kind;
+    int grid;                     // virtual blocks of this run's launch
+    long long npix;               // pixels the launch processes (kernel timing)
+    alignas(16) unsigned char args[kArgStride];
+};
+struct Recorder {
+    std::vector<LaunchRec> recs;
+};
+// The calling thread's recorder (nullptr: launch directly).
+Recorder*& launch_recorder();
+hipError_t record_launch(int kind, const void* args, size_t bytes, int grid, long long npix);
+
+// A grouped launch: prefix = {n, 0, g_0, g_0 + g_1, ..., total} (the runs'
+// virtual block counts), args = n argument blocks of kArgStride bytes.
+struct GroupView {
+    const unsigned char* args;
+    const int* prefix;
+};
+// Device side: walk the virtual blocks of a grouped launch, block b taking
+// b, b + gridDim.x, ...; f(run, virtual block, virtual blocks of that run).
+// The barrier frees the block's shared memory for the next virtual block.
+template <class F>
+__device__ __forceinline__ void for_group_blocks(const GroupView& g, F&& f) {
+    const int n = g.prefix[0];
+    const int* pre = g.prefix + 1;
+    const int total = pre[n];
+    int s = 0;
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        while (vb >= pre[s + 1]) ++s;
+        __syncthreads();
+        f(s, vb - pre[s], pre[s + 1] - pre[s]);
+    }
+}
+// Launch kind `kind` over a group with `grid` blocks (n2f_conv.hip holds the
+// 3x3 kinds, n2f_kernels.hip the others).
+hipError_t launch_group_conv(int kind, GroupView v, int grid, hipStream_t s);
+hipError_t launch_group_misc(int kind, GroupView v, int grid, hipStream_t s);
+inline hipError_t launch_group(int kind, GroupView v, int grid, hipStream_t s) {
+    return (kind <= KK_WGRAD) ? launch_group_conv(kind, v, grid, s) : launch_group_misc(kind, v, grid, s);
+}
+
+// Record one epoch (the four training steps in the configured pair order,
+// then the validation) of network `net` of run r: the launches it would
+// make, in order.  BF16 runs only (N2F_EINVAL otherwise).
+n2f_status record_epoch(n2f_run* r, int net, std::vector<LaunchRec>* out);
+hipStream_t run_stream(n2f_run* r);
+// Kernel timing is on (n2f_profile_begin): grouped runs then poll every epoch,
+// so that no timed launch covers a network that has already finished.
+bool profiling_on();
+
+// Blocks of a grouped launch of each kind (a tuning parameter: results do
+// not depend on it).
+int group_grid(int kind);
+void set_group_grid(int kind, int grid);
+
+// Many runs that advance together: every launch of an epoch is one grouped
+// launch over all of them, and a whole epoch is one recorded graph.  The
+// runs share the group's stream (they must have been created on it) and
+// must have the same channel count.  The argument tables live in caller
+// device memory of table_bytes(cap) bytes and are rewritten (between
+// epochs, on the stream) when a run joins, leaves or moves to its next
+// network; the recorded graph stays valid.
+class Group {
+   public:
+    static constexpr int kMaxPos = 128;   // launches per epoch
+    static size_t table_bytes(int cap);
+    Group(int cap, char* d_tab, hipStream_t s) : cap_(cap), d_tab_(d_tab), stream_(s) {}
+    ~Group();
+    Group(const Group&) = delete;
+    Group& operator=(const Group&) = delete;
+    // Add network `net` of run r under `tag` (the caller's handle).
+    n2f_status add(n2f_run* r, int net, int tag);
+    // The run under `tag` moves on to network `net`.
+    n2f_status set_net(int tag, int net);
+    // Drop `tag`; the caller synchronises the stream before it reuses the
+    // run's workspace.
+    void remove(int tag);
+    int size() const { return (int)slots_.size(); }
+    // Queue `epochs` epochs of every run (graph replays, or direct launches
+    // in the epochs the kernel profiler times).
+    n2f_status launch(int epochs);
+    hipStream_t stream() const { return stream_; }
+
+   private:
+    struct Slot {
+        int tag;
+        n2f_run* run;
+        int net;
+        std::vector<LaunchRec> recs;
+    };
+    size_t pos_bytes() const;
+    n2f_status upload();
+    n2f_status enqueue_all(hipStream_t s, bool timed);
+    int cap_;
+    char* d_tab_;
+    hipStream_t stream_;
+    std::vector<Slot> slots_;
+    std::vector<int> kinds_;
+    std::vector<long long> npix_;          // pixels per launch over all runs
+    std::vector<unsigned char> host_;      // staging copy of the tables
+    bool dirty_ = true;
+    hipStream_t cap_stream_ = nullptr;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+    int exec_grid_[KK_COUNT] = {};
+};
 
 // Message returned by n2f_last_error() on the calling thread.
 void set_last_error(const char* msg);

@@ -324,9 +324,10 @@ template <int C>
 constexpr int conv1_unroll() { return C == 1 ? 4 : (C == 2 ? 2 : 1); }
 
 template <int C, bool BF>
-__global__ __launch_bounds__(kBlock) void k_conv1(const float* __restrict__ in, const float* __restrict__ w1,
-                                                  const float* __restrict__ b1, void* __restrict__ out,
-                                                  uint8_t* __restrict__ mbits, int h, int w, const DevState* st) {
+__device__ __forceinline__ void conv1_block(const float* __restrict__ in, const float* __restrict__ w1,
+                                            const float* __restrict__ b1, void* __restrict__ out,
+                                            uint8_t* __restrict__ mbits, int h, int w, const DevState* st,
+                                            const int bid) {
     const int stop = st->done;   // tested once the loads are in flight
     constexpr int U = conv1_unroll<C>();
     __shared__ __attribute__((aligned(16))) float sw[kTaps * C * kWidth + kWidth];
@@ -335,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_conv1(const float* __restrict__ in, 
     const long long npix = (long long)h * w;
     const int cl = threadIdx.x & 7;
     const int c0 = 32 * (cl & 1) + 4 * (cl >> 1), c1 = c0 + 16;
-    const long long pbase = (long long)blockIdx.x * (kPxPerBlock * U) + (threadIdx.x >> 3);
+    const long long pbase = (long long)bid * (kPxPerBlock * U) + (threadIdx.x >> 3);
     float xv[U][kTaps * C];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -413,8 +414,9 @@ __global__ __launch_bounds__(kBlock) void k_conv1(const float* __restrict__ in, 
 constexpr int kWg1Block = 512;
 
 template <int C, bool BF>
-__global__ __launch_bounds__(kWg1Block) void k_wgrad1(const float* __restrict__ in, const void* __restrict__ dlt,
-                                                   float* __restrict__ part, int h, int w, const DevState* st) {
+__device__ __forceinline__ void wgrad1_block(const float* __restrict__ in, const void* __restrict__ dlt,
+                                             float* __restrict__ part, int h, int w, const DevState* st,
+                                             const int bid, const int nb) {
     const int stop = st->done;                   // tested after the loads of the pixel loop
     constexpr int G = (C == 1) ? 8 : 4;          // channels per lane
     constexpr int LPP = kWidth / G;              // lanes per pixel
@@ -424,8 +426,8 @@ __global__ __launch_bounds__(kWg1Block) void k_wgrad1(const float* __restrict__ 
     __shared__ float red[kWg1Block / 64][n1];
     const int cg = threadIdx.x % LPP, slot = threadIdx.x / LPP;
     const long long npix = (long long)h * w;
-    const long long chunk = (npix + gridDim.x - 1) / gridDim.x;
-    const long long p0 = (long long)blockIdx.x * chunk;
+    const long long chunk = (npix + nb - 1) / nb;
+    const long long p0 = (long long)bid * chunk;
     const long long p1 = min(npix, p0 + chunk);
     float acc[nacc][G];
 #pragma unroll
@@ -494,7 +496,7 @@ __global__ __launch_bounds__(kWg1Block) void k_wgrad1(const float* __restrict__ 
         float sum = red[0][o];
 #pragma unroll
         for (int q = 1; q < kWg1Block / 64; ++q) sum += red[q][o];
-        part[(long long)blockIdx.x * n1 + o] = sum;
+        part[(long long)bid * n1 + o] = sum;
     }
 }
 
@@ -664,8 +666,8 @@ __global__ __launch_bounds__(kBlock) void k_head_val(const void* __restrict__ a8
 // epochs in a row without one end the run; fixed-epoch mode ends after
 // `fixed_epochs`.  One block.  `acc` tells the next kernel whether there is
 // an output to fold in.
-__global__ __launch_bounds__(kBlock) void k_decide(const double* __restrict__ vpart, int nblk, long long npix,
-                                                   DevState* st, double* __restrict__ vtrace) {
+__device__ __forceinline__ void decide_block(const double* __restrict__ vpart, int nblk, long long npix, DevState* st,
+                                             double* __restrict__ vtrace) {
     __shared__ double sv[kBlock];
     if (st->done) {
         if (threadIdx.x == 0) st->acc = 0;
@@ -715,12 +717,12 @@ __global__ __launch_bounds__(kBlock) void k_decide(const double* __restrict__ vp
 
 // Fold the last validation output into the running sum: a new best empties
 // the sum and becomes the best output; otherwise the output is added.
-__global__ __launch_bounds__(kBlock) void k_accumulate(const float* __restrict__ y, float* __restrict__ S,
-                                                       float* __restrict__ ybest, long long npix,
-                                                       const DevState* st) {
+__device__ __forceinline__ void accumulate_block(const float* __restrict__ y, float* __restrict__ S,
+                                                 float* __restrict__ ybest, long long npix, const DevState* st,
+                                                 const int bid, const int nb) {
     if (!st->acc) return;
     const int improved = st->improved;
-    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < npix; i += (long long)gridDim.x * kBlock) {
+    for (long long i = (long long)bid * kBlock + threadIdx.x; i < npix; i += (long long)nb * kBlock) {
         const float v = y[i];
         if (improved) {
             S[i] = 0.f;
@@ -782,18 +784,18 @@ constexpr int kAdamConvBlocks = (kLayers - 1) * kAdamWPL;
 constexpr int kAdamV0 = 4;                               // first layer: values per block
 constexpr int kAdamVH = 1;                               // head: values per block
 
-__global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, float* __restrict__ m,
-                                                 float* __restrict__ v, float* __restrict__ g,
-                                                 const float* __restrict__ part, const float* __restrict__ ginj,
-                                                 ParamTable pt, float lr, double beta1, double beta2, float eps,
-                                                 float* fwd, float* bwd, uint16_t* fwd16, uint16_t* bwd16,
-                                                 const double* __restrict__ lpart, int nloss, long long loss_npix,
-                                                 DevState* st) {
+__device__ __forceinline__ void adam_block(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
+                                           float* __restrict__ g, const float* __restrict__ part,
+                                           const float* __restrict__ ginj, const ParamTable& pt, float lr,
+                                           double beta1, double beta2, float eps, float* fwd, float* bwd,
+                                           uint16_t* fwd16, uint16_t* bwd16, const double* __restrict__ lpart,
+                                           int nloss, long long loss_npix, DevState* st, const int bid,
+                                           const int nb) {
     if (finished(st)) return;
     __shared__ float red[kBlock];
     __shared__ double lred[kBlock];
     const long long t_new = st->t;   // this step, already counted by the head kernel (or the bump)
-    if ((int)blockIdx.x == (int)gridDim.x - 1) {
+    if (bid == nb - 1) {
         // the last block only reports the step's loss: fixed-order sum of
         // the head's FP64 partials (strided per thread, then a tree)
         if (ginj) return;
@@ -814,9 +816,9 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, floa
     const float omb1 = (float)(1.0 - beta1), omb2 = (float)(1.0 - beta2);
     const float bc1 = (float)(1.0 - pow(beta1, (double)t_new));
     const float bc2 = (float)(1.0 - pow(beta2, (double)t_new));
-    if ((int)blockIdx.x < kAdamConvBlocks) {
-        const int l = 1 + (int)blockIdx.x / kAdamWPL;
-        const int il = ((int)blockIdx.x % kAdamWPL) * 256 + 4 * (threadIdx.x & 63);
+    if (bid < kAdamConvBlocks) {
+        const int l = 1 + bid / kAdamWPL;
+        const int il = (bid % kAdamWPL) * 256 + 4 * (threadIdx.x & 63);
         const int wq = threadIdx.x >> 6;
         const bool valid = il < kConvN;   // the layer's last chunk is partly empty
         const int i0 = pt.off[l] + il;
@@ -862,7 +864,7 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ theta, floa
     }
     // first layer, then the head
     const int nb0 = (pt.n[0] + kAdamV0 - 1) / kAdamV0;
-    const int rb = blockIdx.x - kAdamConvBlocks;
+    const int rb = bid - kAdamConvBlocks;
     const bool first = rb < nb0;
     const int l = first ? 0 : kLayers;
     const int V = first ? kAdamV0 : kAdamVH;
@@ -912,6 +914,139 @@ __global__ __launch_bounds__(kBlock) void k_extract(const float* __restrict__ sr
 
 inline unsigned nblocks(long long n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// Arguments of one launch (also one run's entry of a grouped launch), the
+// direct kernels, and their grouped forms (see GroupView).
+struct Conv1Args {
+    const float* in;
+    const float* w1;
+    const float* b1;
+    void* out;
+    uint8_t* mbits;
+    int h, w;
+    const DevState* st;
+};
+struct Wgrad1Args {
+    const float* in;
+    const void* dlt;
+    float* part;
+    int h, w;
+    const DevState* st;
+};
+struct DecideArgs {
+    const double* vpart;
+    int nblk;
+    long long npix;
+    DevState* st;
+    double* vtrace;
+};
+struct AccumArgs {
+    const float* y;
+    float* S;
+    float* ybest;
+    long long npix;
+    const DevState* st;
+};
+struct AdamArgs {
+    float* theta;
+    float* m;
+    float* v;
+    float* g;
+    const float* part;
+    const float* ginj;
+    ParamTable pt;
+    float lr;
+    double beta1, beta2;
+    float eps;
+    float* fwd;
+    float* bwd;
+    uint16_t* fwd16;
+    uint16_t* bwd16;
+    const double* lpart;
+    int nloss;
+    long long loss_npix;
+    DevState* st;
+};
+static_assert(sizeof(AdamArgs) <= kArgStride && sizeof(Conv1Args) <= kArgStride, "argument table stride");
+// pixels a launch processes (kernel timing)
+inline long long npix_of(const Conv1Args& a) { return (long long)a.h * a.w; }
+inline long long npix_of(const Wgrad1Args& a) { return (long long)a.h * a.w; }
+inline long long npix_of(const DecideArgs& a) { return a.npix; }
+inline long long npix_of(const AccumArgs& a) { return a.npix; }
+inline long long npix_of(const AdamArgs& a) { return a.loss_npix; }
+
+template <class A>
+__device__ __forceinline__ const A& group_args(const GroupView& g, int s) {
+    return *reinterpret_cast<const A*>(g.args + (size_t)s * kArgStride);
+}
+
+template <int C, bool BF>
+__global__ __launch_bounds__(kBlock) void k_conv1(Conv1Args a) {
+    conv1_block<C, BF>(a.in, a.w1, a.b1, a.out, a.mbits, a.h, a.w, a.st, blockIdx.x);
+}
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_conv1_group(GroupView g) {
+    for_group_blocks(g, [&](int s, int vb, int) {
+        const Conv1Args& a = group_args<Conv1Args>(g, s);
+        conv1_block<C, true>(a.in, a.w1, a.b1, a.out, a.mbits, a.h, a.w, a.st, vb);
+    });
+}
+
+template <int C, bool BF>
+__global__ __launch_bounds__(kWg1Block) void k_wgrad1(Wgrad1Args a) {
+    wgrad1_block<C, BF>(a.in, a.dlt, a.part, a.h, a.w, a.st, blockIdx.x, gridDim.x);
+}
+template <int C>
+__global__ __launch_bounds__(kWg1Block) void k_wgrad1_group(GroupView g) {
+    for_group_blocks(g, [&](int s, int vb, int nvb) {
+        const Wgrad1Args& a = group_args<Wgrad1Args>(g, s);
+        wgrad1_block<C, true>(a.in, a.dlt, a.part, a.h, a.w, a.st, vb, nvb);
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
+    decide_block(a.vpart, a.nblk, a.npix, a.st, a.vtrace);
+}
+__global__ __launch_bounds__(kBlock) void k_decide_group(GroupView g) {
+    for_group_blocks(g, [&](int s, int, int) {
+        const DecideArgs& a = group_args<DecideArgs>(g, s);
+        decide_block(a.vpart, a.nblk, a.npix, a.st, a.vtrace);
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void k_accumulate(AccumArgs a) {
+    accumulate_block(a.y, a.S, a.ybest, a.npix, a.st, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kBlock) void k_accumulate_group(GroupView g) {
+    for_group_blocks(g, [&](int s, int vb, int nvb) {
+        const AccumArgs& a = group_args<AccumArgs>(g, s);
+        accumulate_block(a.y, a.S, a.ybest, a.npix, a.st, vb, nvb);
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a) {
+    adam_block(a.theta, a.m, a.v, a.g, a.part, a.ginj, a.pt, a.lr, a.beta1, a.beta2, a.eps, a.fwd, a.bwd, a.fwd16,
+               a.bwd16, a.lpart, a.nloss, a.loss_npix, a.st, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kBlock) void k_adam_group(GroupView g) {
+    for_group_blocks(g, [&](int s, int vb, int nvb) {
+        const AdamArgs& a = group_args<AdamArgs>(g, s);
+        adam_block(a.theta, a.m, a.v, a.g, a.part, a.ginj, a.pt, a.lr, a.beta1, a.beta2, a.eps, a.fwd, a.bwd, a.fwd16,
+                   a.bwd16, a.lpart, a.nloss, a.loss_npix, a.st, vb, nvb);
+    });
+}
+
+// Launch one run's kernel directly, or record it for a grouped launch.
+template <class K, class A>
+hipError_t dispatch(K kernel, int kind, const A& a, int grid, int threads, hipStream_t s) {
+    if (launch_recorder()) {
+        if (kind < 0) return hipErrorNotSupported;   // no grouped form (FP32 kernels)
+        return record_launch(kind, &a, sizeof(a), grid, npix_of(a));
+    }
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, s, a);
+    return hipGetLastError();
+}
+
+
 }  // namespace
 
 hipError_t launch_minmax(const float* x, long long n, float* part, int nblk, unsigned* counter, float* lohi,
@@ -959,35 +1094,35 @@ hipError_t launch_pack(const float* theta, const ParamTable& pt, float* fwd, flo
 }
 
 template <int C>
-void launch_conv1_c(const float* in, const float* w1, const float* b1, void* out, uint8_t* mbits, int bf16, int h,
+hipError_t launch_conv1_c(const float* in, const float* w1, const float* b1, void* out, uint8_t* mbits, int bf16, int h,
                     int w, const DevState* st, hipStream_t s) {
-    const dim3 grid(nblocks((long long)h * w, kPxPerBlock * conv1_unroll<C>()));
-    if (bf16) hipLaunchKernelGGL((k_conv1<C, true>), grid, dim3(kBlock), 0, s, in, w1, b1, out, mbits, h, w, st);
-    else hipLaunchKernelGGL((k_conv1<C, false>), grid, dim3(kBlock), 0, s, in, w1, b1, out, mbits, h, w, st);
+    const int grid = (int)nblocks((long long)h * w, kPxPerBlock * conv1_unroll<C>());
+    const Conv1Args a{in, w1, b1, out, mbits, h, w, st};
+    return bf16 ? dispatch(k_conv1<C, true>, KK_CONV1_C1 + C - 1, a, grid, kBlock, s)
+                : dispatch(k_conv1<C, false>, -1, a, grid, kBlock, s);
 }
 
 hipError_t launch_conv1(const float* in, int C, const float* w1, const float* b1, void* out, uint16_t* mbits,
                         int bf16, int h, int w, const DevState* st, hipStream_t s) {
     uint8_t* mb = reinterpret_cast<uint8_t*>(mbits);
-    if (C == 1) launch_conv1_c<1>(in, w1, b1, out, mb, bf16, h, w, st, s);
-    else if (C == 2) launch_conv1_c<2>(in, w1, b1, out, mb, bf16, h, w, st, s);
-    else launch_conv1_c<3>(in, w1, b1, out, mb, bf16, h, w, st, s);
-    return hipGetLastError();
+    if (C == 1) return launch_conv1_c<1>(in, w1, b1, out, mb, bf16, h, w, st, s);
+    if (C == 2) return launch_conv1_c<2>(in, w1, b1, out, mb, bf16, h, w, st, s);
+    return launch_conv1_c<3>(in, w1, b1, out, mb, bf16, h, w, st, s);
 }
 
 template <int C>
-void launch_wgrad1_c(const float* in, const void* dlt, float* part, int nsplit, int bf16, int h, int w,
-                     const DevState* st, hipStream_t s) {
-    if (bf16) hipLaunchKernelGGL((k_wgrad1<C, true>), dim3(nsplit), dim3(kWg1Block), 0, s, in, dlt, part, h, w, st);
-    else hipLaunchKernelGGL((k_wgrad1<C, false>), dim3(nsplit), dim3(kWg1Block), 0, s, in, dlt, part, h, w, st);
+hipError_t launch_wgrad1_c(const float* in, const void* dlt, float* part, int nsplit, int bf16, int h, int w,
+                           const DevState* st, hipStream_t s) {
+    const Wgrad1Args a{in, dlt, part, h, w, st};
+    return bf16 ? dispatch(k_wgrad1<C, true>, KK_WGRAD1_C1 + C - 1, a, nsplit, kWg1Block, s)
+                : dispatch(k_wgrad1<C, false>, -1, a, nsplit, kWg1Block, s);
 }
 
 hipError_t launch_wgrad1(const float* in, int C, const void* dlt, float* part, int nsplit, int bf16, int h, int w,
                          const DevState* st, hipStream_t s) {
-    if (C == 1) launch_wgrad1_c<1>(in, dlt, part, nsplit, bf16, h, w, st, s);
-    else if (C == 2) launch_wgrad1_c<2>(in, dlt, part, nsplit, bf16, h, w, st, s);
-    else launch_wgrad1_c<3>(in, dlt, part, nsplit, bf16, h, w, st, s);
-    return hipGetLastError();
+    if (C == 1) return launch_wgrad1_c<1>(in, dlt, part, nsplit, bf16, h, w, st, s);
+    if (C == 2) return launch_wgrad1_c<2>(in, dlt, part, nsplit, bf16, h, w, st, s);
+    return launch_wgrad1_c<3>(in, dlt, part, nsplit, bf16, h, w, st, s);
 }
 
 int head_splits(long long npix) {
@@ -998,6 +1133,7 @@ int head_splits(long long npix) {
 hipError_t launch_head_train(const void* a8, const float* tgt, int C, int k, const float* w9, const float* b9,
                              void* d8, float* part, double* lpart, int nsplit, int bf16, long long npix,
                              DevState* st, hipStream_t s) {
+    if (launch_recorder()) return hipErrorNotSupported;   // grouped launches are BF16 only (fused head)
     if (bf16)
         hipLaunchKernelGGL(k_head_train<true>, dim3(nsplit), dim3(kBlock), 0, s, a8, tgt, C, k, w9, b9, d8, part,
                            lpart, npix, st);
@@ -1010,6 +1146,7 @@ hipError_t launch_head_train(const void* a8, const float* tgt, int C, int k, con
 hipError_t launch_head_val(const void* a8, const float* xs, int C, int k, const float* w9, const float* b9,
                            float* y, double* vpart, int nblk, int bf16, long long npix, DevState* st,
                            double* vtrace, hipStream_t s) {
+    if (launch_recorder()) return hipErrorNotSupported;
     if (bf16)
         hipLaunchKernelGGL(k_head_val<true>, dim3(nblk), dim3(kBlock), 0, s, a8, xs, C, k, w9, b9, y, vpart, npix,
                            (const DevState*)st);
@@ -1022,15 +1159,13 @@ hipError_t launch_head_val(const void* a8, const float* xs, int C, int k, const 
 }
 
 hipError_t launch_decide(const double* vpart, int nblk, long long npix, DevState* st, double* vtrace, hipStream_t s) {
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kBlock), 0, s, vpart, nblk, npix, st, vtrace);
-    return hipGetLastError();
+    return dispatch(k_decide, KK_DECIDE, DecideArgs{vpart, nblk, npix, st, vtrace}, 1, kBlock, s);
 }
 
 hipError_t launch_accumulate(const float* y, float* S, float* ybest, long long npix, DevState* st,
                              hipStream_t s) {
     const unsigned nb = std::min<unsigned>(nblocks(npix, kBlock * 4), 2048u);
-    hipLaunchKernelGGL(k_accumulate, dim3(nb), dim3(kBlock), 0, s, y, S, ybest, npix, (const DevState*)st);
-    return hipGetLastError();
+    return dispatch(k_accumulate, KK_ACCUM, AccumArgs{y, S, ybest, npix, st}, (int)nb, kBlock, s);
 }
 
 hipError_t launch_finalize(const float* y, const float* S, const float* ybest, const float* lohi, float* out,
@@ -1045,19 +1180,36 @@ hipError_t launch_adam(float* theta, float* m, float* v, float* g, const float* 
                        float* bwd, uint16_t* fwd16, uint16_t* bwd16, const double* lpart, int nloss,
                        long long loss_npix, DevState* st, hipStream_t s) {
     if (ginj) {
+        if (launch_recorder()) return hipErrorNotSupported;
         hipLaunchKernelGGL(k_bump_step, dim3(1), dim3(64), 0, s, st);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     const int nblk = kAdamConvBlocks + (pt.n[0] + kAdamV0 - 1) / kAdamV0 + (pt.n[kLayers] + kAdamVH - 1) / kAdamVH + 1;
-    hipLaunchKernelGGL(k_adam, dim3(nblk), dim3(kBlock), 0, s, theta, m, v, g, part, ginj, pt,
-                       lr, beta1, beta2, eps, fwd, bwd, fwd16, bwd16, lpart, nloss, loss_npix, st);
-    return hipGetLastError();
+    const AdamArgs a{theta, m, v, g, part, ginj, pt, lr, beta1, beta2, eps, fwd, bwd, fwd16, bwd16, lpart, nloss,
+                     loss_npix, st};
+    return dispatch(k_adam, ginj ? -1 : KK_ADAM, a, nblk, kBlock, s);
 }
 
 hipError_t launch_extract(const float* src, int h, int w, int C, float* out_chw, hipStream_t s) {
     const long long npix = (long long)h * w;
     hipLaunchKernelGGL(k_extract, dim3(nblocks(npix * C, kBlock)), dim3(kBlock), 0, s, src, npix, C, out_chw);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_misc(int kind, GroupView v, int grid, hipStream_t s) {
+    switch (kind) {
+        case KK_CONV1_C1: hipLaunchKernelGGL(k_conv1_group<1>, dim3(grid), dim3(kBlock), 0, s, v); break;
+        case KK_CONV1_C2: hipLaunchKernelGGL(k_conv1_group<2>, dim3(grid), dim3(kBlock), 0, s, v); break;
+        case KK_CONV1_C3: hipLaunchKernelGGL(k_conv1_group<3>, dim3(grid), dim3(kBlock), 0, s, v); break;
+        case KK_WGRAD1_C1: hipLaunchKernelGGL(k_wgrad1_group<1>, dim3(grid), dim3(kWg1Block), 0, s, v); break;
+        case KK_WGRAD1_C2: hipLaunchKernelGGL(k_wgrad1_group<2>, dim3(grid), dim3(kWg1Block), 0, s, v); break;
+        case KK_WGRAD1_C3: hipLaunchKernelGGL(k_wgrad1_group<3>, dim3(grid), dim3(kWg1Block), 0, s, v); break;
+        case KK_ADAM: hipLaunchKernelGGL(k_adam_group, dim3(grid), dim3(kBlock), 0, s, v); break;
+        case KK_DECIDE: hipLaunchKernelGGL(k_decide_group, dim3(grid), dim3(kBlock), 0, s, v); break;
+        case KK_ACCUM: hipLaunchKernelGGL(k_accumulate_group, dim3(grid), dim3(kBlock), 0, s, v); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

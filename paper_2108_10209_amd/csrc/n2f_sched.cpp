@@ -10,6 +10,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -103,7 +104,14 @@ struct n2f_batch {
     std::vector<hipStream_t> streams;
     bool own_streams = true;   // false: the batch runs on the caller's stream alone
     hipStream_t caller = nullptr;
+    // grouped mode: one group per channel count, tables after the images
+    bool grouped = false;
+    int group_cap = 0;
+    char* tables = nullptr;
+    std::unique_ptr<n2f::Group> groups[3];
     ~n2f_batch() {
+        if (grouped && !streams.empty()) (void)hipStreamSynchronize(streams[0]);
+        for (auto& g : groups) g.reset();
         for (n2f_run* r : runs)
             if (r) n2f_run_destroy(r);
         if (own_streams)
@@ -123,6 +131,22 @@ n2f_status order_after(hipStream_t s, hipStream_t caller) {
     if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
     (void)hipEventDestroy(ev);   // released once the wait has been satisfied
     return e == hipSuccess ? N2F_OK : sfail(N2F_EDEVICE, "stream ordering failed");
+}
+
+constexpr int kGroupExtra = 64;   // images a grouped batch can take beyond its initial n
+
+size_t batch_table_bytes(int n) { return 3 * align_up(n2f::Group::table_bytes(n + kGroupExtra)); }
+
+// Grouped mode: image i (created, not finished) joins its channel count's
+// group, created on first use.
+n2f_status group_join(n2f_batch* b, int i) {
+    const int c = b->C[i] - 1;
+    if (!b->groups[c]) {
+        b->groups[c].reset(new (std::nothrow) n2f::Group(
+            b->group_cap, b->tables + c * align_up(n2f::Group::table_bytes(b->group_cap)), b->streams[0]));
+        if (!b->groups[c]) return sfail(N2F_ENOMEM, "host allocation failed");
+    }
+    return b->groups[c]->add(b->runs[i], b->net[i], i);
 }
 
 // Create the run of a new batch image on the least loaded stream (by work)
@@ -147,8 +171,65 @@ n2f_status batch_append(n2f_batch* b, const float* d_in, int H, int W, int C, vo
     b->removed.push_back(0);
     b->work.push_back((long long)H * W * C);
     b->status.push_back(N2F_OK);
-    if (index) *index = b->n;
-    b->n++;
+    const int i = b->n++;
+    if (index) *index = i;
+    if (b->grouped && !b->finished[i]) {
+        s = group_join(b, i);
+        if (s != N2F_OK) {
+            n2f_run_destroy(b->runs[i]);
+            b->runs[i] = nullptr;
+            b->removed[i] = 1;
+            b->finished[i] = 1;
+            return s;
+        }
+    }
+    return N2F_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Grouped mode: every group replays whole epochs on the batch stream, then
+// the host reads each image's stopping rule; a finished network leaves its
+// group (or moves on to the image's next network), and the groups' tables
+// are rewritten before their next epoch.
+n2f_status batch_run_grouped(n2f_batch* b, int max_now) {
+    for (int ran = 0; ran < max_now;) {
+        bool any = false;
+        for (auto& g : b->groups) any = any || (g && g->size() > 0);
+        if (!any) break;
+        const int k = std::min(n2f::profiling_on() ? 1 : kPollEpochs, max_now - ran);
+        for (auto& g : b->groups) {
+            if (!g || g->size() == 0) continue;
+            n2f_status st = g->launch(k);
+            if (st < 0) return st;
+        }
+        ran += k;
+        for (int i = 0; i < b->n; ++i) {
+            if (b->finished[i]) continue;
+            n2f::Group* g = b->groups[b->C[i] - 1].get();
+            int done = 0, ep = 0;
+            n2f_status st = n2f_run_poll(b->runs[i], b->net[i], &done, &ep);
+            if (st == N2F_ENUMERIC) {
+                b->epochs[i] += ep;
+                b->status[i] = st;
+                b->finished[i] = 1;
+                g->remove(i);
+                continue;
+            }
+            if (st < 0) return st;
+            if (!done) continue;
+            b->epochs[i] += ep;
+            if (++b->net[i] >= b->C[i]) {
+                b->finished[i] = 1;
+                g->remove(i);
+            } else {
+                st = g->set_net(i, b->net[i]);
+                if (st < 0) return st;
+            }
+        }
+    }
     return N2F_OK;
 }
 
@@ -166,16 +247,19 @@ n2f_status n2f_batch_workspace_bytes(int n, const int* H, const int* W, const in
         if (s != N2F_OK) return s;
         tot += align_up(b);
     }
-    *bytes = tot;
+    *bytes = tot + batch_table_bytes(n);
     return N2F_OK;
 }
 
 n2f_status n2f_batch_create(n2f_batch** out, int n, const float* const* d_in, const int* H, const int* W,
                             const int* C, const n2f_config* cfg, void* d_ws, size_t ws_bytes, int n_streams,
                             hipStream_t stream) {
-    if (!out || !d_in || !d_ws || !cfg || n < 1 || n_streams < 0) return sfail(N2F_EINVAL, "bad batch arguments");
+    if (!out || !d_in || !d_ws || !cfg || n < 1 || n_streams < N2F_BATCH_GROUPED)
+        return sfail(N2F_EINVAL, "bad batch arguments");
     *out = nullptr;
     if (cfg->exact_targets) return sfail(N2F_EINVAL, "exact targets need a clean image per run: not in a batch");
+    if (n_streams == N2F_BATCH_GROUPED && cfg->precision != N2F_BF16)
+        return sfail(N2F_EINVAL, "grouped batches need BF16 (the FP32 path has no grouped kernels)");
     if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return sfail(N2F_EINVAL, "workspace must be 256-byte aligned");
     size_t need = 0;
     n2f_status s = n2f_batch_workspace_bytes(n, H, W, C, cfg, &need);
@@ -185,7 +269,13 @@ n2f_status n2f_batch_create(n2f_batch** out, int n, const float* const* d_in, co
     if (!b) return sfail(N2F_ENOMEM, "host allocation failed");
     b->cfg = *cfg;
     b->caller = stream;
-    if (n_streams == 0) {
+    if (n_streams == N2F_BATCH_GROUPED) {
+        b->grouped = true;
+        b->group_cap = n + kGroupExtra;
+        b->tables = static_cast<char*>(d_ws) + (need - batch_table_bytes(n));
+        b->own_streams = false;
+        b->streams.push_back(stream);
+    } else if (n_streams == 0) {
         b->own_streams = false;
         b->streams.push_back(stream);
     } else {
@@ -247,6 +337,13 @@ n2f_status n2f_batch_create(n2f_batch** out, int n, const float* const* d_in, co
         b->work.push_back(work(i));
         b->status.push_back(N2F_OK);
         b->n++;
+        if (b->grouped && !b->finished[i]) {
+            s = group_join(b, i);
+            if (s != N2F_OK) {
+                delete b;
+                return s;
+            }
+        }
     }
     *out = b;
     return N2F_OK;
@@ -267,6 +364,7 @@ n2f_status n2f_batch_remove(n2f_batch* b, int i) {
     if (!b || i < 0 || i >= b->n) return sfail(N2F_EINVAL, "bad batch arguments");
     if (b->removed[i]) return sfail(N2F_ESTATE, "image " + std::to_string(i) + " already removed");
     if (hipStreamSynchronize(b->streams[b->stream_of[i]]) != hipSuccess) return sfail(N2F_EDEVICE, "sync failed");
+    if (b->grouped && b->groups[b->C[i] - 1]) b->groups[b->C[i] - 1]->remove(i);
     n2f_run_destroy(b->runs[i]);
     b->runs[i] = nullptr;
     b->removed[i] = 1;
@@ -276,6 +374,16 @@ n2f_status n2f_batch_remove(n2f_batch* b, int i) {
 
 n2f_status n2f_batch_run(n2f_batch* b, int max_now, int* n_active) {
     if (!b || max_now < 1) return sfail(N2F_EINVAL, "bad batch arguments");
+    if (b->grouped) {
+        n2f_status st = batch_run_grouped(b, max_now);
+        if (st < 0) return st;
+        if (n_active) {
+            int a = 0;
+            for (int i = 0; i < b->n; ++i) a += !b->finished[i];
+            *n_active = a;
+        }
+        return N2F_OK;
+    }
     std::vector<int> ran(b->n, 0);
     const int ns = (int)b->streams.size();
     std::vector<std::vector<int>> on(ns);   // images of each stream

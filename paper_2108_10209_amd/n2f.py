@@ -33,6 +33,11 @@ SYMBOLS = [
 ]
 SERVER_SIMULATE = 1
 K_CONV_FWD, K_BACKWARD, K_ADAM = 0, 1, 2
+K_GROUP = 16                # + kind: one grouped launch (see n2f.h)
+GROUP_KINDS = ["conv3x3_fwd", "conv3x3_dgrad", "conv3x3_fwd_head", "conv3x3_fwd_val", "conv3x3_fwd_first",
+               "conv3x3_wgrad", "conv1_c1", "conv1_c2", "conv1_c3", "wgrad1_c1", "wgrad1_c2", "wgrad1_c3", "adam",
+               "decide", "accumulate"]
+BATCH_GROUPED = -1          # n_streams of a grouped batch
 
 
 class N2FError(RuntimeError):
@@ -367,7 +372,10 @@ def _ints(v):
 class Batch:
     """Independent images of uneven sizes trained together (see n2f.h).
 
-    n_streams = 0 runs every image on the caller's current stream."""
+    n_streams = 0 runs every image on the caller's current stream;
+    n_streams = BATCH_GROUPED (BF16) makes every launch of an epoch one
+    grouped launch over all images, replayed as one graph per epoch on the
+    caller's current stream."""
 
     def __init__(self, images, cfg: Config | None = None, n_streams: int = 4):
         import torch
