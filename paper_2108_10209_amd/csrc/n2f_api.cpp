@@ -1201,7 +1201,7 @@ Recorder*& launch_recorder() {
     return r;
 }
 
-hipError_t record_launch(int kind, const void* args, size_t bytes, int grid, long long npix) {
+hipError_t record_launch(int kind, const void* args, size_t bytes, int grid, long long npix, int cost) {
     Recorder* r = launch_recorder();
     if (!r || bytes > (size_t)kArgStride || kind < 0 || kind >= KK_COUNT || grid < 1) return hipErrorInvalidValue;
     r->recs.emplace_back();
@@ -1209,6 +1209,7 @@ hipError_t record_launch(int kind, const void* args, size_t bytes, int grid, lon
     rec.kind = kind;
     rec.grid = grid;
     rec.npix = npix;
+    rec.cost = std::max(1, cost);
     std::memset(rec.args, 0, sizeof(rec.args));
     std::memcpy(rec.args, args, bytes);
     return hipSuccess;
@@ -1244,15 +1245,18 @@ int g_group_grid[KK_COUNT] = {256, 256, 256, 256, 256, 256, 1024, 1024, 1024, 51
 
 int group_grid(int kind) { return (kind >= 0 && kind < KK_COUNT) ? g_group_grid[kind] : 1; }
 void set_group_grid(int kind, int grid) {
-    if (kind >= 0 && kind < KK_COUNT && grid >= 1) g_group_grid[kind] = grid;
+    if (kind >= 0 && kind < KK_COUNT && grid >= 1 && grid <= kMaxGroupGrid) g_group_grid[kind] = grid;
 }
 
-size_t Group::table_bytes(int cap) {
-    const size_t pre = align_up(sizeof(int) * (size_t)(cap + 2));
-    return (size_t)kMaxPos * (pre + (size_t)cap * kArgStride);
-}
+namespace {
+// Layout of one launch position of a group's tables: the prefix (cap + 2
+// ints), the block starts (kMaxGroupGrid + 1 ints), then cap argument blocks.
+size_t head_bytes(int cap) { return align_up(sizeof(int) * (size_t)(cap + 2 + kMaxGroupGrid + 1)); }
+}  // namespace
 
-size_t Group::pos_bytes() const { return align_up(sizeof(int) * (size_t)(cap_ + 2)) + (size_t)cap_ * kArgStride; }
+size_t Group::table_bytes(int cap) { return (size_t)kMaxPos * (head_bytes(cap) + (size_t)cap * kArgStride); }
+
+size_t Group::pos_bytes() const { return head_bytes(cap_) + (size_t)cap_ * kArgStride; }
 
 Group::~Group() {
     if (exec_) (void)hipGraphExecDestroy(exec_);
@@ -1309,21 +1313,37 @@ void Group::remove(int tag) {
 n2f_status Group::upload() {
     N2F_HIP(hipStreamSynchronize(stream_));
     const int n = (int)slots_.size();
-    const size_t pb = pos_bytes(), pre = align_up(sizeof(int) * (size_t)(cap_ + 2));
+    const size_t pb = pos_bytes(), hb = head_bytes(cap_);
     const size_t npos = kinds_.size();
     host_.assign(npos * pb, 0);
     npix_.assign(npos, 0);
     for (size_t j = 0; j < npos; ++j) {
         unsigned char* base = host_.data() + j * pb;
         int* pf = reinterpret_cast<int*>(base);
+        int* st = pf + cap_ + 2;
         pf[0] = n;
         pf[1] = 0;
+        long long cost = 0;
         for (int i = 0; i < n; ++i) {
             const LaunchRec& rec = slots_[i].recs[j];
             pf[2 + i] = pf[1 + i] + rec.grid;
-            std::memcpy(base + pre + (size_t)i * kArgStride, rec.args, kArgStride);
+            std::memcpy(base + hb + (size_t)i * kArgStride, rec.args, kArgStride);
             npix_[j] += rec.npix;
+            cost += (long long)rec.grid * rec.cost;
         }
+        // block b starts at the first virtual block whose cost before it is
+        // at least cost * b / G
+        const int G = group_grid(kinds_[j]);
+        long long before = 0;
+        int gv = 0, b = 0;
+        for (int i = 0; i < n; ++i) {
+            const LaunchRec& rec = slots_[i].recs[j];
+            for (int v = 0; v < rec.grid; ++v, ++gv) {
+                while (b < G && before >= (cost * b + G - 1) / G) st[b++] = gv;
+                before += rec.cost;
+            }
+        }
+        while (b <= G) st[b++] = gv;
     }
     if (!host_.empty()) N2F_HIP(hipMemcpyAsync(d_tab_, host_.data(), host_.size(), hipMemcpyHostToDevice, stream_));
     dirty_ = false;
@@ -1331,11 +1351,12 @@ n2f_status Group::upload() {
 }
 
 n2f_status Group::enqueue_all(hipStream_t s, bool with_timing) {
-    const size_t pb = pos_bytes(), pre = align_up(sizeof(int) * (size_t)(cap_ + 2));
+    const size_t pb = pos_bytes(), hb = head_bytes(cap_);
     for (size_t j = 0; j < kinds_.size(); ++j) {
         const int kind = kinds_[j];
         char* base = d_tab_ + j * pb;
-        const GroupView v{reinterpret_cast<const unsigned char*>(base + pre), reinterpret_cast<const int*>(base)};
+        const GroupView v{reinterpret_cast<const unsigned char*>(base + hb), reinterpret_cast<const int*>(base),
+                          reinterpret_cast<const int*>(base) + cap_ + 2};
         const int grid = group_grid(kind);
         if (with_timing) {
             N2F_HIP(timed(N2F_K_GROUP + kind, 1, npix_[j], s, [&] { return launch_group(kind, v, grid, s); }));
@@ -1348,12 +1369,12 @@ n2f_status Group::enqueue_all(hipStream_t s, bool with_timing) {
 
 n2f_status Group::launch(int epochs) {
     if (slots_.empty() || epochs < 1) return N2F_OK;
-    if (dirty_) {
+    bool stale = exec_ == nullptr;
+    for (int k = 0; k < KK_COUNT; ++k) stale = stale || exec_grid_[k] != group_grid(k);
+    if (dirty_ || stale) {   // the block starts depend on the grids too
         n2f_status s = upload();
         if (s != N2F_OK) return s;
     }
-    bool stale = exec_ == nullptr;
-    for (int k = 0; k < KK_COUNT; ++k) stale = stale || exec_grid_[k] != group_grid(k);
     if (stale) {
         // record one epoch of grouped launches on a private stream; the
         // tables it points at are rewritten in place, never moved

@@ -19,6 +19,8 @@
 // B operands stream from the packed weights in L2.
 #include "n2f_internal.h"
 
+#include <algorithm>
+
 namespace n2f {
 
 namespace {
@@ -369,12 +371,45 @@ __device__ __forceinline__ void first_layer_halo(uint16_t* halo, const float* sx
 // four lanes of the pixel add theirs by an xor butterfly, and the head
 // gradient sums over a row's 16 pixels by another, then over the waves in
 // order through LDS.
-// One block of the convolution grid: block `bid` of `nblk`.
+// Shared memory of one convolution block.  Declared in each kernel and
+// passed down: declared inside the (inlined) block function, the compiler
+// addressed it through extra registers and spilled.
 template <int MODE>
-__device__ __forceinline__ void conv_bf16_block(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
+struct ConvLds {
+    static constexpr bool kHead = MODE == 2 || MODE == 3, kFirst = MODE == 4;
+    __attribute__((aligned(16))) uint16_t sw[kTaps * kWidth * kWidth];
+    __attribute__((aligned(16))) uint16_t hb[2][kHaloPix * kWidth];
+    float shw[kHead ? kHeadN : 1];                        // head modes: head weights and bias
+    float shred[kHead ? 8 : 1][kHeadN];                   // MODE 2: per-wave dW9, db9 sums
+    double slred[8];                                      // head modes: per-wave BCE / squared-error sums
+    float sx[2][kFirst ? kXHaloPix : 1];                  // MODE 4: input halo (20 x 20) of each group's tile
+    float sw1[kFirst ? kTaps * kWidth + kWidth : 1];      // MODE 4: first-layer weights [t][co], then biases
+    float sbias[kWidth];                                  // forward and head modes: the layer's biases
+    float stgt[2][kHead ? kTile * kTile : 1];             // head modes: each group's tile of targets
+};
+
+// Blocks [vb_lo, vb_hi) of the convolution grid of one run (nblk blocks):
+// the block's own kernel runs one (vb_hi = vb_lo + 1); a block of a grouped
+// launch runs consecutive blocks of one run in one pass, so the layer's
+// weights are loaded once and the next block's first halo loads during the
+// current block's last tile.  Block vb handles tiles 2 vb + group + 2 k nblk
+// (k = 0, 1, ...) and, in the head modes, writes its own partial row, so
+// what each block computes does not depend on how the blocks are run.
+template <int MODE>
+__device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
                                                 const float* __restrict__ bias, uint16_t* __restrict__ mbits,
                                                 uint16_t* __restrict__ out, int h, int w, int nblk,
-                                                const DevState* st, ConvHead hd, ConvFirst cf, const int bid) {
+                                                const DevState* st, ConvHead hd, ConvFirst cf, const int vb_lo,
+                                                const int vb_hi, ConvLds<MODE>& L) {
+    auto& sw = L.sw;
+    auto& hb = L.hb;
+    auto& shw = L.shw;
+    auto& shred = L.shred;
+    auto& slred = L.slred;
+    auto& sx = L.sx;
+    auto& sw1 = L.sw1;
+    auto& sbias = L.sbias;
+    auto& stgt = L.stgt;
     constexpr bool kHead = (MODE == 2 || MODE == 3);   // head in the epilogue
     constexpr bool kFirst = (MODE == 4);               // first layer computed into the halo
     constexpr bool kFwd = (MODE == 0 || MODE == 4);    // plain forward epilogue
@@ -385,15 +420,6 @@ __device__ __forceinline__ void conv_bf16_block(const uint16_t* __restrict__ in,
     // once the weight and halo loads are in flight, so its memory latency
     // hides under theirs
     const int stop = st->done;
-    __shared__ __attribute__((aligned(16))) uint16_t sw[kTaps * kWidth * kWidth];
-    __shared__ __attribute__((aligned(16))) uint16_t hb[2][kHaloPix * kWidth];
-    __shared__ float shw[kHeadN];          // MODE 2: head weights and bias
-    __shared__ float shred[8][kHeadN];     // MODE 2: per-wave dW9, db9 sums
-    __shared__ double slred[8];            // MODE 2: per-wave BCE sums
-    __shared__ float sx[2][kXHaloPix];     // MODE 4: input halo (20 x 20) of each group's tile
-    __shared__ float sw1[kTaps * kWidth + kWidth];   // MODE 4: first-layer weights [t][co], then biases
-    __shared__ float sbias[kWidth];        // forward and head modes: the layer's biases
-    __shared__ float stgt[2][kTile * kTile];   // head modes: each group's tile of targets
     const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
     const int lane = tid & 63, wq = gt >> 6;
     const int g = lane >> 4, n = lane & 15;
@@ -408,7 +434,10 @@ __device__ __forceinline__ void conv_bf16_block(const uint16_t* __restrict__ in,
     const int tiles_x = (w + kTile - 1) / kTile, tiles_y = (h + kTile - 1) / kTile;
     const int ntiles = tiles_x * tiles_y;
     const int stride = 2 * nblk;
-    const int iters = (ntiles - 2 * bid + stride - 1) / stride;
+    // tile pairs of block v (<= 0 once 2 v >= ntiles); the blocks with
+    // tiles are [vb_lo, vb_work)
+    auto iters_of = [&](int v) { return (ntiles - 2 * v + stride - 1) / stride; };
+    const int vb_work = min(vb_hi, max(vb_lo, (ntiles + 1) / 2));
 
     uint4 pf[kPf];
     auto fetch = [&](int tile) {
@@ -440,9 +469,9 @@ __device__ __forceinline__ void conv_bf16_block(const uint16_t* __restrict__ in,
             if (have && idx < kXHaloPix && gy >= 0 && gy < h && gx >= 0 && gx < w) xf[u] = cf.x[(long long)gy * w + gx];
         }
     };
-    if (iters > 0) {
-        if constexpr (kFirst) fetch_x(2 * bid + grp);
-        else fetch(2 * bid + grp);
+    if (vb_lo < vb_work) {
+        if constexpr (kFirst) fetch_x(2 * vb_lo + grp);
+        else fetch(2 * vb_lo + grp);
     }
     float w1v[2] = {0.f, 0.f};
     if constexpr (kFirst) {
@@ -466,10 +495,41 @@ __device__ __forceinline__ void conv_bf16_block(const uint16_t* __restrict__ in,
 #pragma unroll
     for (int k = 0; k < kWChunks; ++k) reinterpret_cast<uint4*>(sw)[tid + 512 * k] = wr[k];
 
-    for (int k = 0; k < iters; ++k) {
-        const int tile = 2 * bid + grp + k * stride;
+    // head modes: block v's partial row from the per-wave sums (waves in
+    // order), then the sums start again from zero; called after a barrier
+    auto flush = [&](int v) {
+        if (MODE == 2 && tid < kHeadN) {
+            float sum = 0.f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sum += shred[q][tid];
+            hd.part[(long long)v * kHeadN + tid] = sum;
+        }
+        if (tid == 0) {
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sum += slred[q];
+            hd.lpart[v] = sum;
+            // one Adam step follows this head: count it (no other block reads t)
+            if (MODE == 2 && v == 0) hd.st->t += 1;
+        }
+        __syncthreads();
+        if (MODE == 2)
+            for (int i = tid; i < 8 * kHeadN; i += 512) (&shred[0][0])[i] = 0.f;
+        if (tid < 8) slred[tid] = 0.0;
+    };
+    // the work is the sequence of (block vb, tile k) pairs, k < iters_of(vb)
+    int vb = vb_lo, k = 0, iters = iters_of(vb_lo);
+    while (vb < vb_work) {
+        const int tile = 2 * vb + grp + k * stride;
         const bool have = tile < ntiles;
         const int x0 = have ? (tile % tiles_x) * kTile : 0, y0 = have ? (tile / tiles_x) * kTile : 0;
+        int nvb = vb, nk = k + 1;   // the next pair
+        if (nk >= iters) {
+            nvb = vb + 1;
+            nk = 0;
+        }
+        const bool more = nvb < vb_work;
+        const int ntile = 2 * nvb + grp + nk * stride;
         if constexpr (kFirst) {
 #pragma unroll
             for (int u = 0; u < kXPf; ++u) {
@@ -477,7 +537,7 @@ __device__ __forceinline__ void conv_bf16_block(const uint16_t* __restrict__ in,
                 if (idx < kXHaloPix) sx[grp][idx] = xf[u];
             }
             __syncthreads();
-            if (k + 1 < iters) fetch_x(tile + stride);   // in flight during the rest of the tile
+            if (more) fetch_x(ntile);   // in flight during the rest of the tile
             first_layer_halo(halo, sx[grp], sw1, gt, x0, y0, have, h, w, cf);
             __syncthreads();
         } else {
@@ -487,7 +547,7 @@ __device__ __forceinline__ void conv_bf16_block(const uint16_t* __restrict__ in,
                 if (idx < kHaloChunks) *reinterpret_cast<uint4*>(halo + swz(idx >> 3, idx & 7)) = pf[u];
             }
             __syncthreads();
-            if (k + 1 < iters) fetch(tile + stride);   // in flight during the MFMA loop
+            if (more) fetch(ntile);   // in flight during the MFMA loop
         }
 
         // head modes: target pixel gt of the tile, loaded before the MFMA loop
@@ -684,31 +744,16 @@ __device__ __forceinline__ void conv_bf16_block(const uint16_t* __restrict__ in,
             }
         }
         __syncthreads();   // the next tile's halo overwrites this buffer
+        if (kHead && nk == 0) flush(vb);   // block vb is complete
+        vb = nvb;
+        k = nk;
+        if (k == 0) iters = iters_of(vb);
     }
-    if (MODE == 3) {
-        __syncthreads();
-        if (tid == 0) {
-            double sum = 0.0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) sum += slred[q];
-            hd.lpart[bid] = sum;
-        }
-    }
-    if (MODE == 2) {
-        __syncthreads();
-        if (tid < kHeadN) {
-            float sum = 0.f;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) sum += shred[q][tid];
-            hd.part[(long long)bid * kHeadN + tid] = sum;
-        }
-        if (tid == 0) {
-            double sum = 0.0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) sum += slred[q];
-            hd.lpart[bid] = sum;
-            // one Adam step follows this head: count it (no other block reads t)
-            if (bid == 0) hd.st->t += 1;
+    // blocks without tiles still write their (zero) partial rows
+    if (kHead) {
+        for (int v = max(vb_lo, vb_work); v < vb_hi; ++v) {
+            __syncthreads();
+            flush(v);
         }
     }
 }
@@ -729,18 +774,36 @@ struct ConvArgs {
 static_assert(sizeof(ConvArgs) <= kArgStride, "argument table stride");
 inline long long npix_of(const ConvArgs& a) { return (long long)a.h * a.w; }
 
+// Separate parameters (not one argument struct): the struct form costs
+// registers here, and this kernel has none to spare.
 template <int MODE>
-__global__ __launch_bounds__(512) void k_conv_bf16(ConvArgs a) {
-    conv_bf16_block<MODE>(a.in, a.wpk, a.bias, a.mbits, a.out, a.h, a.w, a.nblk, a.st, a.hd, a.cf, blockIdx.x);
+__global__ __launch_bounds__(512) void k_conv_bf16(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
+                                                   const float* __restrict__ bias, uint16_t* __restrict__ mbits,
+                                                   uint16_t* __restrict__ out, int h, int w, int nblk,
+                                                   const DevState* st, ConvHead hd, ConvFirst cf) {
+    __shared__ ConvLds<MODE> L;
+    conv_bf16_range<MODE>(in, wpk, bias, mbits, out, h, w, nblk, st, hd, cf, blockIdx.x, blockIdx.x + 1, L);
 }
 
-// The same convolution over a group of runs (see GroupView).
+// The same convolution over a group of runs (see GroupView): block b runs
+// the consecutive virtual blocks [starts[b], starts[b + 1]) (balanced by
+// their tiles on the host), one run's share at a time.
 template <int MODE>
 __global__ __launch_bounds__(512) void k_conv_bf16_group(GroupView g) {
-    for_group_blocks(g, [&](int s, int vb, int) {
+    __shared__ ConvLds<MODE> L;
+    const int n = g.prefix[0];
+    const int* pre = g.prefix + 1;
+    const int lo = g.starts[blockIdx.x], hi = g.starts[blockIdx.x + 1];
+    int s = 0;
+    for (int gv = lo; gv < hi;) {
+        while (s < n && gv >= pre[s + 1]) ++s;
+        const int end = min(hi, pre[s + 1]);
+        __syncthreads();   // shared memory of the previous run's blocks is free
         const ConvArgs& a = *reinterpret_cast<const ConvArgs*>(g.args + (size_t)s * kArgStride);
-        conv_bf16_block<MODE>(a.in, a.wpk, a.bias, a.mbits, a.out, a.h, a.w, a.nblk, a.st, a.hd, a.cf, vb);
-    });
+        conv_bf16_range<MODE>(a.in, a.wpk, a.bias, a.mbits, a.out, a.h, a.w, a.nblk, a.st, a.hd, a.cf, gv - pre[s],
+                              end - pre[s], L);
+        gv = end;
+    }
 }
 
 // Grid of the BF16 convolution: one block (two tiles in flight) per CU at most.
@@ -1019,8 +1082,14 @@ template <int MODE>
 hipError_t dispatch_conv(const ConvArgs& a, int grid, hipStream_t s) {
     constexpr int kind = MODE == 0 ? KK_CONV_FWD : MODE == 1 ? KK_CONV_DGRAD : MODE == 2 ? KK_CONV_HEAD
                                    : MODE == 3 ? KK_CONV_VAL : KK_CONV_FIRST;
-    if (launch_recorder()) return record_launch(kind, &a, sizeof(a), grid, npix_of(a));
-    hipLaunchKernelGGL(k_conv_bf16<MODE>, dim3(grid), dim3(512), 0, s, a);
+    if (launch_recorder()) {
+        // cost of one virtual block: the tile pairs it runs (at least one)
+        const int ntiles = ((a.w + kTile - 1) / kTile) * ((a.h + kTile - 1) / kTile);
+        const int cost = std::max(1, (ntiles + 2 * a.nblk - 1) / (2 * a.nblk));
+        return record_launch(kind, &a, sizeof(a), grid, npix_of(a), cost);
+    }
+    hipLaunchKernelGGL(k_conv_bf16<MODE>, dim3(grid), dim3(512), 0, s, a.in, a.wpk, a.bias, a.mbits, a.out, a.h, a.w,
+                       a.nblk, a.st, a.hd, a.cf);
     return hipGetLastError();
 }
 
@@ -1095,7 +1164,7 @@ hipError_t launch_wgrad(const void* src, const void* dlt, float* part, int nspli
                         const DevState* st, hipStream_t s) {
     if (bf16) {
         const WgradArgs a{(const uint16_t*)src, (const uint16_t*)dlt, part, h, w, st};
-        if (launch_recorder()) return record_launch(KK_WGRAD, &a, sizeof(a), 4 * nsplit, (long long)h * w);
+        if (launch_recorder()) return record_launch(KK_WGRAD, &a, sizeof(a), 4 * nsplit, (long long)h * w, 1);
         hipLaunchKernelGGL(k_wgrad_bf16, dim3(4 * nsplit), dim3(512), 0, s, a);
         return hipGetLastError();
     }

@@ -187,6 +187,7 @@ struct LaunchRec {
     int kind;
     int grid;                     // virtual blocks of this run's launch
     long long npix;               // pixels the launch processes (kernel timing)
+    int cost;                     // relative work of one virtual block (balancing)
     alignas(16) unsigned char args[kArgStride];
 };
 struct Recorder {
@@ -194,13 +195,17 @@ struct Recorder {
 };
 // The calling thread's recorder (nullptr: launch directly).
 Recorder*& launch_recorder();
-hipError_t record_launch(int kind, const void* args, size_t bytes, int grid, long long npix);
+hipError_t record_launch(int kind, const void* args, size_t bytes, int grid, long long npix, int cost);
 
 // A grouped launch: prefix = {n, 0, g_0, g_0 + g_1, ..., total} (the runs'
-// virtual block counts), args = n argument blocks of kArgStride bytes.
+// virtual block counts), args = n argument blocks of kArgStride bytes,
+// starts = the first virtual block of each block of a launch whose blocks
+// take consecutive ranges (grid + 1 entries, balanced by cost).
+constexpr int kMaxGroupGrid = 1024;
 struct GroupView {
     const unsigned char* args;
     const int* prefix;
+    const int* starts;
 };
 // Device side: walk the virtual blocks of a grouped launch, block b taking
 // b, b + gridDim.x, ...; f(run, virtual block, virtual blocks of that run).
@@ -238,6 +243,9 @@ bool profiling_on();
 // not depend on it).
 int group_grid(int kind);
 void set_group_grid(int kind, int grid);
+// Kinds whose grouped blocks take consecutive, cost-balanced ranges of
+// virtual blocks (GroupView::starts); the others take b, b + grid, ...
+inline bool group_contiguous(int kind) { return kind <= KK_CONV_FIRST; }
 
 // Many runs that advance together: every launch of an epoch is one grouped
 // launch over all of them, and a whole epoch is one recorded graph.  The

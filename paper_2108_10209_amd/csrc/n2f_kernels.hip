@@ -1040,7 +1040,7 @@ template <class K, class A>
 hipError_t dispatch(K kernel, int kind, const A& a, int grid, int threads, hipStream_t s) {
     if (launch_recorder()) {
         if (kind < 0) return hipErrorNotSupported;   // no grouped form (FP32 kernels)
-        return record_launch(kind, &a, sizeof(a), grid, npix_of(a));
+        return record_launch(kind, &a, sizeof(a), grid, npix_of(a), 1);
     }
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, s, a);
     return hipGetLastError();
