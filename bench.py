@@ -1,18 +1,20 @@
 #!/usr/bin/env python3
 """Throughput of Noise2Fast denoising on one MI355X.
 
-Workload: 512x512 grayscale images (blobs scene, seed 0) with Gaussian noise
-sigma 15, 25 and 50 (/255, noise seeds 1, 2, 3), each trained from scratch
-with the paper's early-stopping rule (patience 100) and returned as the
-mean of the last 100 validation outputs.  One "step" denoises one image to
-convergence (standardise, checkerboard downsample, train, validate every
-epoch, stop, write the output); steps cycle through the three noise levels.
-The inputs sit in HBM before the timed region starts.
+Default workload: a batch of 64 independent grayscale images with sides
+uniform in [256, 1024] (blobs scenes, seed 3; Poisson peak 30 + Gaussian
+10/255 noise), each trained from scratch with the paper's early-stopping
+rule (patience 100) and returned as the mean of the last 100 validation
+outputs, BF16 convolutions, grouped launches (one launch per layer covers
+every image, one recorded graph per epoch).  One "step" denoises the whole
+batch to convergence.  The inputs sit in HBM before the timed region starts.
 
-Prints one JSON line: images/s (and Mpx/s, per-image latency and PSNR), the
-roofline position of the dominant convolution kernel measured with HIP
-events over the timed region, and the CPU FP64 oracle timed on a bounded
-sample of the same work.
+Prints one JSON line: images/s and Mpx/s, PSNR, the roofline position of
+the kernel with the largest summed time (HIP events around every grouped
+launch of the sampled epochs), the same images through the plain FP32 path
+one at a time, the single 512x512 configuration as a secondary figure, and
+the CPU FP64 oracle timed on a bounded sample of the same work.
+Other workloads: --workload single | serve | ablation | volume | large.
 """
 from __future__ import annotations
 
@@ -67,11 +69,64 @@ def _psnr_list(outs, cleans):
     return [synth.psnr(y.cpu().numpy(), c) for y, c in zip(outs, cleans)]
 
 
-def bench_batch(args):
+# grouped launch kinds (n2f.GROUP_KINDS order) whose work is the dense 3x3
+# contraction: algorithmic FLOP per pixel of the launch (the fused head and
+# first-layer work is small VALU work on top and is not counted)
+GROUP_CONV_KINDS = {0: CONV_FLOP_PER_PX, 1: CONV_FLOP_PER_PX, 2: CONV_FLOP_PER_PX, 3: CONV_FLOP_PER_PX,
+                    4: CONV_FLOP_PER_PX, 5: CONV_FLOP_PER_PX}
+# rocprofv3 symbol prefix of each grouped kind
+GROUP_SYMBOL = {0: "k_conv_bf16_group<0>", 1: "k_conv_bf16_group<1>", 2: "k_conv_bf16_group<2>",
+                3: "k_conv_bf16_group<3>", 4: "k_conv_bf16_group<4>", 5: "k_wgrad_bf16_group"}
+
+
+def host_info():
+    """Threads the oracle's BLAS uses, and the host CPU model."""
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return int(cores), model, os.cpu_count()
+
+
+def oracle_sec_per_mpx_epoch(noisy, min_seconds: float = 8.0):
+    """The FP64 oracle's seconds per (megapixel x epoch): whole epochs (four
+    training steps in table order, then the full-image validation) of one
+    image, repeated until at least `min_seconds` of CPU work."""
+    from oracle import n2f_oracle as O
+    from paper_2108_10209_amd import synth
+    h = O.Hyper()
+    xs, _, _ = O.standardize(noisy)
+    pairs = O.training_pairs(xs)
+    st = O.new_state(synth.init_params(1, 0)[0])
+    t0 = time.perf_counter()
+    epochs = 0
+    while True:
+        for inp, tgt in pairs:
+            st = O.train_step(st, 1, inp, tgt[0], h)[0]
+        O.validate(st.theta, 1, xs, 0, h)
+        epochs += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    sec = time.perf_counter() - t0
+    return sec / (epochs * noisy.shape[1] * noisy.shape[2] / 1e6), sec, epochs
+
+
+def bench_c3(args):
     """64 independent grayscale images, sides uniform in [256, 1024],
-    Poisson (peak 30) + Gaussian (10/255) noise, trained together as one
-    batch (BF16 by default): images/s to convergence, against the FP32
-    single-image path timed on the first `--fp32-sample` images."""
+    Poisson (peak 30) + Gaussian (10/255) noise, trained together to their
+    own early stops (BF16, grouped launches by default): images/s to
+    convergence.  Beside it: the plain FP32 path on the first
+    `--fp32-sample` images one at a time, the single 512x512 configuration,
+    and the oracle extrapolated per megapixel-epoch."""
     import numpy as np
     import torch
     from paper_2108_10209_amd import n2f, synth
@@ -81,41 +136,126 @@ def bench_batch(args):
     xs = [torch.from_numpy(x).to(dev) for _, x in pairs]
     npx = sum(x.numel() for x in xs)
     prec = n2f.BF16 if args.precision == "bf16" else n2f.FP32
+    streams = args.streams if prec == n2f.BF16 else max(args.streams, 1)
     cfg = n2f.default_config(precision=prec, max_epochs=args.max_epochs)
-    print(f"batch of {len(xs)} images, {npx / 1e6:.1f} Mpx", file=sys.stderr, flush=True)
+    print(f"batch of {len(xs)} images, {npx / 1e6:.1f} Mpx, streams {streams}", file=sys.stderr, flush=True)
+
+    def step():
+        b = n2f.Batch(xs, cfg, n_streams=streams)
+        b.run()
+        outs = [b.result(i) for i in range(len(xs))]
+        ep = [b.progress(i)[0] for i in range(len(xs))]
+        b.close()
+        return outs, ep
+
+    for i in range(args.warmup):
+        t0 = time.perf_counter()
+        step()
+        print(f"warmup {i} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    grouped = streams == n2f.BATCH_GROUPED
+    n2f.profile_begin(args.profile_every)
     t0 = time.perf_counter()
-    b = n2f.Batch(xs, cfg, n_streams=args.streams)
-    b.run()
-    outs = [b.result(i) for i in range(len(xs))]
+    for i in range(args.steps):
+        t1 = time.perf_counter()
+        outs, epochs = step()
+        print(f"step {i} done ({time.perf_counter() - t1:.1f} s)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    epochs = [b.progress(i)[0] for i in range(len(xs))]
-    b.close()
+    n2f.profile_end()
     ps = _psnr_list(outs, cleans)
-    k = min(args.fp32_sample, len(xs))
-    cfg32 = n2f.default_config(precision=n2f.FP32, max_epochs=args.max_epochs)
-    t1 = time.perf_counter()
-    outs32 = [n2f.denoise(xs[i], cfg32)[0] for i in range(k)]
-    torch.cuda.synchronize()
-    wall32 = time.perf_counter() - t1
-    ps32 = _psnr_list(outs32, cleans[:k])
-    ips = len(xs) / wall
-    return {
+    ips = len(xs) * args.steps / wall
+    mpx_epochs = sum(x.numel() * e for x, e in zip(xs, epochs)) / 1e6
+    # kernel timing: every grouped launch of one epoch in profile_every
+    kern, dom = {}, None
+    if grouped:
+        for kind, name in enumerate(n2f.GROUP_KINDS):
+            ms, nl, px = n2f.profile_read(n2f.K_GROUP + kind)
+            if nl == 0:
+                continue
+            kern[name] = {"total_ms_sampled": round(ms, 3), "launches_sampled": nl, "avg_us": round(1e3 * ms / nl, 2)}
+            if kind in GROUP_CONV_KINDS:
+                kern[name]["tflops"] = round(px * GROUP_CONV_KINDS[kind] / max(ms, 1e-9) / 1e9, 2)
+            if dom is None or ms > kern[n2f.GROUP_KINDS[dom]]["total_ms_sampled"]:
+                dom = kind
+    result = {
         "metric": "images/s denoised to convergence (batch of 64 images, sides U[256,1024], Poisson-Gaussian)",
-        "value": round(ips, 4), "unit": "images/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": round(1e3 * wall, 1), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "value": round(ips, 4), "unit": "images/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "baseline_note": "the paper has no figure for this workload; its 512x512 timing (under 45 s on an RTX 5000 "
+                         "mobile) is context only; the oracle on this host is in cpu_baseline",
         "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": f"batch of {len(xs)} independent grayscale images, H and W uniform in [256,1024], "
-                               "Poisson peak 30 + Gaussian 10/255, patience 100",
-                   "precision": args.precision, "streams": args.streams},
-        "mpx_per_s": round(npx / wall / 1e6, 3), "epochs_mean": round(float(np.mean(epochs)), 1),
+        "config": {"workload": f"batch of {len(xs)} independent grayscale images, H and W uniform in [256,1024] "
+                               "(blobs scenes, seed 3), Poisson peak 30 + Gaussian 10/255, patience 100, each to its "
+                               "own early stop; one step = the whole batch",
+                   "precision": args.precision, "launches": "grouped" if grouped else f"{streams} streams",
+                   "images": len(xs), "mpx": round(npx / 1e6, 3)},
+        "mpx_per_s": round(npx * args.steps / wall / 1e6, 3),
+        "mpx_epochs_per_s": round(mpx_epochs * args.steps / wall, 2),
+        "epochs_mean": round(float(np.mean(epochs)), 1),
         "psnr_mean": round(float(np.mean(ps)), 3),
-        "fp32_single_image": {"images": k, "images_per_s": round(k / wall32, 4),
-                              "psnr_mean_same_images": round(float(np.mean(ps32)), 3),
-                              "batched_psnr_mean_same_images": round(float(np.mean(ps[:k])), 3)},
-        "speedup_vs_fp32_single": round(ips / (k / wall32), 2),
+        "noisy_psnr_mean": round(float(np.mean([synth.psnr(x, c) for (c, x) in pairs])), 3),
+        "kernels": kern,
     }
+    if dom is not None:
+        k = kern[n2f.GROUP_KINDS[dom]]
+        peak = PEAK[args.precision]
+        result["roofline"] = {"bound": "mfma", "kernel": GROUP_SYMBOL.get(dom, n2f.GROUP_KINDS[dom]),
+                              "achieved": k.get("tflops", 0.0), "peak": peak, "unit": "TFLOP/s",
+                              "frac": round(k.get("tflops", 0.0) / peak, 4), "traffic": None}
+        tr = measured_traffic(GROUP_SYMBOL.get(dom, ""))
+        if tr is not None:
+            result["roofline"]["traffic"] = tr["bytes_per_launch"]
+            result["roofline"]["traffic_detail"] = tr
+    # the same images through the plain FP32 path, one at a time
+    k32 = min(args.fp32_sample, len(xs))
+    if k32 > 0:
+        cfg32 = n2f.default_config(precision=n2f.FP32, max_epochs=args.max_epochs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        outs32 = [n2f.denoise(xs[i], cfg32)[0] for i in range(k32)]
+        torch.cuda.synchronize()
+        wall32 = time.perf_counter() - t1
+        ps32 = _psnr_list(outs32, cleans[:k32])
+        result["fp32_single_image"] = {
+            "images": k32, "images_per_s": round(k32 / wall32, 4),
+            "psnr_mean_same_images": round(float(np.mean(ps32)), 3),
+            "batched_psnr_mean_same_images": round(float(np.mean(ps[:k32])), 3),
+            "batched_speedup_images_per_s": round(ips / (k32 / wall32), 2)}
+        print(f"fp32 single-image leg: {k32} images in {wall32:.1f} s", file=sys.stderr, flush=True)
+    # the single 512x512 configuration (secondary)
+    if args.secondary:
+        imgs = []
+        for i, sg in enumerate([15, 25, 50]):
+            clean, noisy = synth.single_512(sg, noise_seed=i + 1, size=512)
+            imgs.append((sg, clean, noisy, torch.from_numpy(noisy).to(dev)))
+        a2 = argparse.Namespace(**vars(args))
+        a2.steps, a2.warmup, a2.size = 3, 1, 512
+        single = {}
+        for pname in ("bf16", "fp32"):
+            r = run_single(a2, imgs, pname, profile=False)
+            single[pname] = {"images_per_s": round(r["ips"], 4), "epochs_mean": r["epochs_mean"],
+                             "psnr": [p["psnr"] for p in r["per_image"]],
+                             "ms_per_epoch": round(1e3 * r["wall"] / max(1, sum(p["epochs"] for p in r["per_image"])), 4)}
+        result["single_512"] = {"workload": "512x512 grayscale blobs, Gaussian sigma 15/25/50, one image at a time",
+                                **single}
+        print("single 512 done", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        print("cpu baseline ...", file=sys.stderr, flush=True)
+        med = int(np.argsort([x.numel() for x in xs])[len(xs) // 2])
+        spe, sec, ne = oracle_sec_per_mpx_epoch(pairs[med][1])
+        cores, model, ncpu = host_info()
+        batch_sec = spe * mpx_epochs
+        result["cpu_baseline"] = {
+            "value": round(len(xs) / batch_sec, 6), "unit": "images/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "host_cpus": ncpu, "sec_per_mpx_epoch": round(spe, 3),
+            "sample": f"{ne} whole epoch(s) (4 training steps + validation) of batch image {med} "
+                      f"({pairs[med][1].shape[1]}x{pairs[med][1].shape[2]}, the median size) in {sec:.1f} s, "
+                      f"extrapolated per megapixel-epoch to the batch's {mpx_epochs:.0f} Mpx-epochs "
+                      "(the GPU run's epochs to convergence)"}
+        result["speedup_vs_cpu_oracle"] = round(ips / result["cpu_baseline"]["value"], 1)
+    return result
 
 
 # Table 1 of the paper (BSD68, PSNR dB): normal, 2x2 blocks ("Quad"), exact
@@ -318,7 +458,8 @@ def bench_serve(args):
     outs = [torch.empty_like(x) for x in xs]
     prec = n2f.BF16 if args.precision == "bf16" else n2f.FP32
     cfg = n2f.default_config(precision=prec, max_epochs=args.max_epochs)
-    srv = n2f.Server(args.arena_gib << 30, cfg, n_streams=args.streams, max_active=args.max_active)
+    streams = args.streams if args.streams > 0 else 2
+    srv = n2f.Server(args.arena_gib << 30, cfg, n_streams=streams, max_active=args.max_active)
     torch.cuda.synchronize()
     print(f"serving {len(reqs)} requests at {args.rate}/s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -359,7 +500,7 @@ def bench_serve(args):
         "ms_per_step": round(1e3 * span, 1), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.precision, "data": "synthetic",
         "config": {"workload": f"first {len(reqs)} requests of the seeded trace (seed 5), arrival rate {args.rate}/s",
-                   "precision": args.precision, "streams": args.streams, "max_active": args.max_active,
+                   "precision": args.precision, "streams": streams, "max_active": args.max_active,
                    "epochs_per_step": args.epochs_per_step},
         "latency_s": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)},
         "psnr_mean": round(float(np.mean(ps)), 3),
@@ -371,56 +512,12 @@ def bench_serve(args):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp32", "bf16"], default="bf16")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison run")
-    ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--max-epochs", type=int, default=2000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-every", type=int, default=8,
-                    help="time the kernels of one epoch in N with HIP events")
-    ap.add_argument("--workload", choices=["single", "batch", "serve", "ablation", "volume", "large"], default="single")
-    ap.add_argument("--ablation-seeds", type=int, default=3)
-    ap.add_argument("--volume-z", type=int, default=41)
-    ap.add_argument("--volume-size", type=int, default=1024)
-    ap.add_argument("--large-size", type=int, default=2048)
-    ap.add_argument("--large-seeds", type=int, default=3)
-    ap.add_argument("--batch-n", type=int, default=64)
-    ap.add_argument("--streams", type=int, default=2)
-    ap.add_argument("--fp32-sample", type=int, default=8)
-    ap.add_argument("--serve-n", type=int, default=24)
-    ap.add_argument("--serve-fp32-n", type=int, default=24)
-    ap.add_argument("--rate", type=float, default=0.5)
-    ap.add_argument("--arena-gib", type=int, default=64)
-    ap.add_argument("--max-active", type=int, default=16)
-    ap.add_argument("--epochs-per-step", type=int, default=2)
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only copy MIB MiB device-to-device (a plain copy of known size, to scale HBM counters)")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        import torch
-        a = torch.ones(args.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_mib": args.copy_calibration, "launches": 3}))
-        return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}): each image is an independent run, "
-              "so several GPUs would each take their own images with no communication.", file=sys.stderr)
-        sys.exit(2)
-
-    if args.workload != "single":
-        res = {"batch": bench_batch, "serve": bench_serve, "ablation": bench_ablation,
-               "volume": bench_volume, "large": bench_large}[args.workload](args)
-        print(json.dumps(res), flush=True)
-        return
-
+def bench_single(args):
+    """512x512 grayscale images (blobs scene, seed 0) with Gaussian noise
+    sigma 15, 25 and 50 (/255, noise seeds 1, 2, 3), each trained from
+    scratch to its early stop; one step denoises one image; steps cycle
+    through the noise levels.  Roofline of the forward 3x3 convolution
+    (timed over runs of consecutive launches)."""
     import numpy as np
     import torch
     from paper_2108_10209_amd import n2f, synth
@@ -460,8 +557,9 @@ def main():
         "ms_per_step": round(1e3 * r["wall"] / args.steps, 2),
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": round(r["ips"] / (1.0 / 45.0), 2),
-        "baseline_note": "paper: under 45 s per 512x512 image on an RTX 5000 mobile (context only)",
+        "vs_baseline": None,
+        "baseline_note": "paper: under 45 s per 512x512 image on an RTX 5000 mobile (other hardware and data: "
+                         "context only)",
         "dtype": head,
         "data": "synthetic",
         "config": {"workload": f"single {args.size}x{args.size} grayscale, Gaussian sigma 15/25/50 per 255, "
@@ -490,7 +588,58 @@ def main():
     if not args.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(imgs[1][2], float(r["epochs_mean"]))
-    print(json.dumps(result), flush=True)
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="bf16")
+    ap.add_argument("--no-fp32", action="store_true", help="single: skip the FP32 comparison run")
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--max-epochs", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", dest="secondary", action="store_false",
+                    help="batch: skip the single 512x512 secondary figure")
+    ap.add_argument("--profile-every", type=int, default=8,
+                    help="time the kernels of one epoch in N with HIP events")
+    ap.add_argument("--workload", choices=["batch", "single", "serve", "ablation", "volume", "large"],
+                    default="batch")
+    ap.add_argument("--ablation-seeds", type=int, default=3)
+    ap.add_argument("--volume-z", type=int, default=41)
+    ap.add_argument("--volume-size", type=int, default=1024)
+    ap.add_argument("--large-size", type=int, default=2048)
+    ap.add_argument("--large-seeds", type=int, default=3)
+    ap.add_argument("--batch-n", type=int, default=64)
+    ap.add_argument("--streams", type=int, default=-1, help="batch: -1 grouped launches, >= 1 streams, 0 in turn")
+    ap.add_argument("--fp32-sample", type=int, default=8)
+    ap.add_argument("--serve-n", type=int, default=24)
+    ap.add_argument("--serve-fp32-n", type=int, default=24)
+    ap.add_argument("--rate", type=float, default=0.5)
+    ap.add_argument("--arena-gib", type=int, default=64)
+    ap.add_argument("--max-active", type=int, default=16)
+    ap.add_argument("--epochs-per-step", type=int, default=2)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device (a plain copy of known size, to scale HBM counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(args.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.copy_calibration, "launches": 3}))
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): each image is an independent run, "
+              "so several GPUs would each take their own images with no communication.", file=sys.stderr)
+        sys.exit(2)
+    res = {"batch": bench_c3, "single": bench_single, "serve": bench_serve, "ablation": bench_ablation,
+           "volume": bench_volume, "large": bench_large}[args.workload](args)
+    print(json.dumps(res), flush=True)
 
 
 def run_single(args, imgs, precision, profile):
