@@ -160,6 +160,22 @@ n2f_status n2f_denoise(const float* d_in, float* d_out, int H, int W, int C,
                        const n2f_config* cfg, void* d_ws, size_t ws_bytes,
                        hipStream_t stream);
 
+/* One-shot denoise for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and result as n2f_denoise, but the run's
+ * workspace is a fixed array of N2F_NOALLOC_MAX_BYTES inside the library,
+ * one per device it runs on, held until the process ends; the epochs run as
+ * direct launches (no graph is instantiated).  No device memory, stream,
+ * event or graph is created.  Runs on the current device (`stream` must
+ * belong to it).  N2F_ENOMEM when n2f_workspace_bytes(H, W, C, cfg) exceeds
+ * N2F_NOALLOC_MAX_BYTES (BF16 grayscale fits up to about 256 x 256);
+ * N2F_ESTATE while kernel timing (n2f_profile_begin) is on.  Calls on one
+ * device share the array and must not overlap: concurrent calls race.
+ * Synchronises. */
+#define N2F_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+n2f_status n2f_denoise_noalloc(const float* d_in, float* d_out, int H, int W, int C,
+                               const n2f_config* cfg, hipStream_t stream);
+
 /* "Exact" ablation (Methods, Ablation Study; Table 1 "Exact"; the ODD
  * approximation of the Theoretical Background): with the clean image known,
  * the target of pair (a -> b) becomes x_b - (s_b - s_a), i.e. the input's

@@ -29,8 +29,9 @@ SYMBOLS = [
     "n2f_batch_run", "n2f_batch_result", "n2f_batch_progress", "n2f_batch_destroy", "n2f_server_create",
     "n2f_server_submit", "n2f_server_step", "n2f_server_poll", "n2f_server_memory", "n2f_server_destroy",
     "n2f_run_set_clean", "n2f_max_project", "n2f_batch_run_of", "n2f_checkpoint_bytes", "n2f_save_checkpoint",
-    "n2f_load_checkpoint", "n2f_batch_add", "n2f_batch_remove", "n2f_server_cancel",
+    "n2f_load_checkpoint", "n2f_batch_add", "n2f_batch_remove", "n2f_server_cancel", "n2f_denoise_noalloc",
 ]
+NOALLOC_MAX_BYTES = 128 << 20   # N2F_NOALLOC_MAX_BYTES
 SERVER_SIMULATE = 1
 K_CONV_FWD, K_BACKWARD, K_ADAM = 0, 1, 2
 K_GROUP = 16                # + kind: one grouped launch (see n2f.h)
@@ -82,6 +83,7 @@ def lib():
             "n2f_result": [c_void_p, c_void_p],
             "n2f_denoise": [c_void_p, c_void_p, c_int, c_int, c_int, POINTER(Config), c_void_p, c_size_t,
                             c_void_p],
+            "n2f_denoise_noalloc": [c_void_p, c_void_p, c_int, c_int, c_int, POINTER(Config), c_void_p],
             "n2f_get_state": [c_void_p, c_int, c_void_p, c_void_p, c_void_p, POINTER(c_longlong)],
             "n2f_set_state": [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_longlong],
             "n2f_get_grad": [c_void_p, c_int, c_void_p, POINTER(c_double)],
@@ -333,6 +335,25 @@ def denoise(x, cfg: Config | None = None, ws=None):
     out = torch.empty_like(x)
     st = _check(lib().n2f_denoise(c_void_p(x.data_ptr()), c_void_p(out.data_ptr()), H, W, C, byref(cfg),
                                   c_void_p(ws.data_ptr()), nbytes, _stream_of(x)))
+    return out, st
+
+
+def denoise_noalloc(x, cfg: Config | None = None, out=None):
+    """One-shot denoise through the entry point that allocates no device
+    memory (its workspace is a fixed array inside the library); returns
+    (y, status).  Pass `out` (same shape, FP32, contiguous, same device) to
+    allocate nothing here either."""
+    import torch
+    _check_image(x)
+    cfg = cfg or default_config()
+    C, H, W = (int(s) for s in x.shape)
+    if out is None:
+        out = torch.empty_like(x)
+    _check_image(out, "out")
+    if tuple(out.shape) != tuple(x.shape) or out.device != x.device:
+        raise ValueError("out must have the image's shape and device")
+    st = _check(lib().n2f_denoise_noalloc(c_void_p(x.data_ptr()), c_void_p(out.data_ptr()), H, W, C, byref(cfg),
+                                          _stream_of(x)))
     return out, st
 
 

@@ -123,3 +123,17 @@ def test_max_project_argument_checks_without_device():
     # output inside the stack
     assert L.n2f_max_project(p, 2, 16, ctypes.c_void_p((1 << 20) + 64), None) == n2f.EINVAL
     assert b"overlaps" in L.n2f_last_error()
+
+
+def test_noalloc_rejects_before_touching_the_device():
+    """The allocation-free entry point checks its arguments and the fixed
+    workspace's size on the host first: a NULL pointer is N2F_EINVAL and an
+    image whose workspace exceeds N2F_NOALLOC_MAX_BYTES is N2F_ENOMEM."""
+    L = n2f.lib()
+    cfg = n2f.default_config(precision=n2f.BF16)
+    fake = ctypes.c_void_p(256)
+    assert L.n2f_denoise_noalloc(None, fake, 64, 64, 1, ctypes.byref(cfg), None) == n2f.EINVAL
+    assert n2f.workspace_bytes(1024, 1024, 1, cfg) > n2f.NOALLOC_MAX_BYTES
+    assert L.n2f_denoise_noalloc(fake, fake, 1024, 1024, 1, ctypes.byref(cfg), None) == n2f.ENOMEM
+    assert b"fixed device array" in L.n2f_last_error()
+    assert n2f.workspace_bytes(256, 256, 1, cfg) <= n2f.NOALLOC_MAX_BYTES
