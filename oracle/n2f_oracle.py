@@ -17,7 +17,9 @@ self-contradictory the reading taken here is stated in the function:
   Methods section; the printed +1 form leaves the image on odd rows);
   odd image sizes drop the last row/column for the downsamples only;
 * network: eight 3x3 conv+ReLU layers of width 64 with biases, zero padding,
-  then a 1x1 conv and a sigmoid (Methods, network paragraph; Fig. 2a);
+  then a 1x1 conv and a sigmoid (Methods, network paragraph; Fig. 2a); the
+  paragraph's own widths, doubling from 32 to 256 two layers at a time, are
+  available as LITERAL_WIDTHS (any per-layer widths are);
   one network per output channel, each seeing all input channels (Fig. 2a
   caption on RGB);
 * loss: mean binary cross-entropy over the target's pixels, in its logit form
@@ -49,25 +51,41 @@ import numpy as np
 
 WIDTH = 64
 N_LAYERS = 8
+# The widths the Methods' network paragraph gives layer by layer: two layers
+# each of 32, 64, 128 and 256 channels (the benchmark configurations use 64
+# throughout; both are supported).
+LITERAL_WIDTHS = (32, 32, 64, 64, 128, 128, 256, 256)
+
+
+def layer_widths(width, n_layers: int = N_LAYERS):
+    """Per-layer output channels: `width` is one int for every layer, or a
+    sequence of n_layers ints."""
+    if isinstance(width, (int, np.integer)):
+        return [int(width)] * n_layers
+    ws = [int(v) for v in width]
+    assert len(ws) == n_layers, (ws, n_layers)
+    return ws
 
 
 # ---------------------------------------------------------------------------
 # Parameters: canonical flat layout (W1, b1, ..., W8, b8, W9, b9), C order.
 # ---------------------------------------------------------------------------
-def param_spec(C: int, width: int = WIDTH, n_layers: int = N_LAYERS):
-    """Shapes of one network's parameters (Methods, network paragraph)."""
+def param_spec(C: int, width=WIDTH, n_layers: int = N_LAYERS):
+    """Shapes of one network's parameters (Methods, network paragraph):
+    3x3 layer l maps the previous layer's channels (C for the first) to its
+    own width; the 1x1 head maps the last width to one channel."""
     spec = []
     cin = C
-    for l in range(1, n_layers + 1):
-        spec.append((f"W{l}", (width, cin, 3, 3)))
-        spec.append((f"b{l}", (width,)))
-        cin = width
-    spec.append((f"W{n_layers + 1}", (1, width, 1, 1)))
+    for l, wl in enumerate(layer_widths(width, n_layers), start=1):
+        spec.append((f"W{l}", (wl, cin, 3, 3)))
+        spec.append((f"b{l}", (wl,)))
+        cin = wl
+    spec.append((f"W{n_layers + 1}", (1, cin, 1, 1)))
     spec.append((f"b{n_layers + 1}", (1,)))
     return spec
 
 
-def unflatten(theta: np.ndarray, C: int, width: int = WIDTH, n_layers: int = N_LAYERS) -> dict:
+def unflatten(theta: np.ndarray, C: int, width=WIDTH, n_layers: int = N_LAYERS) -> dict:
     theta = np.asarray(theta, dtype=np.float64)
     out, o = {}, 0
     for name, shape in param_spec(C, width, n_layers):
@@ -78,7 +96,7 @@ def unflatten(theta: np.ndarray, C: int, width: int = WIDTH, n_layers: int = N_L
     return out
 
 
-def flatten(params: dict, C: int, width: int = WIDTH, n_layers: int = N_LAYERS) -> np.ndarray:
+def flatten(params: dict, C: int, width=WIDTH, n_layers: int = N_LAYERS) -> np.ndarray:
     return np.concatenate([np.asarray(params[name], np.float64).ravel()
                            for name, _ in param_spec(C, width, n_layers)])
 
@@ -327,7 +345,7 @@ class Hyper:
     patience: int = 100
     max_epochs: int = 2000
     fixed_epochs: int = 0           # > 0: run exactly this many epochs, no early stop
-    width: int = WIDTH
+    width: object = WIDTH           # int, or one width per layer (e.g. LITERAL_WIDTHS)
     n_layers: int = N_LAYERS
 
 

@@ -32,26 +32,33 @@ WIDTH = 64
 N_LAYERS = 8
 
 
-def param_shapes(C: int, width: int = WIDTH, n_layers: int = N_LAYERS):
+LITERAL_WIDTHS = (32, 32, 64, 64, 128, 128, 256, 256)
+
+
+def param_shapes(C: int, width=WIDTH, n_layers: int = N_LAYERS):
     """Canonical parameter list of one output-channel network.
 
     Order and shapes of the flat parameter vector exchanged with the library:
-    W1 (width, C, 3, 3), b1 (width), W2..W8 (width, width, 3, 3) with biases,
-    then the 1x1 head W9 (1, width, 1, 1) and b9 (1).  Each tensor is
+    W1 (w1, C, 3, 3), b1 (w1), W2..W8 (w_l, w_{l-1}, 3, 3) with biases, then
+    the 1x1 head W9 (1, w8, 1, 1) and b9 (1), with w_l = `width` for every
+    layer or `width[l - 1]` when a sequence is given.  Each tensor is
     flattened in C order.  Returns [(name, shape, fan_in)].
     """
+    ws = [int(width)] * n_layers if isinstance(width, (int, np.integer)) else [int(v) for v in width]
+    assert len(ws) == n_layers
     out = []
     cin = C
     for l in range(1, n_layers + 1):
-        out.append((f"W{l}", (width, cin, 3, 3), cin * 9))
-        out.append((f"b{l}", (width,), cin * 9))
-        cin = width
-    out.append((f"W{n_layers + 1}", (1, width, 1, 1), width))
-    out.append((f"b{n_layers + 1}", (1,), width))
+        wl = ws[l - 1]
+        out.append((f"W{l}", (wl, cin, 3, 3), cin * 9))
+        out.append((f"b{l}", (wl,), cin * 9))
+        cin = wl
+    out.append((f"W{n_layers + 1}", (1, cin, 1, 1), cin))
+    out.append((f"b{n_layers + 1}", (1,), cin))
     return out
 
 
-def n_params(C: int, width: int = WIDTH, n_layers: int = N_LAYERS) -> int:
+def n_params(C: int, width=WIDTH, n_layers: int = N_LAYERS) -> int:
     return sum(int(np.prod(s)) for _, s, _ in param_shapes(C, width, n_layers))
 
 
@@ -80,7 +87,7 @@ def splitmix_uniform(seed: int, counters: np.ndarray) -> np.ndarray:
     return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
 
 
-def init_params(C: int, seed: int, width: int = WIDTH, n_layers: int = N_LAYERS) -> np.ndarray:
+def init_params(C: int, seed: int, width=WIDTH, n_layers: int = N_LAYERS) -> np.ndarray:
     """Initial weights of the C output-channel networks, shape (C, n_params), FP32.
 
     Every weight and bias of a layer is drawn from U(-1/sqrt(fan_in),

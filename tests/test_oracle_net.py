@@ -124,7 +124,8 @@ def _tiny(C, width, n_layers, H, W, seed):
     return theta, x, t
 
 
-@pytest.mark.parametrize("C,width,n_layers", [(1, 4, 3), (1, 4, 8), (3, 3, 2)])
+@pytest.mark.parametrize("C,width,n_layers", [(1, 4, 3), (1, 4, 8), (3, 3, 2), (1, (2, 3, 4, 5), 4),
+                                              (2, (2, 2, 3, 3, 4, 4, 5, 5), 8)])
 def test_gradients_central_differences(C, width, n_layers):
     """Every parameter tensor's gradient against central differences."""
     h = O.Hyper(width=width, n_layers=n_layers)
@@ -154,12 +155,13 @@ def test_gradients_central_differences(C, width, n_layers):
 
 
 def _torch_net(C, width, n_layers):
+    ws = [width] * n_layers if isinstance(width, int) else list(width)
     layers = []
     cin = C
-    for _ in range(n_layers):
-        layers += [torch.nn.Conv2d(cin, width, 3, padding=1), torch.nn.ReLU()]
-        cin = width
-    layers.append(torch.nn.Conv2d(width, 1, 1))
+    for wl in ws:
+        layers += [torch.nn.Conv2d(cin, wl, 3, padding=1), torch.nn.ReLU()]
+        cin = wl
+    layers.append(torch.nn.Conv2d(cin, 1, 1))
     return torch.nn.Sequential(*layers)
 
 
@@ -205,6 +207,51 @@ def test_train_steps_match_torch_adam(C):
             assert abs(lt.item() - loss) < 1e-12
     np.testing.assert_allclose(st.theta, _read(net), rtol=0, atol=1e-12)
     assert st.t == 8
+
+
+@pytest.mark.parametrize("C", [1, 3])
+def test_literal_width_train_steps_match_torch_adam(C):
+    """The Methods' own widths (32, 32, 64, 64, 128, 128, 256, 256): four
+    train steps against a PyTorch CPU FP64 model of those layer shapes
+    trained with BCE-with-logits and torch.optim.Adam(lr=1e-3), from the
+    library's initial weights for that net."""
+    widths, n_layers = O.LITERAL_WIDTHS, 8
+    h = O.Hyper(width=widths, n_layers=n_layers)
+    theta = synth.init_params(C, 7, widths)[C - 1].astype(np.float64)
+    x = np.random.default_rng(30 + C).uniform(0, 1, (C, 12, 10))
+    xs, _, _ = O.standardize(x)
+    pairs = O.training_pairs(xs)
+    k = C - 1
+    net = _torch_net(C, widths, n_layers)
+    _load(net, theta, C, widths, n_layers)
+    opt = torch.optim.Adam(net.parameters(), lr=1e-3)
+    st = O.new_state(theta)
+    for inp, tgt in pairs:
+        st, g, loss, y = O.train_step(st, C, inp, tgt[k], h)
+        opt.zero_grad()
+        z = net(torch.tensor(inp)[None])[0, 0]
+        lt = torch.nn.functional.binary_cross_entropy_with_logits(z, torch.tensor(tgt[k]))
+        lt.backward()
+        opt.step()
+        assert abs(lt.item() - loss) < 1e-12
+    np.testing.assert_allclose(st.theta, _read(net), rtol=0, atol=1e-12)
+    # validation output of the trained net equals the torch model's sigmoid
+    yv, v = O.validate(st.theta, C, xs, k, h)
+    with torch.no_grad():
+        yt = torch.sigmoid(net(torch.tensor(xs)[None])[0, 0]).numpy()
+    np.testing.assert_allclose(yv, yt, rtol=0, atol=1e-12)
+    assert abs(v - float(np.mean((yt - xs[k]) ** 2))) < 1e-14
+
+
+def test_literal_width_parameter_count():
+    """Closed form: sum over layers of w_l (9 w_{l-1} + 1), w_0 = C, plus the
+    head's w_8 + 1."""
+    for C in (1, 2, 3):
+        ws = [C] + list(O.LITERAL_WIDTHS)
+        closed = sum(ws[l] * (9 * ws[l - 1] + 1) for l in range(1, 9)) + ws[8] + 1
+        assert sum(int(np.prod(s)) for _, s in O.param_spec(C, O.LITERAL_WIDTHS)) == closed
+        assert synth.n_params(C, synth.LITERAL_WIDTHS) == closed
+    assert O.LITERAL_WIDTHS == synth.LITERAL_WIDTHS
 
 
 def test_forward_shapes_and_range():
