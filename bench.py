@@ -442,74 +442,141 @@ def bench_large(args):
 
 
 def bench_serve(args):
-    """Poisson-arrival stream (log-uniform sides in [128, 2048], 30% RGB,
-    Gaussian or Poisson noise per request) served by the continuous-batching
-    server in BF16, in real time; p50/p99 latency = completion - arrival.
-    Baseline: the plain FP32 path serving the same trace one request at a
-    time in arrival order, computed from each request's measured FP32
-    service time."""
+    """Poisson-arrival stream of `--serve-n` requests (the seeded trace:
+    sides log-uniform in [128, 2048], 30% RGB, Gaussian or Poisson noise per
+    request) served in real time by the continuous-batching server (BF16,
+    grouped launches by default); p50/p99 latency = completion - arrival.
+    `--rate 0` calibrates the arrival rate first: the first `--calib-n`
+    requests are served as one closed burst and the rate is set to 0.8 x the
+    measured capacity (recorded in the output).  Baseline: the plain FP32
+    path serving the same trace one request at a time in arrival order,
+    simulated from the measured FP32 service times of a stratified sample of
+    `--serve-fp32-n` requests (evenly spaced in work = pixels x channels;
+    each other request takes the service time of the sampled one nearest in
+    work, scaled by the work ratio)."""
     import numpy as np
     import torch
     from paper_2108_10209_amd import n2f, synth
     dev = torch.device("cuda:0")
-    reqs = synth.serving_trace(n=args.serve_n, rate=args.rate, seed=5)
-    data = [synth.request_image(r) for r in reqs]
-    xs = [torch.from_numpy(x).to(dev) for _, x in data]
-    outs = [torch.empty_like(x) for x in xs]
     prec = n2f.BF16 if args.precision == "bf16" else n2f.FP32
-    cfg = n2f.default_config(precision=prec, max_epochs=args.max_epochs)
+    grouped = prec == n2f.BF16 and args.streams < 0
     streams = args.streams if args.streams > 0 else 2
-    srv = n2f.Server(args.arena_gib << 30, cfg, n_streams=streams, max_active=args.max_active)
-    torch.cuda.synchronize()
-    print(f"serving {len(reqs)} requests at {args.rate}/s", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    nxt, done = 0, {}
-    while len(done) < len(reqs):
-        now = time.perf_counter() - t0
-        while nxt < len(reqs) and reqs[nxt].arrival <= now:
-            srv.submit(nxt, xs[nxt], outs[nxt])
-            nxt += 1
-        active, queued = srv.step(args.epochs_per_step) if (nxt > len(done)) else (0, 0)
-        if active == 0 and queued == 0 and nxt < len(reqs):
-            time.sleep(max(0.0, reqs[nxt].arrival - (time.perf_counter() - t0)))
-        for rid, st in srv.poll():
-            done[rid] = time.perf_counter() - t0
-    srv.close()
-    lat = np.array([done[i] - reqs[i].arrival for i in range(len(reqs))])
-    span = max(done.values()) - reqs[0].arrival
-    ps = _psnr_list(outs, [c for c, _ in data])
-    # baseline: FP32, one request at a time in arrival order
-    cfg32 = n2f.default_config(precision=n2f.FP32, max_epochs=args.max_epochs)
-    svc, outs32 = [], []
-    for x in xs[:args.serve_fp32_n]:
+    cfg = n2f.default_config(precision=prec, max_epochs=args.max_epochs)
+    base = synth.serving_trace(n=args.serve_n, rate=1.0, seed=5)
+    print(f"generating {len(base)} request images", file=sys.stderr, flush=True)
+    data = [synth.request_image(r) for r in base]
+    xs = [torch.from_numpy(x).to(dev) for _, x in data]
+    work = np.array([r.H * r.W * r.C for r in base], np.float64)
+
+    def serve(ids, arrivals):
+        """Serve requests `ids` arriving at `arrivals` (s after start, sorted);
+        returns completion times and outputs."""
+        srv = n2f.Server(args.arena_gib << 30, cfg, n_streams=streams, max_active=args.max_active, grouped=grouped)
+        outs = {i: torch.empty_like(xs[i]) for i in ids}
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        outs32.append(n2f.denoise(x, cfg32)[0])
-        torch.cuda.synchronize()
-        svc.append(time.perf_counter() - t1)
-    k = len(svc)
-    comp, t = [], 0.0
-    for i in range(k):
-        t = max(t, reqs[i].arrival) + svc[i]
-        comp.append(t)
-    lat32 = np.array([comp[i] - reqs[i].arrival for i in range(k)])
-    ps32 = _psnr_list(outs32, [c for c, _ in data[:k]])
-    return {
+        t0 = time.perf_counter()
+        nxt, done, last = 0, {}, t0
+        while len(done) < len(ids):
+            now = time.perf_counter() - t0
+            while nxt < len(ids) and arrivals[nxt] <= now:
+                srv.submit(ids[nxt], xs[ids[nxt]], outs[ids[nxt]])
+                nxt += 1
+            active, queued = srv.step(args.epochs_per_step) if (nxt > len(done)) else (0, 0)
+            if active == 0 and queued == 0 and nxt < len(ids):
+                time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+            for rid, st in srv.poll():
+                done[rid] = time.perf_counter() - t0
+            if time.perf_counter() - last > 30:
+                last = time.perf_counter()
+                print(f"  {len(done)}/{len(ids)} done, {active} active, {queued} queued at {now:.0f} s",
+                      file=sys.stderr, flush=True)
+        srv.close()
+        return done, outs
+
+    if args.serve_phase == "baseline":
+        # FP32 service times of the stratified sample only (written to
+        # --fp32-times for a later run of the trace), and the calibration
+        pass
+    rate, calib = args.rate, None
+    if rate <= 0:
+        ids = list(range(min(args.calib_n, len(base))))
+        done, _ = serve(ids, [0.0] * len(ids))
+        cap = len(ids) / max(done.values())
+        rate = 0.8 * cap
+        calib = {"requests": len(ids), "seconds": round(max(done.values()), 2), "capacity_req_per_s": round(cap, 4)}
+        print(f"calibration: capacity {cap:.3f} req/s -> rate {rate:.3f}/s", file=sys.stderr, flush=True)
+    arrivals = [r.arrival / rate for r in base]     # the trace's unit-rate arrivals, scaled
+    if args.serve_phase == "baseline":
+        done, outs = {}, {}
+        lat, span, ps = np.zeros(1), 1.0, [float("nan")] * len(base)
+    else:
+        print(f"serving {len(base)} requests at {rate:.3f}/s", file=sys.stderr, flush=True)
+        done, outs = serve(list(range(len(base))), arrivals)
+        lat = np.array([done[i] - arrivals[i] for i in range(len(base))])
+        span = max(done.values()) - arrivals[0]
+        ps = [synth.psnr(outs[i].cpu().numpy(), data[i][0]) for i in range(len(base))]
+    result = {
         "metric": "served images/s and p50/p99 request latency (Poisson arrivals, sides log-uniform [128,2048], 30% RGB)",
-        "value": round(len(reqs) / span, 4), "unit": "images/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "value": round(len(base) / span, 4), "unit": "images/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": round(1e3 * span, 1), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": f"first {len(reqs)} requests of the seeded trace (seed 5), arrival rate {args.rate}/s",
-                   "precision": args.precision, "streams": streams, "max_active": args.max_active,
+        "config": {"workload": f"first {len(base)} requests of the seeded trace (seed 5), Poisson arrivals at "
+                               f"{rate:.4f}/s", "precision": args.precision,
+                   "launches": "grouped" if grouped else f"{streams} streams", "max_active": args.max_active,
                    "epochs_per_step": args.epochs_per_step},
+        "rate_req_per_s": round(rate, 4), "calibration": calib,
         "latency_s": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)},
         "psnr_mean": round(float(np.mean(ps)), 3),
-        "fp32_sequential": {"requests": k, "images_per_s": round(k / (comp[-1] - reqs[0].arrival), 4),
-                            "latency_s": {"p50": round(float(np.percentile(lat32, 50)), 3),
-                                          "p99": round(float(np.percentile(lat32, 99)), 3)},
-                            "psnr_mean_same_requests": round(float(np.mean(ps32)), 3),
-                            "served_psnr_mean_same_requests": round(float(np.mean(ps[:k])), 3)},
     }
+    k = min(args.serve_fp32_n, len(base))
+    svc, ps32 = {}, {}
+    if args.fp32_times and os.path.exists(args.fp32_times) and args.serve_phase != "baseline":
+        saved = json.load(open(args.fp32_times))
+        svc = {int(i): v for i, v in saved["seconds"].items()}
+        ps32 = {int(i): v for i, v in saved["psnr"].items()}
+        k = len(svc)
+    elif k > 0:
+        order = np.argsort(work)
+        sample = sorted(set(int(order[int(round(q))]) for q in np.linspace(0, len(base) - 1, k)))
+        cfg32 = n2f.default_config(precision=n2f.FP32, max_epochs=args.max_epochs)
+        for j, i in enumerate(sample):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            y32 = n2f.denoise(xs[i], cfg32)[0]
+            torch.cuda.synchronize()
+            svc[i] = time.perf_counter() - t1
+            ps32[i] = synth.psnr(y32.cpu().numpy(), data[i][0])
+            if j % 8 == 7:
+                print(f"  fp32 sample {j + 1}/{len(sample)}", file=sys.stderr, flush=True)
+        if args.fp32_times:
+            with open(args.fp32_times, "w") as f:
+                json.dump({"seconds": svc, "psnr": ps32, "trace_requests": len(base)}, f)
+    if args.serve_phase == "baseline":
+        result["phase"] = "baseline (calibration and FP32 sample only; value and latency are not measured here)"
+        result["fp32_sample_seconds"] = {str(i): round(v, 3) for i, v in svc.items()}
+        return result
+    if svc:
+        sample = sorted(svc)
+        sw = np.array([work[i] for i in sample])
+        st = np.array([svc[i] for i in sample])
+
+        def service(i):   # nearest sampled request in work, scaled by the work ratio
+            j = int(np.argmin(np.abs(np.log(sw) - np.log(work[i]))))
+            return st[j] * work[i] / sw[j]
+        comp, t = [], 0.0
+        for i in range(len(base)):
+            t = max(t, arrivals[i]) + (svc[i] if i in svc else service(i))
+            comp.append(t)
+        lat32 = np.array([comp[i] - arrivals[i] for i in range(len(base))])
+        result["fp32_sequential"] = {
+            "sampled_requests": len(sample), "images_per_s": round(len(base) / (comp[-1] - arrivals[0]), 4),
+            "latency_s": {"p50": round(float(np.percentile(lat32, 50)), 3),
+                          "p99": round(float(np.percentile(lat32, 99)), 3)},
+            "psnr_mean_sampled": round(float(np.mean([ps32[i] for i in sample])), 3),
+            "served_psnr_mean_sampled": round(float(np.mean([ps[i] for i in sample])), 3),
+            "method": "FCFS in arrival order; service times measured on the stratified sample, the others taken "
+                      "from the nearest sampled request in work scaled by the work ratio"}
+    return result
 
 
 def bench_single(args):
@@ -615,11 +682,16 @@ def main():
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--streams", type=int, default=-1, help="batch: -1 grouped launches, >= 1 streams, 0 in turn")
     ap.add_argument("--fp32-sample", type=int, default=8)
-    ap.add_argument("--serve-n", type=int, default=24)
-    ap.add_argument("--serve-fp32-n", type=int, default=24)
-    ap.add_argument("--rate", type=float, default=0.5)
-    ap.add_argument("--arena-gib", type=int, default=64)
-    ap.add_argument("--max-active", type=int, default=16)
+    ap.add_argument("--serve-n", type=int, default=500)
+    ap.add_argument("--serve-fp32-n", type=int, default=48)
+    ap.add_argument("--calib-n", type=int, default=32)
+    ap.add_argument("--serve-phase", choices=["all", "baseline"], default="all",
+                    help="serve: 'baseline' only calibrates the rate and times the FP32 sample")
+    ap.add_argument("--fp32-times", default="", help="serve: JSON of FP32 sample service times (written by the "
+                                                    "baseline phase, read by a later full run)")
+    ap.add_argument("--rate", type=float, default=0.0, help="serve: arrivals per s (0: calibrate to 0.8 x capacity)")
+    ap.add_argument("--arena-gib", type=int, default=128)
+    ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--epochs-per-step", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a plain copy of known size, to scale HBM counters)")

@@ -358,12 +358,22 @@ n2f_status n2f_batch_destroy(n2f_batch* batch);
  * the others keep training.
  * With flags & N2F_SERVER_SIMULATE no device work is done: a request
  * finishes after `sim_epochs` epochs, which tests the admission and
- * bookkeeping logic on a machine without a GPU. */
+ * bookkeeping logic on a machine without a GPU.
+ * With flags & N2F_SERVER_GROUPED (BF16 only) every launch of an epoch is one
+ * grouped launch over all active requests of the same channel count (as in
+ * a grouped batch), replayed as one graph per epoch on the server's single
+ * stream (n_streams is then ignored); the launch tables for max_active runs
+ * per channel count take the first n2f_server_table_bytes(max_active)
+ * bytes of the arena, and requests are admitted into the rest. */
 #define N2F_SERVER_SIMULATE 1
+#define N2F_SERVER_GROUPED  2
 typedef struct n2f_server n2f_server;
 
 n2f_status n2f_server_create(n2f_server** srv, const n2f_config* cfg, void* d_arena, size_t arena_bytes,
                              int n_streams, int max_active, int flags);
+
+/* Arena bytes a grouped server keeps for its launch tables. */
+n2f_status n2f_server_table_bytes(int max_active, size_t* bytes);
 
 /* Queue a request.  d_in and d_out: device CHW images owned by the caller,
  * kept alive and untouched until the id is reported by n2f_server_poll.

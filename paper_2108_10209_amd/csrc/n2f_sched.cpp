@@ -509,12 +509,16 @@ struct n2f_server {
         n2f_run* run;
         size_t off;
         int net, stream, epochs;
+        int tag;   // grouped mode: the run's tag in its group
     };
     n2f_config cfg;
-    char* arena_base = nullptr;
+    char* arena_base = nullptr;   // where request workspaces start (after the tables in grouped mode)
     Arena arena;
     bool simulate = false;
+    bool grouped = false;
     int max_active = 1;
+    int next_tag = 0;
+    std::unique_ptr<n2f::Group> groups[3];
     std::vector<hipStream_t> streams;
     std::vector<int> stream_load;
     std::deque<Req> queue;
@@ -523,6 +527,7 @@ struct n2f_server {
     explicit n2f_server(size_t bytes) : arena(bytes) {}
     ~n2f_server() {
         for (hipStream_t s : streams) (void)hipStreamSynchronize(s);   // queued epochs end first
+        for (auto& g : groups) g.reset();
         for (Active& a : active)
             if (a.run) n2f_run_destroy(a.run);
         for (Req& q : queue)
@@ -537,6 +542,7 @@ namespace {
 // range, report its id.
 void retire(n2f_server* v, size_t idx, int status) {
     n2f_server::Active& a = v->active[idx];
+    if (v->grouped && a.run && v->groups[a.q.C - 1]) v->groups[a.q.C - 1]->remove(a.tag);
     if (a.run) n2f_run_destroy(a.run);
     v->arena.release(a.off, a.q.bytes);
     if (!v->simulate) v->stream_load[a.stream]--;
@@ -548,29 +554,53 @@ void retire(n2f_server* v, size_t idx, int status) {
 
 extern "C" {
 
+n2f_status n2f_server_table_bytes(int max_active, size_t* bytes) {
+    if (max_active < 1 || !bytes) return sfail(N2F_EINVAL, "bad server arguments");
+    *bytes = 3 * align_up(n2f::Group::table_bytes(max_active));
+    return N2F_OK;
+}
+
 n2f_status n2f_server_create(n2f_server** out, const n2f_config* cfg, void* d_arena, size_t arena_bytes,
                              int n_streams, int max_active, int flags) {
-    if (!out || !cfg || n_streams < 1 || max_active < 1) return sfail(N2F_EINVAL, "bad server arguments");
+    if (!out || !cfg || max_active < 1) return sfail(N2F_EINVAL, "bad server arguments");
+    const bool grouped = (flags & N2F_SERVER_GROUPED) != 0;
+    if (!grouped && n_streams < 1) return sfail(N2F_EINVAL, "n_streams must be >= 1");
     if (cfg->exact_targets) return sfail(N2F_EINVAL, "exact targets need a clean image per run: not served");
+    if (grouped && cfg->precision != N2F_BF16)
+        return sfail(N2F_EINVAL, "grouped serving needs BF16 (the FP32 path has no grouped kernels)");
     const bool sim = (flags & N2F_SERVER_SIMULATE) != 0;
+    const size_t tables = grouped ? 3 * align_up(n2f::Group::table_bytes(max_active)) : 0;
+    if (tables >= arena_bytes) return sfail(N2F_ENOMEM, "arena smaller than the grouped launch tables");
     if (!sim && !d_arena) return sfail(N2F_EINVAL, "arena is NULL");
     if (reinterpret_cast<uintptr_t>(d_arena) % kAlign) return sfail(N2F_EINVAL, "arena must be 256-byte aligned");
     size_t probe = 0;
     n2f_status s = n2f_workspace_bytes(2, 2, 1, cfg, &probe);   // validates the config
     if (s != N2F_OK) return s;
-    n2f_server* v = new (std::nothrow) n2f_server(arena_bytes);
+    n2f_server* v = new (std::nothrow) n2f_server(arena_bytes - tables);
     if (!v) return sfail(N2F_ENOMEM, "host allocation failed");
     v->cfg = *cfg;
-    v->arena_base = static_cast<char*>(d_arena);
+    v->arena_base = static_cast<char*>(d_arena) + tables;
     v->simulate = sim;
+    v->grouped = grouped && !sim;
     v->max_active = max_active;
     if (!sim) {
-        s = make_streams(v->streams, n_streams);
+        s = make_streams(v->streams, grouped ? 1 : n_streams);
         if (s != N2F_OK) {
             delete v;
             return s;
         }
         v->stream_load.assign(v->streams.size(), 0);
+        if (v->grouped) {
+            for (int c = 0; c < 3; ++c) {
+                v->groups[c].reset(new (std::nothrow) n2f::Group(
+                    max_active, static_cast<char*>(d_arena) + c * align_up(n2f::Group::table_bytes(max_active)),
+                    v->streams[0]));
+                if (!v->groups[c]) {
+                    delete v;
+                    return sfail(N2F_ENOMEM, "host allocation failed");
+                }
+            }
+        }
     }
     *out = v;
     return N2F_OK;
@@ -649,15 +679,35 @@ n2f_status n2f_server_step(n2f_server* v, int epochs, int* n_active, int* n_queu
                 retire(v, v->active.size() - 1, s);
                 continue;
             }
+            if (v->grouped) {
+                a.tag = v->next_tag++;
+                s = v->groups[q.C - 1]->add(a.run, 0, a.tag);
+                if (s != N2F_OK) {
+                    n2f_run_destroy(a.run);
+                    a.run = nullptr;
+                    v->active.push_back(a);
+                    retire(v, v->active.size() - 1, s);
+                    continue;
+                }
+            }
         }
         v->active.push_back(a);
     }
-    // 2. queue epochs for every active run
+    // 2. queue epochs for every active run (grouped: one launch sequence
+    // per channel count covers them all)
+    if (v->grouped) {
+        for (auto& g : v->groups) {
+            if (g->size() == 0) continue;
+            n2f_status s = g->launch(epochs);
+            if (s < 0) return s;
+        }
+    }
     for (n2f_server::Active& a : v->active) {
         if (v->simulate) {
             a.epochs += epochs;
             continue;
         }
+        if (v->grouped) continue;
         n2f_status s = n2f_run_launch_epochs(a.run, a.net, epochs);
         if (s < 0) return s;
     }
@@ -683,6 +733,13 @@ n2f_status n2f_server_step(n2f_server* v, int epochs, int* n_active, int* n_queu
             if (hipStreamSynchronize(v->streams[a.stream]) != hipSuccess) s = sfail(N2F_EDEVICE, "sync failed");
             retire(v, i, s);
             continue;
+        }
+        if (done && v->grouped) {   // the request's next network joins the group
+            s = v->groups[a.q.C - 1]->set_net(a.tag, a.net);
+            if (s < 0) {
+                retire(v, i, s);
+                continue;
+            }
         }
         ++i;
     }

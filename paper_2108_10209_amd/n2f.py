@@ -33,6 +33,7 @@ SYMBOLS = [
 ]
 NOALLOC_MAX_BYTES = 128 << 20   # N2F_NOALLOC_MAX_BYTES
 SERVER_SIMULATE = 1
+SERVER_GROUPED = 2
 K_CONV_FWD, K_BACKWARD, K_ADAM = 0, 1, 2
 K_GROUP = 16                # + kind: one grouped launch (see n2f.h)
 GROUP_KINDS = ["conv3x3_fwd", "conv3x3_dgrad", "conv3x3_fwd_head", "conv3x3_fwd_val", "conv3x3_fwd_first",
@@ -108,6 +109,7 @@ def lib():
             "n2f_batch_progress": [c_void_p, c_int, POINTER(c_int), POINTER(c_int)],
             "n2f_batch_destroy": [c_void_p],
             "n2f_server_create": [POINTER(c_void_p), POINTER(Config), c_void_p, c_size_t, c_int, c_int, c_int],
+            "n2f_server_table_bytes": [c_int, POINTER(c_size_t)],
             "n2f_server_submit": [c_void_p, c_longlong, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p],
             "n2f_server_cancel": [c_void_p, c_longlong],
             "n2f_server_step": [c_void_p, c_int, POINTER(c_int), POINTER(c_int)],
@@ -482,18 +484,25 @@ class Server:
     """Continuous-batching server over one device arena (see n2f.h)."""
 
     def __init__(self, arena_bytes: int, cfg: Config | None = None, n_streams: int = 4, max_active: int = 64,
-                 simulate: bool = False, device="cuda:0"):
+                 simulate: bool = False, device="cuda:0", grouped: bool = False):
+        """grouped=True (BF16): grouped launches over all active requests of a
+        channel count; the launch tables are added to arena_bytes here."""
         self.cfg = cfg or default_config()
         self.arena = None
         self._keep = {}   # request id -> (x, out), alive until reported finished
+        if grouped and not simulate:
+            tb = c_size_t()
+            _check(lib().n2f_server_table_bytes(max_active, byref(tb)))
+            arena_bytes += tb.value
         ptr = None
         if not simulate:
             import torch
             self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device)
             ptr = self.arena.data_ptr()
         self._ptr = c_void_p()
+        flags = (SERVER_SIMULATE if simulate else 0) | (SERVER_GROUPED if grouped else 0)
         _check(lib().n2f_server_create(byref(self._ptr), byref(self.cfg), ptr, arena_bytes, n_streams, max_active,
-                                       SERVER_SIMULATE if simulate else 0))
+                                       flags))
 
     def submit(self, rid: int, x=None, out=None, H: int = 0, W: int = 0, C: int = 1, sim_epochs: int = 0):
         """Queue request rid.  A real server takes x and out, (C, H, W) FP32

@@ -132,3 +132,34 @@ def test_grouped_kernel_timing_classes():
     assert n == 2 * (4 * 5 + 5) and ms > 0
     assert px == 2 * (4 * 5 * (64 * 32) + 5 * (64 * 64)) + 2 * (2 * 5 * (48 * 40) + 2 * 5 * (24 * 80) + 5 * 48 * 80)
     b.close()
+
+
+def test_grouped_server_results_equal_alone():
+    """Grouped serving (N2F_SERVER_GROUPED): requests of one and three
+    channels arrive while others train, wait for arena space, join their
+    channel count's group and leave it at epoch boundaries; each result is
+    the same bits as the request denoised alone."""
+    say("grouped server")
+    shapes = SHAPES + [(1, 70, 90), (3, 36, 30), (1, 128, 64)]
+    imgs = _images(shapes, seed=60)
+    cfg = n2f.default_config(precision=n2f.BF16, patience=4, max_epochs=50)
+    arena = 3 * max(n2f.workspace_bytes(H, W, C, cfg) for C, H, W in shapes)
+    srv = n2f.Server(arena, cfg, max_active=8, grouped=True)
+    xs = [dev(x) for x in imgs]
+    outs = [torch.empty_like(x) for x in xs]
+    pending = list(range(len(xs)))
+    finished, steps = {}, 0
+    while len(finished) < len(xs):
+        for _ in range(2):
+            if pending:
+                i = pending.pop(0)
+                srv.submit(i, xs[i], outs[i])
+        srv.step(2)
+        for rid, st in srv.poll():
+            assert st in (n2f.OK, n2f.WCAPPED)
+            finished[rid] = steps
+        steps += 1
+        assert steps < 500
+    for i, x in enumerate(imgs):
+        assert torch.equal(outs[i], _alone(x, cfg)[0]), i
+    srv.close()
