@@ -32,9 +32,10 @@
  *    wait for that stream; the others return once the work is queued.
  *  - A run is not thread-safe; distinct runs are independent.
  *  - Parameter vectors exchanged with the host use the canonical layout of
- *    one output-channel network: W1 (64, C, 3, 3), b1 (64), W2..W8
- *    (64, 64, 3, 3) each followed by its bias (64), W9 (1, 64, 1, 1), b9 (1),
- *    each flattened in C order (n2f_param_count() floats in total).
+ *    one output-channel network: W1 (w1, C, 3, 3), b1 (w1), W2..W8
+ *    (w_l, w_{l-1}, 3, 3) each followed by its bias (w_l), W9 (1, w8, 1, 1),
+ *    b9 (1), each flattened in C order (n2f_param_count() floats in total);
+ *    w_l = 64 for the default network.
  */
 #ifndef N2F_H
 #define N2F_H
@@ -66,7 +67,7 @@ typedef int n2f_status;
 
 typedef struct n2f_config {
     int    n_layers;          /* 3x3 conv layers; only 8 is supported */
-    int    width;             /* channels per conv layer; only 64 is supported */
+    int    width;             /* channels of every 3x3 layer when widths[] is all zero (16..256, multiple of 16) */
     float  lr;                /* Adam step size (Methods: 1e-3) */
     float  eps;               /* Adam epsilon (Kingma and Ba default 1e-8) */
     double beta1, beta2;      /* Adam moment decays (0.9, 0.999); double so that 1 - beta is exact to FP32 */
@@ -79,11 +80,15 @@ typedef struct n2f_config {
     int    use_graph;         /* n2f_run_epochs replays one recorded HIP graph per epoch */
     int    downsample;        /* N2F_DS_CHECKERBOARD or N2F_DS_QUAD (training pairs only) */
     int    exact_targets;     /* 1: "Exact" ablation; the run waits for n2f_run_set_clean() */
+    int    widths[8];         /* per-layer output channels (16..256, multiples of 16), e.g. the Methods'
+                                 own 32, 32, 64, 64, 128, 128, 256, 256; all zero: every layer `width`.
+                                 Width 64 throughout runs on the tuned kernels; any other widths on generic
+                                 FP32-MFMA kernels (BF16 storage in BF16 runs), not in grouped launches */
 } n2f_config;
 
 typedef struct n2f_run n2f_run;
 
-/* Fill *cfg with the paper's settings: 8 layers of width 64, Adam lr 1e-3,
+/* Fill *cfg with the paper's settings: 8 layers of width 64 (widths[] zero), Adam lr 1e-3,
  * betas 0.9/0.999, eps 1e-8, patience 100, max_epochs 2000, early stopping,
  * pairs in table order, FP32, seed 0, epochs replayed as HIP graphs,
  * checkerboard downsampling, plain targets. */

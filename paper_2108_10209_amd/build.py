@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libn2f.so")
-SOURCES = ["n2f_kernels.hip", "n2f_conv.hip", "n2f_api.cpp", "n2f_sched.cpp", "n2f_noalloc.hip"]
+SOURCES = ["n2f_kernels.hip", "n2f_conv.hip", "n2f_api.cpp", "n2f_sched.cpp", "n2f_noalloc.hip", "n2f_generic.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -48,26 +48,44 @@ struct CanonLayer {
     int cout, cin, taps;
 };
 
-std::vector<CanonLayer> canon_layers(int C) {
+// Per-layer output channels of the eight 3x3 layers: widths[] if set, else
+// `width` for every layer.
+struct Widths {
+    int w[kLayers];
+};
+Widths eff_widths(const n2f_config* cfg) {
+    Widths ew{};
+    for (int l = 0; l < kLayers; ++l) ew.w[l] = cfg->widths[0] ? cfg->widths[l] : cfg->width;
+    return ew;
+}
+bool is_default_width(const Widths& ew) {
+    for (int l = 0; l < kLayers; ++l)
+        if (ew.w[l] != kWidth) return false;
+    return true;
+}
+
+std::vector<CanonLayer> canon_layers(int C, const Widths& ew) {
     std::vector<CanonLayer> v;
     int cin = C;
     for (int l = 0; l < kLayers; ++l) {
-        v.push_back({kWidth, cin, kTaps});
-        cin = kWidth;
+        v.push_back({ew.w[l], cin, kTaps});
+        cin = ew.w[l];
     }
-    v.push_back({1, kWidth, 1});
+    v.push_back({1, cin, 1});
     return v;
 }
 
-ParamTable make_table(int C, int n1split, int nsplit, int hsplit) {
+ParamTable make_table(int C, const Widths& ew, int n1split, int nsplit, int hsplit) {
     ParamTable pt{};
     int off = 0;
     long long poff = 0;
     for (int l = 0; l <= kLayers; ++l) {
-        const int cin = (l == 0) ? C : kWidth;
+        const int cin = (l == 0) ? C : ew.w[l - 1];
+        const int cout = (l < kLayers) ? ew.w[l] : 1;
         pt.cin[l] = cin;
+        pt.cout[l] = cout;
         pt.off[l] = off;
-        pt.n[l] = (l < kLayers) ? kTaps * cin * kWidth + kWidth : kHeadN;
+        pt.n[l] = (l < kLayers) ? kTaps * cin * cout + cout : cin + 1;
         pt.split[l] = (l == 0) ? n1split : (l < kLayers) ? nsplit : hsplit;
         pt.poff[l] = poff;
         off += pt.n[l];
@@ -82,39 +100,37 @@ long long partial_floats(const ParamTable& pt) {
 }
 
 // Canonical (OIHW per layer) <-> internal (tap-major W[t][ci][co]) maps.
-void canon_to_internal(const float* src, float* dst, int C, const ParamTable& pt) {
-    const auto L = canon_layers(C);
+void canon_to_internal(const float* src, float* dst, const ParamTable& pt) {
     int co_off = 0;
     for (int l = 0; l <= kLayers; ++l) {
-        const CanonLayer& cl = L[l];
+        const int cin = pt.cin[l], cout = pt.cout[l];
         const float* s = src + co_off;
         float* d = dst + pt.off[l];
         if (l < kLayers) {
-            for (int co = 0; co < cl.cout; ++co)
-                for (int ci = 0; ci < cl.cin; ++ci)
-                    for (int t = 0; t < kTaps; ++t) d[(t * cl.cin + ci) * kWidth + co] = s[(co * cl.cin + ci) * kTaps + t];
-            std::memcpy(d + kTaps * cl.cin * kWidth, s + kTaps * cl.cin * kWidth, sizeof(float) * kWidth);
+            for (int co = 0; co < cout; ++co)
+                for (int ci = 0; ci < cin; ++ci)
+                    for (int t = 0; t < kTaps; ++t) d[(t * cin + ci) * cout + co] = s[(co * cin + ci) * kTaps + t];
+            std::memcpy(d + kTaps * cin * cout, s + kTaps * cin * cout, sizeof(float) * cout);
         } else {
-            std::memcpy(d, s, sizeof(float) * kHeadN);
+            std::memcpy(d, s, sizeof(float) * pt.n[l]);
         }
         co_off += pt.n[l];
     }
 }
 
-void internal_to_canon(const float* src, float* dst, int C, const ParamTable& pt) {
-    const auto L = canon_layers(C);
+void internal_to_canon(const float* src, float* dst, const ParamTable& pt) {
     int co_off = 0;
     for (int l = 0; l <= kLayers; ++l) {
-        const CanonLayer& cl = L[l];
+        const int cin = pt.cin[l], cout = pt.cout[l];
         const float* s = src + pt.off[l];
         float* d = dst + co_off;
         if (l < kLayers) {
-            for (int co = 0; co < cl.cout; ++co)
-                for (int ci = 0; ci < cl.cin; ++ci)
-                    for (int t = 0; t < kTaps; ++t) d[(co * cl.cin + ci) * kTaps + t] = s[(t * cl.cin + ci) * kWidth + co];
-            std::memcpy(d + kTaps * cl.cin * kWidth, s + kTaps * cl.cin * kWidth, sizeof(float) * kWidth);
+            for (int co = 0; co < cout; ++co)
+                for (int ci = 0; ci < cin; ++ci)
+                    for (int t = 0; t < kTaps; ++t) d[(co * cin + ci) * kTaps + t] = s[(t * cin + ci) * cout + co];
+            std::memcpy(d + kTaps * cin * cout, s + kTaps * cin * cout, sizeof(float) * cout);
         } else {
-            std::memcpy(d, s, sizeof(float) * kHeadN);
+            std::memcpy(d, s, sizeof(float) * pt.n[l]);
         }
         co_off += pt.n[l];
     }
@@ -133,12 +149,24 @@ struct Plan {
     size_t act_elems, dlt_elems;
     // offsets inside one network's block
     size_t s_state, s_theta, s_m, s_v, s_g, s_fwd, s_bwd, s_fwd16, s_bwd16, s_trace, s_S, s_yb, s_y;
+    // widths other than 64 throughout (generic kernels): per-layer widths,
+    // padded input channels of the packed forward operands, packed operand
+    // offsets inside a network's block (bytes), stash offsets (elements)
+    int gen;
+    Widths ew;
+    int maxw;
+    int cipad[kLayers];
+    size_t g_fwd[kLayers], g_bwd[kLayers];
+    size_t g_act[kLayers];
 };
 
 n2f_status check_cfg(const n2f_config* cfg) {
     if (!cfg) return fail(N2F_EINVAL, "config is NULL");
-    if (cfg->n_layers != kLayers || cfg->width != kWidth)
-        return fail(N2F_EINVAL, "only 8 layers of width 64 are supported");
+    if (cfg->n_layers != kLayers) return fail(N2F_EINVAL, "only 8 layers are supported");
+    const Widths ew = eff_widths(cfg);
+    for (int l = 0; l < kLayers; ++l)
+        if (ew.w[l] < 16 || ew.w[l] > 256 || ew.w[l] % 16)
+            return fail(N2F_EINVAL, "layer widths must be multiples of 16 from 16 to 256");
     if (!(cfg->lr > 0.f) || !(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0) || !(cfg->beta2 >= 0.0 && cfg->beta2 < 1.0) ||
         !(cfg->eps > 0.f))
         return fail(N2F_EINVAL, "bad Adam hyper-parameters");
@@ -180,16 +208,30 @@ n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
         q.wl = q.Wc;
     }
     q.P = q.hu * q.wu;
-    q.nsplit = std::max(wgrad_splits(q.hu, q.wu, q.bf), wgrad_splits(q.hl, q.wl, q.bf));
-    q.n1split = (int)std::max(1LL, std::min((long long)kMaxSplit, ((long long)q.P + 511) / 512));
-    // BF16: the head runs in the last forward convolution's epilogue, one
-    // partial row per block of its grid (the larger of the two pair shapes)
-    q.hsplit = q.bf ? std::max(head_fused_blocks(q.hu, q.wu), head_fused_blocks(q.hl, q.wl)) : head_splits(q.P);
+    q.ew = eff_widths(cfg);
+    q.gen = !is_default_width(q.ew);
+    q.maxw = 0;
+    for (int l = 0; l < kLayers; ++l) q.maxw = std::max(q.maxw, q.ew.w[l]);
     const long long HW = (long long)H * W;
-    q.vblk = (int)std::max(1LL, std::min((HW + 255) / 256, 1024LL));
+    if (q.gen) {
+        // generic kernels: one split count for every weight gradient (up to
+        // 64 tiles' worth of partial rows), one head block per 128 pixels
+        auto tiles = [](int h, int w) { return ((w + 15) / 16) * ((h + 15) / 16); };
+        q.nsplit = std::max(1, std::min(64, std::max(tiles(q.hu, q.wu), tiles(q.hl, q.wl))));
+        q.n1split = q.nsplit;
+        q.hsplit = head_splits(q.P);
+        q.vblk = head_splits(HW);
+    } else {
+        q.nsplit = std::max(wgrad_splits(q.hu, q.wu, q.bf), wgrad_splits(q.hl, q.wl, q.bf));
+        q.n1split = (int)std::max(1LL, std::min((long long)kMaxSplit, ((long long)q.P + 511) / 512));
+        // BF16: the head runs in the last forward convolution's epilogue, one
+        // partial row per block of its grid (the larger of the two pair shapes)
+        q.hsplit = q.bf ? std::max(head_fused_blocks(q.hu, q.wu), head_fused_blocks(q.hl, q.wl)) : head_splits(q.P);
+        q.vblk = (int)std::max(1LL, std::min((HW + 255) / 256, 1024LL));
+    }
     q.mmblk = (int)std::max(1LL, std::min((HW * C + 4095) / 4096, 1024LL));
     q.max_trace = std::max(cfg->max_epochs, cfg->fixed_epochs) + 1;
-    q.pt = make_table(C, q.n1split, q.nsplit, q.hsplit);
+    q.pt = make_table(C, q.ew, q.n1split, q.nsplit, q.hsplit);
 
     size_t o = 0;
     q.o_misc = o;
@@ -217,7 +259,7 @@ n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
     n += tb;
     q.s_g = n;
     n += tb;
-    const size_t pk = (size_t)(kLayers - 1) * kPackN;
+    const size_t pk = q.gen ? 0 : (size_t)(kLayers - 1) * kPackN;
     q.s_fwd = n;
     n += q.bf ? 0 : align_up(sizeof(float) * pk);
     q.s_bwd = n;
@@ -226,6 +268,18 @@ n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
     n += q.bf ? align_up(sizeof(uint16_t) * pk) : 0;
     q.s_bwd16 = n;
     n += q.bf ? align_up(sizeof(uint16_t) * pk) : 0;
+    if (q.gen) {
+        // packed operands of every layer: FP32 for the first layer (and the
+        // FP32 path), BF16 for layers 2..8 of a BF16 run
+        for (int l = 0; l < kLayers; ++l) {
+            q.cipad[l] = l == 0 ? (C + 15) / 16 * 16 : q.ew.w[l - 1];
+            const size_t es_w = (q.bf && l > 0) ? 2 : 4;
+            q.g_fwd[l] = n;
+            n += align_up(es_w * kTaps * q.cipad[l] * q.ew.w[l]);
+            q.g_bwd[l] = n;
+            if (l > 0) n += align_up(es_w * kTaps * q.ew.w[l] * q.ew.w[l - 1]);
+        }
+    }
     q.s_trace = n;
     n += align_up(sizeof(double) * q.max_trace);
     q.s_S = n;
@@ -240,12 +294,24 @@ n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
         o += n;
     }
     const size_t es = q.bf ? 2 : 4;
-    q.act_elems = (size_t)std::max<long long>(8LL * q.P, 2LL * HW) * kWidth;
-    q.dlt_elems = (size_t)q.P * kWidth;
+    if (q.gen) {
+        // training stash: layer l's activation at P * (w_0 + .. + w_{l-1});
+        // validation ping-pong: two buffers of HW x max width, aliased
+        size_t acc = 0;
+        for (int l = 0; l < kLayers; ++l) {
+            q.g_act[l] = acc;
+            acc += (size_t)q.P * q.ew.w[l];
+        }
+        q.act_elems = std::max<size_t>(acc, (size_t)2 * HW * q.maxw);
+        q.dlt_elems = (size_t)q.P * q.maxw;
+    } else {
+        q.act_elems = (size_t)std::max<long long>(8LL * q.P, 2LL * HW) * kWidth;
+        q.dlt_elems = (size_t)q.P * kWidth;
+    }
     q.o_act = o;
     o += align_up(es * q.act_elems);
     q.o_mbits = o;      // BF16: ReLU bit masks of stashed layers 0..6, 8 bytes per pixel
-    if (q.bf) o += align_up((size_t)(kLayers - 1) * q.P * 8);
+    if (q.bf && !q.gen) o += align_up((size_t)(kLayers - 1) * q.P * 8);
     q.o_dlt = o;
     o += 2 * align_up(es * q.dlt_elems);
     q.o_part = o;
@@ -326,6 +392,7 @@ struct n2f_run {
         uint16_t *fwd16, *bwd16;
         double* trace;
         float *S, *yb, *y;
+        char* base;   // the network's workspace block (generic packed operands)
     } net[3];
     char* act;
     char* mbits;       // BF16 ReLU bit masks of the stashed training layers
@@ -387,7 +454,91 @@ void pair_io(n2f_run* r, int pair, const float** in, const float** tgt, int* h, 
     }
 }
 
+// Packed convolution operands of network k from its parameters (after
+// creation, state loads and every Adam step).
+hipError_t pack_net(n2f_run* r, int k, hipStream_t s, const DevState* st = nullptr) {
+    const Plan& pl = r->pl;
+    n2f_run::Net& N = r->net[k];
+    if (!pl.gen) return launch_pack(N.theta, pl.pt, N.fwd, N.bwd, N.fwd16, N.bwd16, s);
+    for (int l = 0; l < kLayers; ++l) {
+        const bool wf = !pl.bf || l == 0;   // FP32 weights: the FP32 path and every first layer
+        hipError_t e = launch_gpack(N.theta, pl.pt.off[l], pl.pt.cin[l], pl.pt.cout[l], pl.cipad[l],
+                                    N.base + pl.g_fwd[l], l > 0 ? N.base + pl.g_bwd[l] : nullptr, wf, st, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// One training step of a network of other widths than 64 (generic kernels):
+// the same sequence as the 64-wide step, layer by layer.
+n2f_status enqueue_train_step_generic(n2f_run* r, int k, int pair) {
+    const Plan& pl = r->pl;
+    n2f_run::Net& N = r->net[k];
+    const float *in, *tgt;
+    int h, w;
+    pair_io(r, pair, &in, &tgt, &h, &w);
+    const long long npix = (long long)h * w;
+    const int bf = pl.bf;
+    const ParamTable& pt = pl.pt;
+    hipStream_t s = r->stream;
+    const size_t es = bf ? 2 : 4;
+    auto act = [&](int l) -> void* { return r->act + es * pl.g_act[l]; };   // stash: a_{l+1}
+    auto Bl = [&](int l) { return N.theta + pt.off[l] + kTaps * pt.cin[l] * pt.cout[l]; };
+    auto fwdpk = [&](int l) -> const void* { return N.base + pl.g_fwd[l]; };
+    auto bwdpk = [&](int l) -> const void* { return N.base + pl.g_bwd[l]; };
+    N2F_HIP(launch_gconv(in, pl.C, true, fwdpk(0), true, pl.cipad[0], Bl(0), nullptr, act(0), pt.cout[0], 0, bf, h,
+                         w, N.st, s));
+    for (int l = 1; l < kLayers; ++l)
+        N2F_HIP(launch_gconv(act(l - 1), pt.cin[l], false, fwdpk(l), !bf, pl.cipad[l], Bl(l), nullptr, act(l),
+                             pt.cout[l], 0, bf, h, w, N.st, s));
+    const float* w9 = N.theta + pt.off[kLayers];
+    N2F_HIP(launch_ghead(act(kLayers - 1), pt.cin[kLayers], tgt, pl.C, k, w9, r->dlt[0], nullptr,
+                         r->part + pt.poff[kLayers], r->lpart, pt.split[kLayers], 1, bf, npix, N.st, s));
+    int cur = 0;
+    for (int l = kLayers - 1; l >= 1; --l) {
+        N2F_HIP(launch_gwgrad(act(l - 1), pt.cin[l], false, r->dlt[cur], pt.cout[l], r->part + pt.poff[l],
+                              pt.split[l], bf, h, w, N.st, s));
+        N2F_HIP(launch_gconv(r->dlt[cur], pt.cout[l], false, bwdpk(l), !bf, pt.cout[l], nullptr, act(l - 1),
+                             r->dlt[1 - cur], pt.cin[l], 1, bf, h, w, N.st, s));
+        cur = 1 - cur;
+    }
+    N2F_HIP(launch_gwgrad(in, pl.C, true, r->dlt[cur], pt.cout[0], r->part + pt.poff[0], pt.split[0], bf, h, w,
+                          N.st, s));
+    N2F_HIP(launch_gadam(N.theta, N.m, N.v, N.g, r->part, pt, r->cfg.lr, r->cfg.beta1, r->cfg.beta2, r->cfg.eps,
+                         r->lpart, pt.split[kLayers], npix, N.st, s));
+    N2F_HIP(pack_net(r, k, s, N.st));
+    return N2F_OK;
+}
+
+// Validation of a network of other widths than 64: full-image forward through
+// two ping-pong buffers, the head with the squared-error partials, then the
+// stopping decision and the running output sum.
+n2f_status enqueue_validate_generic(n2f_run* r, int k) {
+    const Plan& pl = r->pl;
+    n2f_run::Net& N = r->net[k];
+    const ParamTable& pt = pl.pt;
+    const int bf = pl.bf;
+    const long long HW = (long long)pl.H * pl.W;
+    hipStream_t s = r->stream;
+    const size_t es = bf ? 2 : 4;
+    auto vbuf = [&](int b) -> void* { return r->act + es * (size_t)b * HW * pl.maxw; };
+    auto Bl = [&](int l) { return N.theta + pt.off[l] + kTaps * pt.cin[l] * pt.cout[l]; };
+    auto fwdpk = [&](int l) -> const void* { return N.base + pl.g_fwd[l]; };
+    N2F_HIP(launch_gconv(r->xs, pl.C, true, fwdpk(0), true, pl.cipad[0], Bl(0), nullptr, vbuf(0), pt.cout[0], 0, bf,
+                         pl.H, pl.W, N.st, s));
+    for (int l = 1; l < kLayers; ++l)
+        N2F_HIP(launch_gconv(vbuf((l - 1) & 1), pt.cin[l], false, fwdpk(l), !bf, pl.cipad[l], Bl(l), nullptr,
+                             vbuf(l & 1), pt.cout[l], 0, bf, pl.H, pl.W, N.st, s));
+    const float* w9 = N.theta + pt.off[kLayers];
+    N2F_HIP(launch_ghead(vbuf((kLayers - 1) & 1), pt.cin[kLayers], r->xs, pl.C, k, w9, nullptr, N.y, nullptr, r->vpart,
+                         pl.vblk, 0, bf, HW, N.st, s));
+    N2F_HIP(launch_decide(r->vpart, pl.vblk, HW, N.st, N.trace, s));
+    N2F_HIP(launch_accumulate(N.y, N.S, N.yb, HW, N.st, s));
+    return N2F_OK;
+}
+
 n2f_status enqueue_train_step(n2f_run* r, int k, int pair) {
+    if (r->pl.gen) return enqueue_train_step_generic(r, k, pair);
     const Plan& pl = r->pl;
     n2f_run::Net& N = r->net[k];
     const float *in, *tgt;
@@ -463,6 +614,7 @@ n2f_status enqueue_train_step(n2f_run* r, int k, int pair) {
 }
 
 n2f_status enqueue_validate(n2f_run* r, int k) {
+    if (r->pl.gen) return enqueue_validate_generic(r, k);
     const Plan& pl = r->pl;
     n2f_run::Net& N = r->net[k];
     const ParamTable& pt = pl.pt;
@@ -585,7 +737,7 @@ n2f_status n2f_param_count(int C, const n2f_config* cfg, size_t* count) {
     n2f_status s = check_cfg(cfg);
     if (s != N2F_OK) return s;
     if (C < 1 || C > 3 || !count) return fail(N2F_EINVAL, "need 1 <= C <= 3 and a non-NULL count");
-    *count = (size_t)make_table(C, 1, 1, 1).total;
+    *count = (size_t)make_table(C, eff_widths(cfg), 1, 1, 1).total;
     return N2F_OK;
 }
 
@@ -594,7 +746,7 @@ n2f_status n2f_init_params(int C, const n2f_config* cfg, unsigned long long seed
     n2f_status s = n2f_param_count(C, cfg, &np);
     if (s != N2F_OK) return s;
     if (!theta) return fail(N2F_EINVAL, "theta is NULL");
-    const auto L = canon_layers(C);
+    const auto L = canon_layers(C, eff_widths(cfg));
     for (int k = 0; k < C; ++k) {
         size_t i = 0;
         for (const CanonLayer& cl : L) {
@@ -670,6 +822,7 @@ n2f_status n2f_run_create(n2f_run** out, const float* d_in, int H, int W, int C,
         N.S = at<float>(nb, pl.s_S);
         N.yb = at<float>(nb, pl.s_yb);
         N.y = at<float>(nb, pl.s_y);
+        N.base = nb;
         r->host_done[k] = false;
         r->host_epochs[k] = 0;
     }
@@ -719,7 +872,7 @@ n2f_status n2f_run_create(n2f_run** out, const float* d_in, int H, int W, int C,
     n2f_init_params(C, cfg, cfg->init_seed, th0.data());
     for (int k = 0; k < C; ++k) {
         n2f_run::Net& N = r->net[k];
-        canon_to_internal(th0.data() + (size_t)k * pl.pt.total, internal.data(), C, pl.pt);
+        canon_to_internal(th0.data() + (size_t)k * pl.pt.total, internal.data(), pl.pt);
         if (hipMemcpyAsync(N.theta, internal.data(), sizeof(float) * pl.pt.total, hipMemcpyHostToDevice, sm) !=
                 hipSuccess ||
             hipMemsetAsync(N.m, 0, sizeof(float) * pl.pt.total, sm) != hipSuccess ||
@@ -729,7 +882,7 @@ n2f_status n2f_run_create(n2f_run** out, const float* d_in, int H, int W, int C,
             hipMemsetAsync(N.yb, 0, sizeof(float) * H * W, sm) != hipSuccess ||
             hipMemsetAsync(N.y, 0, sizeof(float) * H * W, sm) != hipSuccess ||
             launch_init_state(N.st, cfg->patience, cfg->max_epochs, cfg->fixed_epochs, sm) != hipSuccess ||
-            launch_pack(N.theta, pl.pt, N.fwd, N.bwd, N.fwd16, N.bwd16, sm) != hipSuccess ||
+            pack_net(r, k, sm) != hipSuccess ||
             hipStreamSynchronize(sm) != hipSuccess)  // host buffer must outlive the copy
             return bail(fail(N2F_EDEVICE, "initialising network state failed"));
     }
@@ -948,7 +1101,7 @@ n2f_status n2f_get_state(n2f_run* r, int net, float* theta, float* m, float* v, 
         if (!dsts[i]) continue;
         N2F_HIP(hipMemcpyAsync(tmp.data(), srcs[i], sizeof(float) * pt.total, hipMemcpyDeviceToHost, r->stream));
         N2F_HIP(hipStreamSynchronize(r->stream));
-        internal_to_canon(tmp.data(), dsts[i], r->pl.C, pt);
+        internal_to_canon(tmp.data(), dsts[i], pt);
     }
     if (t) {
         DevState st;
@@ -970,14 +1123,14 @@ n2f_status n2f_set_state(n2f_run* r, int net, const float* theta, const float* m
     float* dsts[3] = {N.theta, N.m, N.v};
     for (int i = 0; i < 3; ++i) {
         if (srcs[i]) {
-            canon_to_internal(srcs[i], tmp.data(), r->pl.C, pt);
+            canon_to_internal(srcs[i], tmp.data(), pt);
             N2F_HIP(hipMemcpyAsync(dsts[i], tmp.data(), sizeof(float) * pt.total, hipMemcpyHostToDevice, r->stream));
             N2F_HIP(hipStreamSynchronize(r->stream));
         } else {
             N2F_HIP(hipMemsetAsync(dsts[i], 0, sizeof(float) * pt.total, r->stream));
         }
     }
-    N2F_HIP(launch_pack(N.theta, pt, N.fwd, N.bwd, N.fwd16, N.bwd16, r->stream));
+    N2F_HIP(pack_net(r, net, r->stream));
     DevState st;
     s = read_state(r, net, &st);
     if (s != N2F_OK) return s;
@@ -997,9 +1150,10 @@ namespace {
 struct CkptHeader {
     unsigned long long magic;
     int H, W, C, precision, downsample, exact, max_trace, reserved;
+    int widths[kLayers];
     unsigned long long net_bytes;
 };
-constexpr unsigned long long kCkptMagic = 0x31544b4350463248ULL;   // "H2FPCKT1"
+constexpr unsigned long long kCkptMagic = 0x32544b4350463248ULL;   // "H2FPCKT2"
 
 CkptHeader ckpt_header(const n2f_run* r) {
     CkptHeader h{};
@@ -1011,6 +1165,7 @@ CkptHeader ckpt_header(const n2f_run* r) {
     h.downsample = r->pl.quad;
     h.exact = r->pl.exact;
     h.max_trace = r->pl.max_trace;
+    for (int l = 0; l < kLayers; ++l) h.widths[l] = r->pl.ew.w[l];
     h.net_bytes = r->pl.net_bytes;
     return h;
 }
@@ -1047,7 +1202,7 @@ n2f_status n2f_load_checkpoint(n2f_run* r, int net, const void* buf, size_t byte
     if (h.magic != kCkptMagic) return fail(N2F_EINVAL, "not a checkpoint");
     if (h.H != mine.H || h.W != mine.W || h.C != mine.C || h.precision != mine.precision ||
         h.downsample != mine.downsample || h.exact != mine.exact || h.max_trace != mine.max_trace ||
-        h.net_bytes != mine.net_bytes)
+        std::memcmp(h.widths, mine.widths, sizeof(h.widths)) != 0 || h.net_bytes != mine.net_bytes)
         return fail(N2F_EINVAL, "checkpoint of a different image size or configuration");
     if (bytes < sizeof(h) + h.net_bytes) return fail(N2F_EINVAL, "checkpoint buffer too small");
     N2F_HIP(hipMemcpyAsync(r->ws + r->pl.o_net[net], static_cast<const char*>(buf) + sizeof(h), r->pl.net_bytes,
@@ -1069,7 +1224,7 @@ n2f_status n2f_get_grad(n2f_run* r, int net, float* g, double* loss) {
         std::vector<float> tmp(pt.total);
         N2F_HIP(hipMemcpyAsync(tmp.data(), r->net[net].g, sizeof(float) * pt.total, hipMemcpyDeviceToHost, r->stream));
         N2F_HIP(hipStreamSynchronize(r->stream));
-        internal_to_canon(tmp.data(), g, r->pl.C, pt);
+        internal_to_canon(tmp.data(), g, pt);
     }
     if (loss) {
         DevState st;
@@ -1085,10 +1240,11 @@ n2f_status n2f_debug_adam(n2f_run* r, int net, const float* g) {
     if (s != N2F_OK) return s;
     if (!g) return fail(N2F_EINVAL, "gradient is NULL");
     if (r->host_done[net]) return fail(N2F_ESTATE, "network already finished");
+    if (r->pl.gen) return fail(N2F_EINVAL, "injected-gradient Adam steps are for the 64-wide network only");
     const ParamTable& pt = r->pl.pt;
     n2f_run::Net& N = r->net[net];
     std::vector<float> tmp(pt.total);
-    canon_to_internal(g, tmp.data(), r->pl.C, pt);
+    canon_to_internal(g, tmp.data(), pt);
     // stage the injected gradient in the partial-sum buffer (unused between steps)
     N2F_HIP(hipMemcpyAsync(r->part, tmp.data(), sizeof(float) * pt.total, hipMemcpyHostToDevice, r->stream));
     N2F_HIP(launch_adam(N.theta, N.m, N.v, N.g, r->part, r->part, pt, r->cfg.lr, r->cfg.beta1,
@@ -1219,6 +1375,7 @@ n2f_status record_epoch(n2f_run* r, int net, std::vector<LaunchRec>* out) {
     n2f_status s = check_run(r, net);
     if (s != N2F_OK) return s;
     if (!r->pl.bf) return fail(N2F_EINVAL, "grouped launches need BF16 runs");
+    if (r->pl.gen) return fail(N2F_EINVAL, "grouped launches need the 64-wide network");
     s = check_targets(r);
     if (s != N2F_OK) return s;
     Recorder rec;

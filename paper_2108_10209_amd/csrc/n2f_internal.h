@@ -50,6 +50,7 @@ struct ParamTable {
     int off[kLayers + 1];     // offset of layer l (0-based, 8 = head) in theta
     int n[kLayers + 1];       // floats of layer l
     int cin[kLayers + 1];     // input channels of layer l
+    int cout[kLayers + 1];    // output channels of layer l (1 for the head)
     int split[kLayers + 1];   // number of partial copies of layer l
     long long poff[kLayers + 1];  // offset of layer l's partials in the partial buffer
     int total;                // parameters of one network
@@ -298,6 +299,27 @@ class Group {
     hipGraphExec_t exec_ = nullptr;
     int exec_grid_[KK_COUNT] = {};
 };
+
+// Networks of other widths than 64 (n2f_generic.hip): generic 3x3
+// convolution (mode 0 forward + bias + ReLU, mode 1 data gradient masked by
+// [act > 0]) from a packed operand, weight-gradient partials (nsplit copies of
+// 9 CI CO + CO floats), the heads (train: d8, head partial rows of CI + 1 and
+// loss partials; validation: y and squared-error partials), Adam from the
+// partials, and the packed operands of one layer.  in_fp32 / w_fp32 mark the
+// first layer of a BF16 run (FP32 image and weights).
+hipError_t launch_gconv(const void* in, int CI, bool in_fp32, const void* wp, bool w_fp32, int CIpad,
+                        const float* bias, const void* act, void* out, int CO, int mode, int bf16, int h, int w,
+                        const DevState* st, hipStream_t s);
+hipError_t launch_gwgrad(const void* src, int CI, bool src_fp32, const void* dlt, int CO, float* part, int nsplit,
+                         int bf16, int h, int w, const DevState* st, hipStream_t s);
+hipError_t launch_ghead(const void* a8, int CI, const float* tgt, int C, int k, const float* w9, void* d8, float* y,
+                        float* part, double* lpart, int nblk, int train, int bf16, long long npix, DevState* st,
+                        hipStream_t s);
+hipError_t launch_gadam(float* theta, float* m, float* v, float* g, const float* part, const ParamTable& pt, float lr,
+                        double beta1, double beta2, float eps, const double* lpart, int nloss, long long loss_npix,
+                        DevState* st, hipStream_t s);
+hipError_t launch_gpack(const float* theta, int off, int cin, int cout, int CIpad, void* fwd, void* bwd, bool w_fp32,
+                        const DevState* st, hipStream_t s);
 
 // Message returned by n2f_last_error() on the calling thread.
 void set_last_error(const char* msg);

@@ -30,11 +30,13 @@ SYMBOLS = [
     "n2f_server_submit", "n2f_server_step", "n2f_server_poll", "n2f_server_memory", "n2f_server_destroy",
     "n2f_run_set_clean", "n2f_max_project", "n2f_batch_run_of", "n2f_checkpoint_bytes", "n2f_save_checkpoint",
     "n2f_load_checkpoint", "n2f_batch_add", "n2f_batch_remove", "n2f_server_cancel", "n2f_denoise_noalloc",
+    "n2f_server_table_bytes",
 ]
 NOALLOC_MAX_BYTES = 128 << 20   # N2F_NOALLOC_MAX_BYTES
 SERVER_SIMULATE = 1
 SERVER_GROUPED = 2
 K_CONV_FWD, K_BACKWARD, K_ADAM = 0, 1, 2
+LITERAL_WIDTHS = (32, 32, 64, 64, 128, 128, 256, 256)   # the Methods' per-layer widths
 K_GROUP = 16                # + kind: one grouped launch (see n2f.h)
 GROUP_KINDS = ["conv3x3_fwd", "conv3x3_dgrad", "conv3x3_fwd_head", "conv3x3_fwd_val", "conv3x3_fwd_first",
                "conv3x3_wgrad", "conv1_c1", "conv1_c2", "conv1_c3", "wgrad1_c1", "wgrad1_c2", "wgrad1_c3", "adam",
@@ -54,7 +56,7 @@ class Config(ctypes.Structure):
         ("lr", c_float), ("eps", c_float), ("beta1", c_double), ("beta2", c_double),
         ("patience", c_int), ("max_epochs", c_int), ("fixed_epochs", c_int),
         ("pair_order", c_int * 4), ("precision", c_int), ("init_seed", c_ulonglong),
-        ("use_graph", c_int), ("downsample", c_int), ("exact_targets", c_int),
+        ("use_graph", c_int), ("downsample", c_int), ("exact_targets", c_int), ("widths", c_int * 8),
     ]
 
 
@@ -143,6 +145,8 @@ def default_config(**kw) -> Config:
     for k, v in kw.items():
         if k == "pair_order":
             cfg.pair_order = (c_int * 4)(*v)
+        elif k == "widths":
+            cfg.widths = (c_int * 8)(*v)
         else:
             setattr(cfg, k, v)
     return cfg

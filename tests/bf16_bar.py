@@ -30,9 +30,9 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def split(vec, C):
+def split(vec, C, width=O.WIDTH):
     out, o = {}, 0
-    for name, shape in O.param_spec(C):
+    for name, shape in O.param_spec(C, width):
         n = int(np.prod(shape))
         out[name] = np.asarray(vec[o:o + n])
         o += n
@@ -46,12 +46,12 @@ def bf16_round(a):
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def bf16_emulated_gradient(theta, C, inp, tgt):
+def bf16_emulated_gradient(theta, C, inp, tgt, width=O.WIDTH):
     """Flat gradient with the BF16 path's rounding points applied to the
     oracle's FP64 layer functions (first-layer weights, biases, the head and
     all sums stay unrounded)."""
     L = O.N_LAYERS
-    prm = O.unflatten(theta, C)
+    prm = O.unflatten(theta, C, width)
     for l in range(2, L + 1):
         prm[f"W{l}"] = bf16_round(prm[f"W{l}"])
     acts = [np.asarray(inp, np.float64)]
@@ -68,7 +68,7 @@ def bf16_emulated_gradient(theta, C, inp, tgt):
         g[f"W{l}"], g[f"b{l}"] = dW, db
         if l > 1:
             delta = bf16_round(da * (acts[l - 1] > 0))
-    return O.flatten(g, C)
+    return O.flatten(g, C, width)
 
 
 def bf16_check(g, theta, C, inp, tgt, h=O.Hyper()):
@@ -76,8 +76,8 @@ def bf16_check(g, theta, C, inp, tgt, h=O.Hyper()):
     state theta on one pair.  Returns (ok, rows) with rows[name] = (error vs
     exact, rounding sensitivity, error vs the rounding model, criterion)."""
     _, g_or, _ = O.gradients(theta, C, inp, tgt, h)
-    g_em = bf16_emulated_gradient(theta, C, inp, tgt)
-    gg, go, ge = split(g, C), split(g_or, C), split(g_em, C)
+    g_em = bf16_emulated_gradient(theta, C, inp, tgt, h.width)
+    gg, go, ge = split(g, C, h.width), split(g_or, C, h.width), split(g_em, C, h.width)
     rows, ok = {}, True
     for nm in gg:
         e_exact, sens, e_model = rel(gg[nm], go[nm]), rel(ge[nm], go[nm]), rel(gg[nm], ge[nm])

@@ -30,7 +30,10 @@ static int config_checks() {
     c.n_layers = 7;
     CHECK(n2f_workspace_bytes(64, 64, 1, &c, &b) == N2F_EINVAL);
     c = d;
-    c.width = 32;
+    c.width = 40;
+    CHECK(n2f_workspace_bytes(64, 64, 1, &c, &b) == N2F_EINVAL);
+    c = d;
+    c.widths[0] = 32;   // the other seven stay zero
     CHECK(n2f_workspace_bytes(64, 64, 1, &c, &b) == N2F_EINVAL);
     c = d;
     c.lr = 0.f;
@@ -60,22 +63,27 @@ static int plan_checks() {
     n2f_config d;
     n2f_config_default(&d);
     const int sides[] = {2, 3, 4, 5, 16, 17, 31, 64, 100, 255, 256, 511, 512, 1023, 2048, 4096};
+    const int literal[8] = {32, 32, 64, 64, 128, 128, 256, 256};
+    for (int lit = 0; lit < 2; ++lit)
     for (int prec = 0; prec < 2; ++prec)
         for (int ds = 0; ds < 2; ++ds)
             for (int ex = 0; ex < 2; ++ex)
                 for (int C = 1; C <= 3; ++C)
                     for (int H : sides)
                         for (int W : sides) {
+                            if (lit && (H > 1024 || W > 1024)) continue;
                             n2f_config c = d;
                             c.precision = prec;
                             c.downsample = ds;
                             c.exact_targets = ex;
+                            if (lit)
+                                for (int l = 0; l < 8; ++l) c.widths[l] = literal[l];
                             size_t b = 0, b2 = 0;
                             CHECK(n2f_workspace_bytes(H, W, C, &c, &b) == N2F_OK);
                             CHECK(b % 256 == 0);
                             // at least the stashed activations of the training image
                             const size_t P = ds ? (size_t)(H / 2) * (W / 2) : (size_t)(H & ~1) * (W & ~1) / 2;
-                            CHECK(b >= P * 64 * 8 * (prec ? 2 : 4));
+                            CHECK(b >= P * (lit ? 992 : 64 * 8) * (prec ? 2 : 4));
                             if (ex) {
                                 c.exact_targets = 0;
                                 CHECK(n2f_workspace_bytes(H, W, C, &c, &b2) == N2F_OK && b2 < b);

@@ -67,7 +67,7 @@ def test_workspace_bytes_scales_and_rejects():
 
 
 def test_config_validation():
-    for kw in [dict(n_layers=7), dict(width=32), dict(lr=0.0), dict(beta1=1.0), dict(patience=0),
+    for kw in [dict(n_layers=7), dict(width=40), dict(width=512), dict(lr=0.0), dict(beta1=1.0), dict(patience=0),
                dict(max_epochs=0), dict(pair_order=(0, 0, 1, 2)), dict(precision=7), dict(downsample=2),
                dict(exact_targets=2)]:
         with pytest.raises(n2f.N2FError) as e:
@@ -137,3 +137,25 @@ def test_noalloc_rejects_before_touching_the_device():
     assert L.n2f_denoise_noalloc(fake, fake, 1024, 1024, 1, ctypes.byref(cfg), None) == n2f.ENOMEM
     assert b"fixed device array" in L.n2f_last_error()
     assert n2f.workspace_bytes(256, 256, 1, cfg) <= n2f.NOALLOC_MAX_BYTES
+
+
+@pytest.mark.parametrize("C", [1, 3])
+def test_literal_widths_parameters(C):
+    """Per-layer widths (the Methods' 32, ..., 256): the library's parameter
+    count and initial weights equal the generator's for that net, and its
+    workspace grows accordingly."""
+    cfg = n2f.default_config(widths=n2f.LITERAL_WIDTHS)
+    assert n2f.param_count(C, cfg) == synth.n_params(C, synth.LITERAL_WIDTHS)
+    a = n2f.init_params(C, 11, cfg)
+    b = synth.init_params(C, 11, synth.LITERAL_WIDTHS)
+    np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert n2f.workspace_bytes(64, 64, C, cfg) > n2f.workspace_bytes(64, 64, C)
+
+
+def test_widths_are_checked():
+    for bad in [(32, 32, 64, 64, 128, 128, 256, 512), (24,) * 8, (32, 32, 64, 64, 128, 128, 256, 0)]:
+        cfg = n2f.default_config(widths=bad)
+        with pytest.raises(n2f.N2FError) as e:
+            n2f.workspace_bytes(64, 64, 1, cfg)
+        assert e.value.code == n2f.EINVAL
+    assert n2f.param_count(1, n2f.default_config(width=32)) == synth.n_params(1, 32)

@@ -15,7 +15,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2108_10209_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["n2f_kernels.hip", "n2f_conv.hip", "n2f_api.cpp", "n2f_sched.cpp", "n2f_noalloc.hip"]
+SOURCES = ["n2f_kernels.hip", "n2f_conv.hip", "n2f_api.cpp", "n2f_sched.cpp", "n2f_noalloc.hip", "n2f_generic.hip"]
 # sanitizers for the host side of each translation unit only
 HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
