@@ -120,6 +120,25 @@ def oracle_sec_per_mpx_epoch(noisy, min_seconds: float = 8.0):
     return sec / (epochs * noisy.shape[1] * noisy.shape[2] / 1e6), sec, epochs
 
 
+def launch_geometry(args, xs, n2f):
+    """Grouped launch geometry for the timed batch (never changes results)."""
+    import torch
+    from paper_2108_10209_amd import autotune, synth
+    src = args.tuning
+    entry = None
+    if src == "tune":
+        t0 = time.perf_counter()
+        pairs = synth.batch_images(len(xs), 256, 1024, seed=11)   # other images than the timed ones
+        entry = autotune.tune([torch.from_numpy(x).to(xs[0].device) for _, x in pairs])
+        print(f"tuned in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    elif src != "none":
+        npix = sum(int(x.shape[-2]) * int(x.shape[-1]) for x in xs) / len(xs)
+        entry = autotune.apply(npix, autotune.TABLE if src == "auto" else src)
+    grids = {name: n2f.group_grid(k) for k, name in enumerate(n2f.GROUP_KINDS)}
+    return {"source": src if entry is not None else "built-in", "group_grid": grids,
+            "tuning_bucket": entry["bucket"] if entry else None}
+
+
 def bench_c3(args):
     """64 independent grayscale images, sides uniform in [256, 1024],
     Poisson (peak 30) + Gaussian (10/255) noise, trained together to their
@@ -139,6 +158,7 @@ def bench_c3(args):
     streams = args.streams if prec == n2f.BF16 else max(args.streams, 1)
     cfg = n2f.default_config(precision=prec, max_epochs=args.max_epochs)
     print(f"batch of {len(xs)} images, {npx / 1e6:.1f} Mpx, streams {streams}", file=sys.stderr, flush=True)
+    geometry = launch_geometry(args, xs, n2f)
 
     def step():
         b = n2f.Batch(xs, cfg, n_streams=streams)
@@ -197,6 +217,7 @@ def bench_c3(args):
         "psnr_mean": round(float(np.mean(ps)), 3),
         "noisy_psnr_mean": round(float(np.mean([synth.psnr(x, c) for (c, x) in pairs])), 3),
         "kernels": kern,
+        "launch_geometry": geometry,
     }
     if dom is not None:
         k = kern[n2f.GROUP_KINDS[dom]]
@@ -680,6 +701,9 @@ def main():
     ap.add_argument("--large-size", type=int, default=2048)
     ap.add_argument("--large-seeds", type=int, default=3)
     ap.add_argument("--batch-n", type=int, default=64)
+    ap.add_argument("--tuning", default="auto",
+                    help="batch: grouped launch geometry: 'auto' (the package's tuning table, when it has an entry "
+                         "for this device), 'none' (built-in grids), 'tune' (tune on other images first), or a path")
     ap.add_argument("--streams", type=int, default=-1, help="batch: -1 grouped launches, >= 1 streams, 0 in turn")
     ap.add_argument("--fp32-sample", type=int, default=8)
     ap.add_argument("--serve-n", type=int, default=500)

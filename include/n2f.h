@@ -441,6 +441,19 @@ n2f_status n2f_profile_begin(int every);
 n2f_status n2f_profile_read(int kernel_class, double* total_ms, long long* launches, long long* pixels);
 n2f_status n2f_profile_end(void);
 
+/* Launch geometry of grouped launches (tuning; no paper passage: how many
+ * hardware blocks one grouped launch of a kind uses to walk the virtual
+ * blocks of its images).  `kind` is a grouped kind 0..14 as listed above;
+ * `grid` is 1..N2F_MAX_GROUP_GRID.  The geometry never changes results: each
+ * virtual block computes the same values whichever hardware block runs it.
+ * A change takes effect at the next epoch of every group (their captured
+ * launches are recorded again).  Process-wide; not thread-safe with running
+ * groups.  N2F_EINVAL for a kind or grid out of range. */
+#define N2F_GROUP_KINDS 15
+#define N2F_MAX_GROUP_GRID 1024
+n2f_status n2f_group_grid_get(int kind, int* grid);
+n2f_status n2f_group_grid_set(int kind, int grid);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1576,3 +1576,20 @@ n2f_status Group::launch(int epochs) {
 }
 
 }  // namespace n2f
+
+extern "C" {
+
+n2f_status n2f_group_grid_get(int kind, int* grid) {
+    if (kind < 0 || kind >= KK_COUNT || !grid) return fail(N2F_EINVAL, "grouped kind out of range or grid is NULL");
+    *grid = group_grid(kind);
+    return N2F_OK;
+}
+
+n2f_status n2f_group_grid_set(int kind, int grid) {
+    if (kind < 0 || kind >= KK_COUNT) return fail(N2F_EINVAL, "grouped kind out of range");
+    if (grid < 1 || grid > kMaxGroupGrid) return fail(N2F_EINVAL, "grid must be in 1.." + std::to_string(kMaxGroupGrid));
+    set_group_grid(kind, grid);
+    return N2F_OK;
+}
+
+}  // extern "C"

@@ -182,6 +182,7 @@ enum KernelKind : int {
     KK_ACCUM,          // k_accumulate
     KK_COUNT
 };
+static_assert(KK_COUNT == N2F_GROUP_KINDS, "grouped kinds of the header");
 constexpr int kArgStride = 512;   // bytes per run of a grouped launch's argument table
 
 struct LaunchRec {
@@ -202,7 +203,7 @@ hipError_t record_launch(int kind, const void* args, size_t bytes, int grid, lon
 // virtual block counts), args = n argument blocks of kArgStride bytes,
 // starts = the first virtual block of each block of a launch whose blocks
 // take consecutive ranges (grid + 1 entries, balanced by cost).
-constexpr int kMaxGroupGrid = 1024;
+constexpr int kMaxGroupGrid = N2F_MAX_GROUP_GRID;
 struct GroupView {
     const unsigned char* args;
     const int* prefix;

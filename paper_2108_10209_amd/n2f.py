@@ -30,7 +30,7 @@ SYMBOLS = [
     "n2f_server_submit", "n2f_server_step", "n2f_server_poll", "n2f_server_memory", "n2f_server_destroy",
     "n2f_run_set_clean", "n2f_max_project", "n2f_batch_run_of", "n2f_checkpoint_bytes", "n2f_save_checkpoint",
     "n2f_load_checkpoint", "n2f_batch_add", "n2f_batch_remove", "n2f_server_cancel", "n2f_denoise_noalloc",
-    "n2f_server_table_bytes",
+    "n2f_server_table_bytes", "n2f_group_grid_get", "n2f_group_grid_set",
 ]
 NOALLOC_MAX_BYTES = 128 << 20   # N2F_NOALLOC_MAX_BYTES
 SERVER_SIMULATE = 1
@@ -124,6 +124,8 @@ def lib():
             "n2f_checkpoint_bytes": [c_void_p, POINTER(c_size_t)],
             "n2f_save_checkpoint": [c_void_p, c_int, c_void_p, c_size_t],
             "n2f_load_checkpoint": [c_void_p, c_int, c_void_p, c_size_t],
+            "n2f_group_grid_get": [c_int, POINTER(c_int)],
+            "n2f_group_grid_set": [c_int, c_int],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -390,6 +392,21 @@ def profile_read(kernel_class: int):
 
 def profile_end():
     _check(lib().n2f_profile_end())
+
+
+MAX_GROUP_GRID = 1024       # N2F_MAX_GROUP_GRID
+
+
+def group_grid(kind: int) -> int:
+    """Hardware blocks of one grouped launch of `kind` (see n2f.h)."""
+    g = c_int()
+    _check(lib().n2f_group_grid_get(kind, byref(g)))
+    return g.value
+
+
+def set_group_grid(kind: int, grid: int):
+    """Set the launch geometry of grouped kind `kind`; results do not change."""
+    _check(lib().n2f_group_grid_set(kind, grid))
 
 
 def _ints(v):

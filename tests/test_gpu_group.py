@@ -163,3 +163,36 @@ def test_grouped_server_results_equal_alone():
     for i, x in enumerate(imgs):
         assert torch.equal(outs[i], _alone(x, cfg)[0]), i
     srv.close()
+
+
+def test_launch_geometry_never_changes_results():
+    """Other grids for the grouped kinds (fewer and more hardware blocks than
+    virtual blocks) give the same bits; the tuner's entry covers every kind
+    it timed and leaves valid grids."""
+    say("group grids")
+    imgs = _images([(1, 96, 80), (3, 40, 44), (1, 300, 170), (1, 50, 66)], seed=70)
+    cfg = n2f.default_config(precision=n2f.BF16, fixed_epochs=3)
+    saved = [n2f.group_grid(k) for k in range(len(n2f.GROUP_KINDS))]
+    try:
+        ref = n2f.Batch([dev(x) for x in imgs], cfg, n_streams=n2f.BATCH_GROUPED)
+        assert ref.run() == 0
+        for grid in (1, 7, 1024):
+            for k in range(len(n2f.GROUP_KINDS)):
+                n2f.set_group_grid(k, grid)
+            b = n2f.Batch([dev(x) for x in imgs], cfg, n_streams=n2f.BATCH_GROUPED)
+            assert b.run() == 0
+            for i in range(len(imgs)):
+                assert torch.equal(b.result(i), ref.result(i)), (grid, i)
+            b.close()
+        ref.close()
+        for k, g in enumerate(saved):
+            n2f.set_group_grid(k, g)
+        from paper_2108_10209_amd import autotune
+        entry = autotune.tune([dev(x) for x in imgs[:2]], candidates=(64, 512), epochs=1, log=lambda *a: None)
+        assert "conv3x3_wgrad" in entry["group_grid"] and "adam" in entry["group_grid"]
+        for name, g in entry["group_grid"].items():
+            assert g in (64, 512, saved[n2f.GROUP_KINDS.index(name)])
+            assert n2f.group_grid(n2f.GROUP_KINDS.index(name)) == g
+    finally:
+        for k, g in enumerate(saved):
+            n2f.set_group_grid(k, g)
