@@ -287,7 +287,8 @@ n2f_status n2f_run_poll(n2f_run* run, int net, int* done, int* epochs);
 typedef struct n2f_batch n2f_batch;
 
 /* Workspace for a batch: the 256-byte aligned sum of the images' needs,
- * plus the launch tables of grouped mode (a few MB). */
+ * plus the launch tables of grouped mode (12 groups: 3 channel counts x up
+ * to 4 streams). */
 n2f_status n2f_batch_workspace_bytes(int n, const int* H, const int* W, const int* C, const n2f_config* cfg,
                                      size_t* bytes);
 
@@ -304,8 +305,12 @@ n2f_status n2f_batch_workspace_bytes(int n, const int* H, const int* W, const in
  * epoch is one grouped launch over all images of the same channel count,
  * whose blocks run each image's blocks exactly as its own launch would (the
  * same bits as the image alone), and one recorded graph per epoch replays
- * on `stream`; at most n + 64 images train at once (n2f_batch_add beyond
- * that returns N2F_ENOMEM).  Synchronises.  Constant images are finished at
+ * on `stream`; n_streams = -K, K = 2..4 (BF16 only): grouped launches on K
+ * streams the batch creates, the images split between them by work
+ * (pixels x channels, largest first), one group per channel count and
+ * stream, so launches of different kinds overlap across the streams (the
+ * same bits again).  At most n + 64 images train at once (n2f_batch_add
+ * beyond that returns N2F_ENOMEM).  Synchronises.  Constant images are finished at
  * once.  cfg->exact_targets is refused (N2F_EINVAL), here and by the
  * server. */
 #define N2F_BATCH_GROUPED (-1)

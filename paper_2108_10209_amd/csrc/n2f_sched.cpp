@@ -104,13 +104,16 @@ struct n2f_batch {
     std::vector<hipStream_t> streams;
     bool own_streams = true;   // false: the batch runs on the caller's stream alone
     hipStream_t caller = nullptr;
-    // grouped mode: one group per channel count, tables after the images
+    // grouped mode: one group per (channel count, batch stream), tables after
+    // the images; group of image i: groups[3 * stream_of[i] + C[i] - 1]
     bool grouped = false;
     int group_cap = 0;
     char* tables = nullptr;
-    std::unique_ptr<n2f::Group> groups[3];
+    std::vector<std::unique_ptr<n2f::Group>> groups;
+    n2f::Group* group_of(int i) { return groups[3 * stream_of[i] + C[i] - 1].get(); }
     ~n2f_batch() {
-        if (grouped && !streams.empty()) (void)hipStreamSynchronize(streams[0]);
+        if (grouped)
+            for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
         for (auto& g : groups) g.reset();
         for (n2f_run* r : runs)
             if (r) n2f_run_destroy(r);
@@ -134,19 +137,23 @@ n2f_status order_after(hipStream_t s, hipStream_t caller) {
 }
 
 constexpr int kGroupExtra = 64;   // images a grouped batch can take beyond its initial n
+constexpr int kMaxGroupStreams = 4;   // streams of a grouped batch (n_streams = -1 .. -4)
 
-size_t batch_table_bytes(int n) { return 3 * align_up(n2f::Group::table_bytes(n + kGroupExtra)); }
+size_t batch_table_bytes(int n) {
+    return (size_t)3 * kMaxGroupStreams * align_up(n2f::Group::table_bytes(n + kGroupExtra));
+}
 
-// Grouped mode: image i (created, not finished) joins its channel count's
-// group, created on first use.
+// Grouped mode: image i (created, not finished) joins the group of its
+// channel count on its stream, created on first use.
 n2f_status group_join(n2f_batch* b, int i) {
-    const int c = b->C[i] - 1;
-    if (!b->groups[c]) {
-        b->groups[c].reset(new (std::nothrow) n2f::Group(
-            b->group_cap, b->tables + c * align_up(n2f::Group::table_bytes(b->group_cap)), b->streams[0]));
-        if (!b->groups[c]) return sfail(N2F_ENOMEM, "host allocation failed");
+    const int gi = 3 * b->stream_of[i] + b->C[i] - 1;
+    if (!b->groups[gi]) {
+        b->groups[gi].reset(new (std::nothrow) n2f::Group(
+            b->group_cap, b->tables + gi * align_up(n2f::Group::table_bytes(b->group_cap)),
+            b->streams[b->stream_of[i]]));
+        if (!b->groups[gi]) return sfail(N2F_ENOMEM, "host allocation failed");
     }
-    return b->groups[c]->add(b->runs[i], b->net[i], i);
+    return b->groups[gi]->add(b->runs[i], b->net[i], i);
 }
 
 // Create the run of a new batch image on the least loaded stream (by work)
@@ -190,10 +197,11 @@ n2f_status batch_append(n2f_batch* b, const float* d_in, int H, int W, int C, vo
 
 namespace {
 
-// Grouped mode: every group replays whole epochs on the batch stream, then
-// the host reads each image's stopping rule; a finished network leaves its
-// group (or moves on to the image's next network), and the groups' tables
-// are rewritten before their next epoch.
+// Grouped mode: every group replays whole epochs on its stream (the groups
+// of different streams run concurrently), then the host reads each image's
+// stopping rule; a finished network leaves its group (or moves on to the
+// image's next network), and the groups' tables are rewritten before their
+// next epoch.
 n2f_status batch_run_grouped(n2f_batch* b, int max_now) {
     for (int ran = 0; ran < max_now;) {
         bool any = false;
@@ -208,7 +216,7 @@ n2f_status batch_run_grouped(n2f_batch* b, int max_now) {
         ran += k;
         for (int i = 0; i < b->n; ++i) {
             if (b->finished[i]) continue;
-            n2f::Group* g = b->groups[b->C[i] - 1].get();
+            n2f::Group* g = b->group_of(i);
             int done = 0, ep = 0;
             n2f_status st = n2f_run_poll(b->runs[i], b->net[i], &done, &ep);
             if (st == N2F_ENUMERIC) {
@@ -254,11 +262,11 @@ n2f_status n2f_batch_workspace_bytes(int n, const int* H, const int* W, const in
 n2f_status n2f_batch_create(n2f_batch** out, int n, const float* const* d_in, const int* H, const int* W,
                             const int* C, const n2f_config* cfg, void* d_ws, size_t ws_bytes, int n_streams,
                             hipStream_t stream) {
-    if (!out || !d_in || !d_ws || !cfg || n < 1 || n_streams < N2F_BATCH_GROUPED)
+    if (!out || !d_in || !d_ws || !cfg || n < 1 || n_streams < -kMaxGroupStreams)
         return sfail(N2F_EINVAL, "bad batch arguments");
     *out = nullptr;
     if (cfg->exact_targets) return sfail(N2F_EINVAL, "exact targets need a clean image per run: not in a batch");
-    if (n_streams == N2F_BATCH_GROUPED && cfg->precision != N2F_BF16)
+    if (n_streams <= N2F_BATCH_GROUPED && cfg->precision != N2F_BF16)
         return sfail(N2F_EINVAL, "grouped batches need BF16 (the FP32 path has no grouped kernels)");
     if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return sfail(N2F_EINVAL, "workspace must be 256-byte aligned");
     size_t need = 0;
@@ -269,12 +277,21 @@ n2f_status n2f_batch_create(n2f_batch** out, int n, const float* const* d_in, co
     if (!b) return sfail(N2F_ENOMEM, "host allocation failed");
     b->cfg = *cfg;
     b->caller = stream;
-    if (n_streams == N2F_BATCH_GROUPED) {
+    if (n_streams <= N2F_BATCH_GROUPED) {
         b->grouped = true;
         b->group_cap = n + kGroupExtra;
         b->tables = static_cast<char*>(d_ws) + (need - batch_table_bytes(n));
-        b->own_streams = false;
-        b->streams.push_back(stream);
+        b->groups.resize(3 * kMaxGroupStreams);
+        if (n_streams == N2F_BATCH_GROUPED) {   // the caller's stream
+            b->own_streams = false;
+            b->streams.push_back(stream);
+        } else {
+            s = make_streams(b->streams, -n_streams);
+            if (s != N2F_OK) {
+                delete b;
+                return s;
+            }
+        }
     } else if (n_streams == 0) {
         b->own_streams = false;
         b->streams.push_back(stream);
@@ -364,7 +381,7 @@ n2f_status n2f_batch_remove(n2f_batch* b, int i) {
     if (!b || i < 0 || i >= b->n) return sfail(N2F_EINVAL, "bad batch arguments");
     if (b->removed[i]) return sfail(N2F_ESTATE, "image " + std::to_string(i) + " already removed");
     if (hipStreamSynchronize(b->streams[b->stream_of[i]]) != hipSuccess) return sfail(N2F_EDEVICE, "sync failed");
-    if (b->grouped && b->groups[b->C[i] - 1]) b->groups[b->C[i] - 1]->remove(i);
+    if (b->grouped && b->group_of(i)) b->group_of(i)->remove(i);
     n2f_run_destroy(b->runs[i]);
     b->runs[i] = nullptr;
     b->removed[i] = 1;

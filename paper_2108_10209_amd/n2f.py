@@ -419,7 +419,8 @@ class Batch:
     n_streams = 0 runs every image on the caller's current stream;
     n_streams = BATCH_GROUPED (BF16) makes every launch of an epoch one
     grouped launch over all images, replayed as one graph per epoch on the
-    caller's current stream."""
+    caller's current stream; n_streams = -K (K = 2..4, BF16) splits the
+    images into K groups launched on K streams of the batch's own."""
 
     def __init__(self, images, cfg: Config | None = None, n_streams: int = 4):
         import torch

@@ -208,6 +208,24 @@ static int argument_checks() {
     CHECK(n2f_max_project(nullptr, 1, 1, nullptr, nullptr) == N2F_EINVAL);
     n2f_batch* b = nullptr;
     CHECK(n2f_batch_create(&b, 0, nullptr, nullptr, nullptr, nullptr, &d, nullptr, 0, 1, nullptr) == N2F_EINVAL);
+    {   // grouped on more streams than the tables hold, and grouped FP32: refused before any device work
+        const float* in1[1] = {reinterpret_cast<const float*>(256)};
+        const int h1[1] = {8}, w1[1] = {8}, c1[1] = {1};
+        n2f_config bf = d;
+        bf.precision = N2F_BF16;
+        CHECK(n2f_batch_create(&b, 1, in1, h1, w1, c1, &bf, reinterpret_cast<void*>(256), 1 << 30, -5, nullptr) ==
+              N2F_EINVAL);
+        n2f_config f32 = d;
+        f32.precision = N2F_FP32;
+        CHECK(n2f_batch_create(&b, 1, in1, h1, w1, c1, &f32, reinterpret_cast<void*>(256), 1 << 30, -2, nullptr) ==
+              N2F_EINVAL);
+        CHECK(n2f_group_grid_set(5, 0) == N2F_EINVAL);
+        CHECK(n2f_group_grid_set(15, 256) == N2F_EINVAL);
+        int gg = 0;
+        CHECK(n2f_group_grid_get(-1, &gg) == N2F_EINVAL);
+        CHECK(n2f_group_grid_get(5, nullptr) == N2F_EINVAL);
+        CHECK(n2f_group_grid_get(5, &gg) == N2F_OK && gg >= 1);
+    }
     CHECK(n2f_batch_add(nullptr, nullptr, 8, 8, 1, nullptr, 0, nullptr) == N2F_EINVAL);
     CHECK(n2f_batch_remove(nullptr, 0) == N2F_EINVAL);
     CHECK(n2f_server_cancel(nullptr, 0) == N2F_EINVAL);

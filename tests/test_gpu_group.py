@@ -46,13 +46,17 @@ def _alone(x, cfg):
     return r.result(), [r.progress(k) for k in range(C)], [r.history(k) for k in range(C)]
 
 
-@pytest.mark.parametrize("kw", [dict(fixed_epochs=4), dict(patience=4, max_epochs=60),
-                                dict(patience=3, max_epochs=40, downsample=n2f.DS_QUAD)])
-def test_grouped_batch_equals_alone(kw):
-    say("grouped batch", kw)
+@pytest.mark.parametrize("kw,streams", [(dict(fixed_epochs=4), n2f.BATCH_GROUPED),
+                                        (dict(patience=4, max_epochs=60), n2f.BATCH_GROUPED),
+                                        (dict(patience=3, max_epochs=40, downsample=n2f.DS_QUAD), n2f.BATCH_GROUPED),
+                                        (dict(patience=4, max_epochs=60), -2), (dict(fixed_epochs=4), -3)])
+def test_grouped_batch_equals_alone(kw, streams):
+    """On the caller's stream (-1) or split over 2 or 3 streams of the
+    batch's own (-2, -3): every image ends as it would alone."""
+    say("grouped batch", kw, streams)
     imgs = _images(SHAPES)
     cfg = n2f.default_config(precision=n2f.BF16, **kw)
-    b = n2f.Batch([dev(x) for x in imgs], cfg, n_streams=n2f.BATCH_GROUPED)
+    b = n2f.Batch([dev(x) for x in imgs], cfg, n_streams=streams)
     assert b.run() == 0
     for i, x in enumerate(imgs):
         yb = b.result(i)
@@ -79,13 +83,14 @@ def test_grouped_multi_tile_image_equals_alone():
     b.close()
 
 
-def test_grouped_add_remove_and_partial_runs():
+@pytest.mark.parametrize("streams", [n2f.BATCH_GROUPED, -2])
+def test_grouped_add_remove_and_partial_runs(streams):
     """Runs of a few epochs at a time; an image joins mid-way, another leaves;
     the ones that stay and the one that joins end as they would alone."""
-    say("grouped add/remove")
+    say("grouped add/remove", streams)
     imgs = _images([(1, 60, 52), (1, 45, 80), (3, 30, 26), (1, 90, 40)], seed=20)
     cfg = n2f.default_config(precision=n2f.BF16, patience=3, max_epochs=50)
-    b = n2f.Batch([dev(x) for x in imgs[:3]], cfg, n_streams=n2f.BATCH_GROUPED)
+    b = n2f.Batch([dev(x) for x in imgs[:3]], cfg, n_streams=streams)
     assert b.run(max_epochs=2) > 0
     b.remove(1)
     j = b.add(dev(imgs[3]))
