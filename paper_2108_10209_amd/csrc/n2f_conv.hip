@@ -384,7 +384,7 @@ struct ConvLds {
     double slred[8];                                      // head modes: per-wave BCE / squared-error sums
     float sx[2][kFirst ? kXHaloPix : 1];                  // MODE 4: input halo (20 x 20) of each group's tile
     float sw1[kFirst ? kTaps * kWidth + kWidth : 1];      // MODE 4: first-layer weights [t][co], then biases
-    float sbias[kWidth];                                  // forward and head modes: the layer's biases
+    __attribute__((aligned(16))) float sbias[kWidth];     // forward and head modes: the layer's biases
     float stgt[2][kHead ? kTile * kTile : 1];             // head modes: each group's tile of targets
 };
 
@@ -622,11 +622,9 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in,
                 for (int r = 0; r < 4; ++r) hg[j][r] = 0.f;
             float hbs = 0.f;
             double hls = 0.0;
-            float bv[4][4];   // bias of the lane's 16 channels
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) bv[j][r] = sbias[16 * j + 4 * g + r];
+            // the biases are read from LDS where they are used (16-byte words):
+            // held in registers across the pixel loop they push the grouped
+            // kernel past 256 VGPRs
             const float hb9 = shw[kWidth];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -634,20 +632,28 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in,
                 const bool valid = gy < h && gx < w;
                 const long long pix = (long long)gy * w + gx;
                 const float t = stgt[grp][(4 * wq + i) * kTile + n];   // 0 outside the image
-                // a8 as the BF16 value the forward would store
-                float a[4][4];
+                // a8 as the BF16 value the forward would store, channels
+                // 16 j + 4 g .. + 3 of this lane: computed where used (twice:
+                // for z, then for the delta and dW9) rather than held, to
+                // keep the grouped kernel within 256 VGPRs
+                auto a_of = [&](int j, float (&av)[4]) __attribute__((always_inline)) {
+                    const float4 b4 = *reinterpret_cast<const float4*>(&sbias[16 * j + 4 * g]);
+                    const float bv[4] = {b4.x, b4.y, b4.z, b4.w};
+#pragma unroll
+                    for (int r = 0; r < 4; r += 2) {
+                        const uint32_t pk = pack_bf16x2(fmaxf(acc[i][j][r] + bv[r], 0.f),
+                                                        fmaxf(acc[i][j][r + 1] + bv[r + 1], 0.f));
+                        av[r] = __uint_as_float(pk << 16);
+                        av[r + 1] = __uint_as_float(pk & 0xffff0000u);
+                    }
+                };
                 float zp = 0.f;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
+                    float av[4];
+                    a_of(j, av);
 #pragma unroll
-                    for (int r = 0; r < 4; r += 2) {
-                        const uint32_t pk = pack_bf16x2(fmaxf(acc[i][j][r] + bv[j][r], 0.f),
-                                                        fmaxf(acc[i][j][r + 1] + bv[j][r + 1], 0.f));
-                        a[j][r] = __uint_as_float(pk << 16);
-                        a[j][r + 1] = __uint_as_float(pk & 0xffff0000u);
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) zp = fmaf(a[j][r], shw[16 * j + 4 * g + r], zp);
+                    for (int r = 0; r < 4; ++r) zp = fmaf(av[r], shw[16 * j + 4 * g + r], zp);
                 }
                 zp = add_xor32(add_xor16(zp));
                 const float z = zp + hb9;
@@ -662,24 +668,24 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in,
                     continue;
                 }
                 const float d = valid ? (y - t) * hd.invP : 0.f;
-                if (valid) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < 4; ++j) {
+                    float av[4];
+                    a_of(j, av);
+                    if (valid) {
                         float dv[4];
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) dv[r] = a[j][r] > 0.f ? d * shw[16 * j + 4 * g + r] : 0.f;
+                        for (int r = 0; r < 4; ++r) dv[r] = av[r] > 0.f ? d * shw[16 * j + 4 * g + r] : 0.f;
                         const uint2 o = make_uint2(pack_bf16x2(dv[0], dv[1]), pack_bf16x2(dv[2], dv[3]));
                         *reinterpret_cast<uint2*>(out + pix * kWidth + 16 * j + 4 * g) = o;
                     }
-                    if (g == 0) {
-                        hbs += d;
-                        hls += (double)(fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - t * z);
-                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) hg[j][r] = fmaf(d, av[r], hg[j][r]);
                 }
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) hg[j][r] = fmaf(d, a[j][r], hg[j][r]);
+                if (valid && g == 0) {
+                    hbs += d;
+                    hls += (double)(fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - t * z);
+                }
             }
             // the 16 pixels (lanes n) of each row, then the wave's slot
             if (MODE == 2) {
@@ -799,7 +805,7 @@ __global__ __launch_bounds__(512) void k_conv_bf16_group(GroupView g) {
         while (s < n && gv >= pre[s + 1]) ++s;
         const int end = min(hi, pre[s + 1]);
         __syncthreads();   // shared memory of the previous run's blocks is free
-        const ConvArgs& a = *reinterpret_cast<const ConvArgs*>(g.args + (size_t)s * kArgStride);
+        const ConvArgs a = load_uniform(reinterpret_cast<const ConvArgs*>(g.args + (size_t)s * kArgStride));
         conv_bf16_range<MODE>(a.in, a.wpk, a.bias, a.mbits, a.out, a.h, a.w, a.nblk, a.st, a.hd, a.cf, gv - pre[s],
                               end - pre[s], L);
         gv = end;
@@ -1072,7 +1078,7 @@ __global__ __launch_bounds__(512) void k_wgrad_bf16(WgradArgs a) {
 
 __global__ __launch_bounds__(512) void k_wgrad_bf16_group(GroupView g) {
     for_group_blocks(g, [&](int s, int vb, int nvb) {
-        const WgradArgs& a = *reinterpret_cast<const WgradArgs*>(g.args + (size_t)s * kArgStride);
+        const WgradArgs a = load_uniform(reinterpret_cast<const WgradArgs*>(g.args + (size_t)s * kArgStride));
         wgrad_bf16_block(a.src, a.dlt, a.part, a.h, a.w, a.st, vb, nvb);
     });
 }

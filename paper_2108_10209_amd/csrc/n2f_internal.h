@@ -209,6 +209,23 @@ struct GroupView {
     const int* prefix;
     const int* starts;
 };
+// One run's argument block of a grouped launch, read by every lane of the
+// block (one cache line) and moved word by word to scalar registers: loaded
+// as ordinary vector loads they would hold the run's pointers in vector
+// registers for the whole kernel.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "argument blocks are whole 4-byte words");
+    constexpr int kWords = sizeof(T) / 4;
+    union {
+        T t;
+        int w[kWords];
+    } u;
+    const int* src = reinterpret_cast<const int*>(p);
+#pragma unroll
+    for (int i = 0; i < kWords; ++i) u.w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return u.t;
+}
 // Device side: walk the virtual blocks of a grouped launch, block b taking
 // b, b + gridDim.x, ...; f(run, virtual block, virtual blocks of that run).
 // The barrier frees the block's shared memory for the next virtual block.
