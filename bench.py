@@ -141,7 +141,8 @@ def launch_geometry(args, xs, n2f):
         entry = autotune.apply(npix, autotune.TABLE if src == "auto" else src)
     grids = {name: n2f.group_grid(k) for k, name in enumerate(n2f.GROUP_KINDS)}
     return {"source": src if entry is not None else "built-in", "group_grid": grids,
-            "tuning_bucket": entry["bucket"] if entry else None}
+            "tuning_bucket": entry["bucket"] if entry else None,
+            "wgrad_splits": entry.get("wgrad_splits", 0) if entry else 0}
 
 
 def bench_c3(args):
@@ -161,9 +162,14 @@ def bench_c3(args):
     npx = sum(x.numel() for x in xs)
     prec = n2f.BF16 if args.precision == "bf16" else n2f.FP32
     streams = args.streams if prec == n2f.BF16 else max(args.streams, 1)
-    cfg = n2f.default_config(precision=prec, max_epochs=args.max_epochs)
-    print(f"batch of {len(xs)} images, {npx / 1e6:.1f} Mpx, streams {streams}", file=sys.stderr, flush=True)
     geometry = launch_geometry(args, xs, n2f)
+    splits = args.wgrad_splits if args.wgrad_splits >= 0 else (geometry.get("wgrad_splits") or 0)
+    if prec != n2f.BF16:
+        splits = 0
+    geometry["wgrad_splits"] = splits
+    cfg = n2f.default_config(precision=prec, max_epochs=args.max_epochs, wgrad_splits=splits)
+    print(f"batch of {len(xs)} images, {npx / 1e6:.1f} Mpx, streams {streams}, weight-gradient splits "
+          f"{splits or 'default'}", file=sys.stderr, flush=True)
 
     def step():
         b = n2f.Batch(xs, cfg, n_streams=streams)
@@ -743,6 +749,9 @@ def main():
     ap.add_argument("--large-seeds", type=int, default=3)
     ap.add_argument("--large-crop", type=int, default=0, help="large: denoise the centre crop of this side instead")
     ap.add_argument("--batch-n", type=int, default=64)
+    ap.add_argument("--wgrad-splits", type=int, default=-1,
+                    help="batch: most pixel splits of a 64->64 weight gradient (0: the library default; -1: the "
+                         "tuning table's choice)")
     ap.add_argument("--tuning", default="auto",
                     help="batch: grouped launch geometry: 'auto' (the package's tuning table, when it has an entry "
                          "for this device), 'none' (built-in grids), 'tune' (tune on other images first), or a path")

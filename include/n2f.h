@@ -84,6 +84,11 @@ typedef struct n2f_config {
                                  own 32, 32, 64, 64, 128, 128, 256, 256; all zero: every layer `width`.
                                  Width 64 throughout runs on the tuned kernels; any other widths on generic
                                  FP32-MFMA kernels (BF16 storage in BF16 runs), not in grouped launches */
+    int    wgrad_splits;      /* most pixel splits of a 64->64 weight gradient (1..256); 0: 64 (BF16) or
+                                 256 (FP32).  Fewer splits write and re-read fewer partial rows (each is
+                                 9*64*64+64 floats) at the cost of fewer blocks per launch; the split count
+                                 fixes the order of the gradient's sums, so runs compare bit for bit only
+                                 at the same value */
 } n2f_config;
 
 typedef struct n2f_run n2f_run;

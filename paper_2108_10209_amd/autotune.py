@@ -10,6 +10,13 @@ the fastest, and stores the choice per (device, size bucket) in a JSON table
 that `apply` loads at start-up.  The geometry never changes results: every
 virtual block computes the same values whichever hardware block runs it.
 
+It also picks the weight gradient's split count for batches
+(`n2f_config.wgrad_splits`): in a batch the other images already fill the
+chip, so fewer, longer splits pay (less per-split overhead, fewer partial
+rows for Adam to read).  Unlike the geometry, the split count fixes the order
+of the gradient's sums, so runs agree bit for bit only at the same value; the
+entry records it and the caller puts it in the batch's configuration.
+
     python -m paper_2108_10209_amd.autotune --out paper_2108_10209_amd/tuning.json
 """
 from __future__ import annotations
@@ -25,6 +32,7 @@ from . import n2f
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 CANDIDATES = (128, 256, 384, 512, 768, 1024)
+SPLIT_CANDIDATES = (0, 32, 16)   # 0: the library default (64 for BF16)
 
 
 def size_bucket(npix_per_image: float) -> int:
@@ -55,7 +63,7 @@ def _time_kinds(batch, epochs: int) -> dict:
     return out
 
 
-def tune(images, candidates=CANDIDATES, epochs: int = 2, log=None) -> dict:
+def tune(images, candidates=CANDIDATES, epochs: int = 2, log=None, split_candidates=SPLIT_CANDIDATES) -> dict:
     """Tune the grid of every grouped kind on `images` (device tensors, C x
     H x W).  The images train for a fixed number of epochs meanwhile, so none
     drops out of the group; the returned entry has the chosen grid and the
@@ -86,9 +94,25 @@ def tune(images, candidates=CANDIDATES, epochs: int = 2, log=None) -> dict:
                 f"{1e3 * base[kind]:.1f} -> {1e3 * best_t:.1f} us per launch")
     finally:
         batch.close()
+    # the weight gradient's split count: whole-epoch kernel time (every kind)
+    split_ms = {}
+    for k in split_candidates:
+        b = n2f.Batch(images, n2f.default_config(precision=n2f.BF16, fixed_epochs=1000, wgrad_splits=k),
+                      n_streams=n2f.BATCH_GROUPED)
+        try:
+            b.run(max_epochs=1)
+            n2f.profile_begin(1)
+            b.run(max_epochs=epochs)
+            split_ms[k] = sum(n2f.profile_read(n2f.K_GROUP + kind)[0] for kind in range(len(n2f.GROUP_KINDS))) / epochs
+            n2f.profile_end()
+        finally:
+            b.close()
+        log(f"  wgrad_splits {k}: {split_ms[k]:.2f} ms of kernels per epoch")
+    best_split = min(split_ms, key=split_ms.get) if split_ms else 0
     npix = sum(int(x.shape[-2]) * int(x.shape[-1]) for x in images) / len(images)
     return {"device": _device_name(), "precision": "bf16", "bucket": size_bucket(npix),
-            "images": len(images), "mean_pixels": round(npix), "group_grid": chosen, "report": report}
+            "images": len(images), "mean_pixels": round(npix), "group_grid": chosen, "wgrad_splits": best_split,
+            "split_ms_per_epoch": {str(k): round(v, 3) for k, v in split_ms.items()}, "report": report}
 
 
 def load_table(path: str = TABLE) -> list:
@@ -141,7 +165,7 @@ def main(argv=None):
     entry = tune(xs, epochs=args.epochs)
     entry["tuned_in_s"] = round(time.perf_counter() - t0, 1)
     save_entry(entry, args.out)
-    print(json.dumps({k: entry[k] for k in ("device", "bucket", "group_grid", "tuned_in_s")}))
+    print(json.dumps({k: entry[k] for k in ("device", "bucket", "group_grid", "wgrad_splits", "tuned_in_s")}))
 
 
 if __name__ == "__main__":

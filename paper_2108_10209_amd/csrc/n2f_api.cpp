@@ -176,6 +176,8 @@ n2f_status check_cfg(const n2f_config* cfg) {
     if (cfg->downsample != N2F_DS_CHECKERBOARD && cfg->downsample != N2F_DS_QUAD)
         return fail(N2F_EINVAL, "unknown downsample");
     if (cfg->exact_targets != 0 && cfg->exact_targets != 1) return fail(N2F_EINVAL, "exact_targets must be 0 or 1");
+    if (cfg->wgrad_splits < 0 || cfg->wgrad_splits > kMaxSplit)
+        return fail(N2F_EINVAL, "wgrad_splits must be 0 (default) or 1.." + std::to_string(kMaxSplit));
     int seen[4] = {0, 0, 0, 0};
     for (int i = 0; i < 4; ++i) {
         if (cfg->pair_order[i] < 0 || cfg->pair_order[i] > 3 || seen[cfg->pair_order[i]]++)
@@ -222,7 +224,8 @@ n2f_status make_plan(int H, int W, int C, const n2f_config* cfg, Plan* p) {
         q.hsplit = head_splits(q.P);
         q.vblk = head_splits(HW);
     } else {
-        q.nsplit = std::max(wgrad_splits(q.hu, q.wu, q.bf), wgrad_splits(q.hl, q.wl, q.bf));
+        q.nsplit = std::max(wgrad_splits(q.hu, q.wu, q.bf, cfg->wgrad_splits),
+                            wgrad_splits(q.hl, q.wl, q.bf, cfg->wgrad_splits));
         q.n1split = (int)std::max(1LL, std::min((long long)kMaxSplit, ((long long)q.P + 511) / 512));
         // BF16: the head runs in the last forward convolution's epilogue, one
         // partial row per block of its grid (the larger of the two pair shapes)

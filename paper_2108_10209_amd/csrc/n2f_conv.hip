@@ -1160,9 +1160,9 @@ hipError_t launch_conv_bwd(const void* dlt, const void* wpk, const void* mask, v
 
 int head_fused_blocks(int h, int w) { return conv_bf16_blocks(h, w); }
 
-int wgrad_splits(int h, int w, int bf16) {
+int wgrad_splits(int h, int w, int bf16, int cap) {
     const int tiles = ((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile);
-    const int cap = bf16 ? kMaxSplitBf16 : kMaxSplit;
+    if (cap <= 0) cap = bf16 ? kMaxSplitBf16 : kMaxSplit;
     return tiles < cap ? tiles : cap;
 }
 

@@ -128,7 +128,7 @@ hipError_t launch_conv_fwd_val(const void* in, const void* wpk, const float* bia
                                DevState* st, double* vtrace, hipStream_t s);
 // Fixed-order sum of nblk validation partials and the stopping decision.
 hipError_t launch_decide(const double* vpart, int nblk, long long npix, DevState* st, double* vtrace, hipStream_t s);
-int wgrad_splits(int h, int w, int bf16);
+int wgrad_splits(int h, int w, int bf16, int cap = 0);   // cap 0: kMaxSplitBf16 / kMaxSplit
 hipError_t launch_wgrad(const void* src, const void* dlt, float* part, int nsplit, int bf16,
                         int h, int w, const DevState* st, hipStream_t s);
 hipError_t launch_wgrad1(const float* in, int C, const void* dlt, float* part, int nsplit, int bf16,

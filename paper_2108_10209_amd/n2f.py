@@ -57,6 +57,7 @@ class Config(ctypes.Structure):
         ("patience", c_int), ("max_epochs", c_int), ("fixed_epochs", c_int),
         ("pair_order", c_int * 4), ("precision", c_int), ("init_seed", c_ulonglong),
         ("use_graph", c_int), ("downsample", c_int), ("exact_targets", c_int), ("widths", c_int * 8),
+        ("wgrad_splits", c_int),
     ]
 
 

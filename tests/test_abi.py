@@ -69,10 +69,21 @@ def test_workspace_bytes_scales_and_rejects():
 def test_config_validation():
     for kw in [dict(n_layers=7), dict(width=40), dict(width=512), dict(lr=0.0), dict(beta1=1.0), dict(patience=0),
                dict(max_epochs=0), dict(pair_order=(0, 0, 1, 2)), dict(precision=7), dict(downsample=2),
-               dict(exact_targets=2)]:
+               dict(exact_targets=2), dict(wgrad_splits=-1), dict(wgrad_splits=257)]:
         with pytest.raises(n2f.N2FError) as e:
             n2f.workspace_bytes(8, 8, 1, n2f.default_config(**kw))
         assert e.value.code == n2f.EINVAL
+
+
+def test_wgrad_splits_shrink_the_partials():
+    """Fewer weight-gradient splits need less workspace: the partial rows of
+    the seven 64->64 layers (9 * 64 * 64 + 64 floats each per split)."""
+    base = n2f.workspace_bytes(1024, 1024, 1, n2f.default_config(precision=n2f.BF16))
+    assert n2f.default_config().wgrad_splits == 0
+    for k in (16, 32):
+        b = n2f.workspace_bytes(1024, 1024, 1, n2f.default_config(precision=n2f.BF16, wgrad_splits=k))
+        assert b < base
+        assert base - b >= 7 * (64 - k) * (9 * 64 * 64 + 64) * 4
 
 
 def test_null_arguments_rejected_without_device():

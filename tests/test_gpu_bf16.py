@@ -86,6 +86,33 @@ def test_bf16_train_step_teacher_forced(C, H, W, pre):
         assert abs(loss - loss_or) / abs(loss_or) < TOL
 
 
+@pytest.mark.parametrize("splits", [1, 16])
+def test_bf16_train_step_with_fewer_weight_gradient_splits(splits):
+    """A 512x384 step (training images of 384 and 512 tiles) with the
+    weight gradient cut into 1 or 16 pixel splits instead of 64: same bars
+    against the oracle, and a different split count changes only the order
+    of the sums (the step stays within the bar of the default one)."""
+    say("bf16 step, splits", splits)
+    C, H, W = 1, 512, 384
+    clean = synth.blobs(H, W, 4)
+    noisy = synth.add_gaussian(clean, 25 / 255, 14)
+    r = n2f.Run(dev(noisy), n2f.default_config(precision=n2f.BF16, wgrad_splits=splits))
+    xs = r.image(4).cpu().numpy().astype(np.float64)
+    pairs = O.training_pairs(xs)
+    st = O.new_state(synth.init_params(C, 0)[0])
+    st = O.train_step(st, C, pairs[0][0], pairs[0][1][0], H0)[0]
+    r.set_state(0, st.theta, st.m, st.v, st.t)
+    st32 = O.NetState(st.theta.astype(np.float32).astype(np.float64), st.m.astype(np.float32).astype(np.float64),
+                      st.v.astype(np.float32).astype(np.float64), st.t)
+    r.train_step(0, 1)
+    g, loss = r.get_grad(0)
+    _, g_or, loss_or, _ = O.train_step(st32, C, pairs[1][0], pairs[1][1][0], H0)
+    errs = {nm: rel(a, b) for (nm, a), b in zip(split(g, C).items(), split(g_or, C).values())}
+    say("  worst grad err", max(errs.values()), max(errs, key=errs.get))
+    assert max(errs.values()) < TOL, errs
+    assert abs(loss - loss_or) / abs(loss_or) < TOL
+
+
 def test_bf16_deterministic_and_one_shot():
     clean = synth.blobs(48, 56, 3)
     noisy = synth.add_gaussian(clean, 25 / 255, 13)

@@ -49,7 +49,8 @@ def _alone(x, cfg):
 @pytest.mark.parametrize("kw,streams", [(dict(fixed_epochs=4), n2f.BATCH_GROUPED),
                                         (dict(patience=4, max_epochs=60), n2f.BATCH_GROUPED),
                                         (dict(patience=3, max_epochs=40, downsample=n2f.DS_QUAD), n2f.BATCH_GROUPED),
-                                        (dict(patience=4, max_epochs=60), -2), (dict(fixed_epochs=4), -3)])
+                                        (dict(patience=4, max_epochs=60), -2), (dict(fixed_epochs=4), -3),
+                                        (dict(fixed_epochs=4, wgrad_splits=8), n2f.BATCH_GROUPED)])
 def test_grouped_batch_equals_alone(kw, streams):
     """On the caller's stream (-1) or split over 2 or 3 streams of the
     batch's own (-2, -3): every image ends as it would alone."""
