@@ -265,7 +265,7 @@ def bench_c3(args):
     # streams (secondary; timed after the main region, one step, after one
     # warm step): throughput and a check that every image's result is the
     # same bits as in the grouped run
-    if args.secondary and grouped and streams == n2f.BATCH_GROUPED:
+    if args.secondary and grouped:
         def step_streams():
             b = n2f.Batch(xs, cfg, n_streams=2)
             b.run()
@@ -756,7 +756,8 @@ def main():
                     help="batch: grouped launch geometry: 'auto' (the package's tuning table, when it has an entry "
                          "for this device), 'none' (built-in grids), 'tune' (tune on other images first), or a path")
     ap.add_argument("--streams", type=int, default=-1,
-                    help="batch: -1 grouped launches, -K grouped on K streams, >= 1 streams, 0 in turn")
+                    help="batch: -1 grouped launches on the caller's stream, -K grouped on K streams (K = 2..4), "
+                         ">= 1 per-image graphs on that many streams, 0 in turn")
     ap.add_argument("--fp32-sample", type=int, default=8)
     ap.add_argument("--serve-n", type=int, default=500)
     ap.add_argument("--serve-fp32-n", type=int, default=48)

@@ -314,7 +314,10 @@ n2f_status n2f_batch_workspace_bytes(int n, const int* H, const int* W, const in
  * streams the batch creates, the images split between them by work
  * (pixels x channels, largest first), one group per channel count and
  * stream, so launches of different kinds overlap across the streams (the
- * same bits again).  At most n + 64 images train at once (n2f_batch_add
+ * same bits again); the streams are refed in turn, each as soon as its own
+ * images' stopping rules are read.  While kernel timing is on
+ * (n2f_profile_begin), each timed epoch of such a batch runs alone: its
+ * stream waits for the others and they wait for it.  At most n + 64 images train at once (n2f_batch_add
  * beyond that returns N2F_ENOMEM).  Synchronises.  Constant images are finished at
  * once.  cfg->exact_targets is refused (N2F_EINVAL), here and by the
  * server. */

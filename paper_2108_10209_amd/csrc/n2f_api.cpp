@@ -1397,6 +1397,8 @@ hipStream_t run_stream(n2f_run* r) { return r->stream; }
 
 bool profiling_on() { return g_prof.on; }
 
+bool Group::next_epoch_timed() { return g_prof.on && (g_prof.epochs % g_prof.every) == 0; }
+
 namespace {
 // Blocks per grouped launch: the 3x3 kernels hold most of a CU's shared
 // memory (one block per CU); the others are short memory-bound blocks.

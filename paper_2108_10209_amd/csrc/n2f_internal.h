@@ -293,6 +293,9 @@ class Group {
     // in the epochs the kernel profiler times).
     n2f_status launch(int epochs);
     hipStream_t stream() const { return stream_; }
+    // The next epoch this process launches runs as timed direct launches
+    // (kernel timing is on and this is one epoch in `every`).
+    static bool next_epoch_timed();
 
    private:
     struct Slot {

@@ -197,25 +197,51 @@ n2f_status batch_append(n2f_batch* b, const float* d_in, int H, int W, int C, vo
 
 namespace {
 
-// Grouped mode: every group replays whole epochs on its stream (the groups
-// of different streams run concurrently), then the host reads each image's
-// stopping rule; a finished network leaves its group (or moves on to the
-// image's next network), and the groups' tables are rewritten before their
-// next epoch.
+// Grouped mode: the groups of each stream replay whole epochs there, then
+// the host reads the stopping rule of that stream's images; a finished
+// network leaves its group (or moves on to the image's next network), and
+// the group's tables are rewritten before its next epochs.  Streams are
+// served in turn, each refed as soon as its own epochs are read, so groups
+// on different streams drift to different points of their epochs and their
+// launches of different kinds overlap.
 n2f_status batch_run_grouped(n2f_batch* b, int max_now) {
-    for (int ran = 0; ran < max_now;) {
-        bool any = false;
-        for (auto& g : b->groups) any = any || (g && g->size() > 0);
-        if (!any) break;
-        const int k = std::min(n2f::profiling_on() ? 1 : kPollEpochs, max_now - ran);
-        for (auto& g : b->groups) {
-            if (!g || g->size() == 0) continue;
-            n2f_status st = g->launch(k);
-            if (st < 0) return st;
+    const int ns = (int)b->streams.size();
+    std::vector<int> ran(ns, 0);
+    // a timed epoch (kernel timing on) has the GPU to itself: its stream
+    // first waits for the work queued on the others, and they wait for it,
+    // so the timed launches are not slowed by concurrent ones
+    auto fence = [&](int s, bool before) -> n2f_status {
+        for (int t = 0; t < ns; ++t) {
+            if (t == s) continue;
+            n2f_status st = before ? order_after(b->streams[s], b->streams[t]) : order_after(b->streams[t], b->streams[s]);
+            if (st != N2F_OK) return st;
         }
-        ran += k;
+        return N2F_OK;
+    };
+    auto feed = [&](int s, bool* fed) -> n2f_status {
+        *fed = false;
+        if (ran[s] >= max_now) return N2F_OK;
+        const int k = std::min(n2f::profiling_on() ? 1 : kPollEpochs, max_now - ran[s]);
+        for (int c = 0; c < 3; ++c) {
+            n2f::Group* g = b->groups[3 * s + c].get();
+            if (!g || g->size() == 0) continue;
+            const bool excl = ns > 1 && n2f::Group::next_epoch_timed();
+            n2f_status st = excl ? fence(s, true) : N2F_OK;
+            if (st != N2F_OK) return st;
+            st = g->launch(k);
+            if (st < 0) return st;
+            if (excl) {
+                st = fence(s, false);
+                if (st != N2F_OK) return st;
+            }
+            *fed = true;
+        }
+        if (*fed) ran[s] += k;
+        return N2F_OK;
+    };
+    auto drain = [&](int s) -> n2f_status {
         for (int i = 0; i < b->n; ++i) {
-            if (b->finished[i]) continue;
+            if (b->finished[i] || b->stream_of[i] != s) continue;
             n2f::Group* g = b->group_of(i);
             int done = 0, ep = 0;
             n2f_status st = n2f_run_poll(b->runs[i], b->net[i], &done, &ep);
@@ -236,6 +262,29 @@ n2f_status batch_run_grouped(n2f_batch* b, int max_now) {
                 st = g->set_net(i, b->net[i]);
                 if (st < 0) return st;
             }
+        }
+        return N2F_OK;
+    };
+    std::vector<char> pending(ns, 0);
+    bool any = false;
+    for (int s = 0; s < ns; ++s) {
+        bool fed = false;
+        n2f_status st = feed(s, &fed);
+        if (st < 0) return st;
+        pending[s] = fed;
+        any = any || fed;
+    }
+    while (any) {
+        any = false;
+        for (int s = 0; s < ns; ++s) {
+            if (!pending[s]) continue;
+            n2f_status st = drain(s);
+            if (st < 0) return st;
+            bool fed = false;
+            st = feed(s, &fed);
+            if (st < 0) return st;
+            pending[s] = fed;
+            any = any || fed;
         }
     }
     return N2F_OK;
