@@ -332,7 +332,8 @@ __device__ __forceinline__ void first_layer_halo(uint16_t* halo, const float* sx
         *reinterpret_cast<uint4*>(halo + swz(pix, q)) = c;
         const bool interior = inside && hy >= 1 && hy <= kTile && hx >= 1 && hx <= kTile;
         const long long gp = (long long)gy * w + gx;
-        if (cf.a1 && interior) *reinterpret_cast<uint4*>(cf.a1 + gp * kWidth + 8 * q) = c;
+        if (cf.a1 && interior)
+            *reinterpret_cast<N2F_GLOBAL uint4*>(as_global(cf.a1) + gp * kWidth + 8 * q) = c;
         if (cf.m1) {
             // channel 8q + e is bit 16 (2 (q & 1) + e / 4) + 4 (q / 2) + e % 4:
             // within the low word (even q) or the high word (odd q), bit
@@ -355,7 +356,7 @@ __device__ __forceinline__ void first_layer_halo(uint16_t* halo, const float* sx
             t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x114, 0xf, 0xf, false);
             if (q >= 4) bits |= t;
             const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x111, 0xf, 0xf, false);
-            if (q == 7 && interior) reinterpret_cast<uint2*>(cf.m1)[gp] = make_uint2(lo, bits);
+            if (q == 7 && interior) reinterpret_cast<N2F_GLOBAL uint2*>(as_global(cf.m1))[gp] = make_uint2(lo, bits);
         }
     }
 }
@@ -396,11 +397,16 @@ struct ConvLds {
 // (k = 0, 1, ...) and, in the head modes, writes its own partial row, so
 // what each block computes does not depend on how the blocks are run.
 template <int MODE>
-__device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
-                                                const float* __restrict__ bias, uint16_t* __restrict__ mbits,
-                                                uint16_t* __restrict__ out, int h, int w, int nblk,
+__device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in_, const uint16_t* __restrict__ wpk_,
+                                                const float* __restrict__ bias_, uint16_t* __restrict__ mbits_,
+                                                uint16_t* __restrict__ out_, int h, int w, int nblk,
                                                 const DevState* st, ConvHead hd, ConvFirst cf, const int vb_lo,
                                                 const int vb_hi, ConvLds<MODE>& L) {
+    const N2F_GLOBAL uint16_t* __restrict__ in = as_global(in_);
+    const N2F_GLOBAL uint16_t* __restrict__ wpk = as_global(wpk_);
+    const N2F_GLOBAL float* __restrict__ bias = as_global(bias_);
+    N2F_GLOBAL uint16_t* __restrict__ mbits = as_global(mbits_);
+    N2F_GLOBAL uint16_t* __restrict__ out = as_global(out_);
     auto& sw = L.sw;
     auto& hb = L.hb;
     auto& shw = L.shw;
@@ -419,7 +425,7 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in,
     // the stop flag (st is never NULL here) is read first but tested only
     // once the weight and halo loads are in flight, so its memory latency
     // hides under theirs
-    const int stop = st->done;
+    const int stop = *as_global(&st->done);
     const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
     const int lane = tid & 63, wq = gt >> 6;
     const int g = lane >> 4, n = lane & 15;
@@ -466,7 +472,8 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in,
             const int hy = idx / kXHalo, hx = idx - hy * kXHalo;
             const int gy = y0 - 2 + hy, gx = x0 - 2 + hx;
             xf[u] = 0.f;
-            if (have && idx < kXHaloPix && gy >= 0 && gy < h && gx >= 0 && gx < w) xf[u] = cf.x[(long long)gy * w + gx];
+            if (have && idx < kXHaloPix && gy >= 0 && gy < h && gx >= 0 && gx < w)
+                xf[u] = as_global(cf.x)[(long long)gy * w + gx];
         }
     };
     if (vb_lo < vb_work) {
@@ -475,10 +482,12 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in,
     }
     float w1v[2] = {0.f, 0.f};
     if constexpr (kFirst) {
-        w1v[0] = cf.w1[tid];   // 576 weights, then 64 biases
-        if (tid < kTaps * kWidth + kWidth - 512) w1v[1] = (tid + 512 < kTaps * kWidth) ? cf.w1[tid + 512] : cf.b1[tid + 512 - kTaps * kWidth];
+        w1v[0] = as_global(cf.w1)[tid];   // 576 weights, then 64 biases
+        if (tid < kTaps * kWidth + kWidth - 512)
+            w1v[1] = (tid + 512 < kTaps * kWidth) ? as_global(cf.w1)[tid + 512]
+                                                  : as_global(cf.b1)[tid + 512 - kTaps * kWidth];
     }
-    const float hwv = (kHead && tid < kHeadN) ? hd.w9[tid] : 0.f;
+    const float hwv = (kHead && tid < kHeadN) ? as_global(hd.w9)[tid] : 0.f;
     const float bvv = (MODE != 1 && tid < kWidth) ? bias[tid] : 0.f;
     asm volatile("" ::: "memory");   // keeps those loads ahead of the test
     if (stop) return;
@@ -502,15 +511,15 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in,
             float sum = 0.f;
 #pragma unroll
             for (int q = 0; q < 8; ++q) sum += shred[q][tid];
-            hd.part[(long long)v * kHeadN + tid] = sum;
+            as_global(hd.part)[(long long)v * kHeadN + tid] = sum;
         }
         if (tid == 0) {
             double sum = 0.0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) sum += slred[q];
-            hd.lpart[v] = sum;
+            as_global(hd.lpart)[v] = sum;
             // one Adam step follows this head: count it (no other block reads t)
-            if (MODE == 2 && v == 0) hd.st->t += 1;
+            if (MODE == 2 && v == 0) *as_global(&hd.st->t) += 1;
         }
         __syncthreads();
         if (MODE == 2)
@@ -555,7 +564,7 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in,
         float tq = 0.f;
         if (kHead) {
             const int gy = y0 + (gt >> 4), gx = x0 + (gt & 15);
-            if (have && gy < h && gx < w) tq = hd.tgt[((long long)gy * w + gx) * hd.C + hd.k];
+            if (have && gy < h && gx < w) tq = as_global(hd.tgt)[((long long)gy * w + gx) * hd.C + hd.k];
         }
         // the data gradient's ReLU mask words of this lane's 4 pixels load
         // before the MFMA loop, so their latency hides under it
@@ -661,7 +670,7 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in,
                 if (MODE == 3) {
                     // validation: the output pixel and its squared error against the noisy image
                     if (valid && g == 0) {
-                        hd.y[pix] = y;
+                        as_global(hd.y)[pix] = y;
                         const double e = (double)y - (double)t;
                         hls += e * e;
                     }
@@ -828,17 +837,18 @@ int conv_bf16_blocks(int h, int w) {
 // split are placed on one XCD (block ids 8 apart), where they share the
 // delta tiles through that XCD's L2.
 //
-// Per tile, each of the 8 waves takes 32 pixels (two tile rows) as one K
-// step of all 36 16x16 output tiles (9 taps x 4 blocks of co).  Both
-// operands stay pixel-major in LDS and are read with the gfx950 16-bit
-// transpose load: within a group of 16 lanes, row-lane r addresses pixel
-// p0 + r/4 and channels c0 + 4(r%4).., and lane L then holds channel c0 + L
-// of pixels p0..p0+3; two such loads give the 8 K values of an MFMA
-// fragment.  A tap shift is only a different row address.  The next tile is
-// loaded into registers while the current one is multiplied (two LDS
-// buffers, one barrier per tile).  The bias gradient (quarter-0 blocks) is
-// summed from the staged delta with 16-byte reads.  At the end the waves'
-// sums are added in wave order through LDS, three taps at a time.
+// Per tile, wave (pr, oh) of the 8 takes the 64 pixels 64 pr .. (four tile
+// rows, two K steps) for the 18 output tiles of its half oh of co (9 taps
+// x 2 blocks of 16).  Both operands stay pixel-major in LDS and are read
+// with the gfx950 16-bit transpose load: within a group of 16 lanes,
+// row-lane r addresses pixel p0 + r/4 and channels c0 + 4(r%4).., and lane
+// L then holds channel c0 + L of pixels p0..p0+3; two such loads give the 8
+// K values of an MFMA fragment.  A tap shift is only a different row
+// address.  Tiles flow global -> registers -> LDS two tiles ahead (two
+// LDS buffers, one barrier per tile).  The bias gradient is summed from the
+// staged delta with 16-byte reads, a quarter of it in each quarter block.
+// At the end the waves' sums are added in wave order through LDS, five taps
+// at a time.
 constexpr int kWgPSA = 16;                                // bf16 per staged halo pixel (one quarter)
 constexpr int kWgPSB = 64;                                // bf16 per staged delta pixel (chunks XOR-placed)
 constexpr int kWgHaloE = kHalo * kHalo * kWgPSA;
@@ -874,9 +884,9 @@ __device__ __forceinline__ int wg_dt(int p, int ch) { return p * kWgPSB + ((((ch
 
 // Global -> registers: the halo quarter (channels 16q..16q+15 of the 18x18
 // pixels around the tile) and the 16x16x64 delta tile, zero outside.
-__device__ __forceinline__ void wg_load(uint4 (&pf)[kWgPf], const uint16_t* __restrict__ src,
-                                        const uint16_t* __restrict__ dlt, int tile, int tiles_x, int q, int h,
-                                        int w) {
+__device__ __forceinline__ void wg_load(uint4 (&pf)[kWgPf], const N2F_GLOBAL uint16_t* __restrict__ src,
+                                        const N2F_GLOBAL uint16_t* __restrict__ dlt, int tile, int tiles_x, int q,
+                                        int h, int w) {
     const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
 #pragma unroll
     for (int k = 0; k < kWgPf; ++k) {
@@ -887,12 +897,14 @@ __device__ __forceinline__ void wg_load(uint4 (&pf)[kWgPf], const uint16_t* __re
             const int hy = hp / kHalo, hx = hp - hy * kHalo;
             const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
             if (gy >= 0 && gy < h && gx >= 0 && gx < w)
-                v = *reinterpret_cast<const uint4*>(src + ((long long)gy * w + gx) * kWidth + 16 * q + 8 * hh);
+                v = *reinterpret_cast<const N2F_GLOBAL uint4*>(src + ((long long)gy * w + gx) * kWidth + 16 * q +
+                                                                8 * hh);
         } else if (c < kWgChunks) {
             const int c2 = c - kWgHaloChunks;
             const int p = c2 >> 3, qd = c2 & 7;
             const int gy = y0 + (p >> 4), gx = x0 + (p & 15);
-            if (gy < h && gx < w) v = *reinterpret_cast<const uint4*>(dlt + ((long long)gy * w + gx) * kWidth + 8 * qd);
+            if (gy < h && gx < w)
+                v = *reinterpret_cast<const N2F_GLOBAL uint4*>(dlt + ((long long)gy * w + gx) * kWidth + 8 * qd);
         }
         pf[k] = v;
     }
@@ -913,10 +925,12 @@ __device__ __forceinline__ void wg_store(const uint4 (&pf)[kWgPf], uint16_t* buf
 }
 
 // One block of the weight-gradient grid: block `b` of `nb` = 4 x nsplit.
-__device__ __forceinline__ void wgrad_bf16_block(const uint16_t* __restrict__ src, const uint16_t* __restrict__ dlt,
+__device__ __forceinline__ void wgrad_bf16_block(const uint16_t* __restrict__ src_, const uint16_t* __restrict__ dlt_,
                                                  float* __restrict__ part, int h, int w, const DevState* st,
                                                  const int b, const int nb) {
-    const int stop = st->done;   // tested once the first tiles' loads are in flight
+    const N2F_GLOBAL uint16_t* src = as_global(src_);
+    const N2F_GLOBAL uint16_t* dlt = as_global(dlt_);
+    const int stop = *as_global(&st->done);   // tested once the first tiles' loads are in flight
     __shared__ __attribute__((aligned(16))) unsigned char lds[kWgLdsBytes];
     __shared__ float dbs[256][16];     // bias gradient: per-thread sums of this block's 16 channels
     __shared__ float dbs2[32][16];
@@ -976,6 +990,9 @@ __device__ __forceinline__ void wgrad_bf16_block(const uint16_t* __restrict__ sr
                 db[2 * e + 1] += __uint_as_float(u[e] & 0xffff0000u);
             }
         }
+        // K step 1 covers the two pixel rows below K step 0, so its dy = 0
+        // fragments are K step 0's dy = 2 fragments: read once, used twice
+        bf16x8 a_dy2[3];
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
             // pixels of K step ks: k0 = 64 pr + 32 ks + 8 g + r/4 and k0 + 4
@@ -990,8 +1007,11 @@ __device__ __forceinline__ void wgrad_bf16_block(const uint16_t* __restrict__ sr
 #pragma unroll
             for (int t = 0; t < kTaps; ++t) {
                 const int dy = t / 3, dx = t - 3 * (t / 3);
-                const bf16x8 a = tr16_frag(halo + ((py0 + dy) * kHalo + wg_hslot(px0 + dx)) * kWgPSA + rc,
-                                           halo + ((py1 + dy) * kHalo + wg_hslot(px1 + dx)) * kWgPSA + rc);
+                const bf16x8 a = (ks == 1 && dy == 0)
+                                     ? a_dy2[dx]
+                                     : tr16_frag(halo + ((py0 + dy) * kHalo + wg_hslot(px0 + dx)) * kWgPSA + rc,
+                                                 halo + ((py1 + dy) * kHalo + wg_hslot(px1 + dx)) * kWgPSA + rc);
+                if (ks == 0 && dy == 2) a_dy2[dx] = a;
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[j], acc[t][j], 0, 0, 0);
@@ -1010,7 +1030,7 @@ __device__ __forceinline__ void wgrad_bf16_block(const uint16_t* __restrict__ sr
     // of an MFMA tile) move as one 16-byte LDS word; a reader adds the same
     // word of the 4 waves and stores its 4 rows
     float4* red = reinterpret_cast<float4*>(lds);
-    float* pp = part + (long long)sp * kConvN;
+    N2F_GLOBAL float* pp = as_global(part) + (long long)sp * kConvN;
 #pragma unroll
     for (int pass = 0; pass < 2; ++pass) {
         const int t0 = pass * kWgRedT, nt = pass == 0 ? kWgRedT : kTaps - kWgRedT;
@@ -1036,7 +1056,7 @@ __device__ __forceinline__ void wgrad_bf16_block(const uint16_t* __restrict__ sr
                 sum.w += x.w;
             }
             const int co = 16 * (2 * ohh + jj) + (ln & 15), cil = 4 * (ln >> 4);
-            float* o = pp + ((t0 + tt) * kWidth + 16 * q + cil) * kWidth + co;
+            N2F_GLOBAL float* o = pp + ((t0 + tt) * kWidth + 16 * q + cil) * kWidth + co;
             o[0] = sum.x;
             o[kWidth] = sum.y;
             o[2 * kWidth] = sum.z;

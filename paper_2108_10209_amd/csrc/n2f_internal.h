@@ -226,6 +226,27 @@ __device__ __forceinline__ T load_uniform(const T* p) {
     for (int i = 0; i < kWords; ++i) u.w[i] = __builtin_amdgcn_readfirstlane(src[i]);
     return u.t;
 }
+// A pointer read out of an argument block carries no address space, so
+// loads and stores through it compile to flat instructions.  Those count as
+// LDS operations as well, and every wait for an LDS read then also waits
+// for the global loads in flight.  Every pointer of an argument block
+// points into device memory; the hot loads and stores go through
+// `as_global` pointers, which compile to global instructions.  (The host
+// pass of a HIP source parses device functions too; there the qualifier is
+// empty.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define N2F_GLOBAL __attribute__((address_space(1)))
+#else
+#define N2F_GLOBAL
+#endif
+template <class T>
+__device__ __forceinline__ const N2F_GLOBAL T* as_global(const T* p) {
+    return (const N2F_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ N2F_GLOBAL T* as_global(T* p) {
+    return (N2F_GLOBAL T*)p;
+}
 // Device side: walk the virtual blocks of a grouped launch, block b taking
 // b, b + gridDim.x, ...; f(run, virtual block, virtual blocks of that run).
 // The barrier frees the block's shared memory for the next virtual block.

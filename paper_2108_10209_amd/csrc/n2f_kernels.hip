@@ -324,10 +324,15 @@ template <int C>
 constexpr int conv1_unroll() { return C == 1 ? 4 : (C == 2 ? 2 : 1); }
 
 template <int C, bool BF>
-__device__ __forceinline__ void conv1_block(const float* __restrict__ in, const float* __restrict__ w1,
-                                            const float* __restrict__ b1, void* __restrict__ out,
-                                            uint8_t* __restrict__ mbits, int h, int w, const DevState* st,
+__device__ __forceinline__ void conv1_block(const float* __restrict__ in_, const float* __restrict__ w1_,
+                                            const float* __restrict__ b1_, void* __restrict__ out_,
+                                            uint8_t* __restrict__ mbits_, int h, int w, const DevState* st,
                                             const int bid) {
+    const N2F_GLOBAL float* __restrict__ in = as_global(in_);
+    const N2F_GLOBAL float* __restrict__ w1 = as_global(w1_);
+    const N2F_GLOBAL float* __restrict__ b1 = as_global(b1_);
+    N2F_GLOBAL void* __restrict__ out = as_global(out_);
+    N2F_GLOBAL uint8_t* __restrict__ mbits = as_global(mbits_);
     const int stop = st->done;   // tested once the loads are in flight
     constexpr int U = conv1_unroll<C>();
     __shared__ __attribute__((aligned(16))) float sw[kTaps * C * kWidth + kWidth];
@@ -414,9 +419,12 @@ __device__ __forceinline__ void conv1_block(const float* __restrict__ in, const 
 constexpr int kWg1Block = 512;
 
 template <int C, bool BF>
-__device__ __forceinline__ void wgrad1_block(const float* __restrict__ in, const void* __restrict__ dlt,
-                                             float* __restrict__ part, int h, int w, const DevState* st,
+__device__ __forceinline__ void wgrad1_block(const float* __restrict__ in_, const void* __restrict__ dlt_,
+                                             float* __restrict__ part_, int h, int w, const DevState* st,
                                              const int bid, const int nb) {
+    const N2F_GLOBAL float* __restrict__ in = as_global(in_);
+    const N2F_GLOBAL void* __restrict__ dlt = as_global(dlt_);
+    N2F_GLOBAL float* __restrict__ part = as_global(part_);
     const int stop = st->done;                   // tested after the loads of the pixel loop
     constexpr int G = (C == 1) ? 8 : 4;          // channels per lane
     constexpr int LPP = kWidth / G;              // lanes per pixel
@@ -666,8 +674,10 @@ __global__ __launch_bounds__(kBlock) void k_head_val(const void* __restrict__ a8
 // epochs in a row without one end the run; fixed-epoch mode ends after
 // `fixed_epochs`.  One block.  `acc` tells the next kernel whether there is
 // an output to fold in.
-__device__ __forceinline__ void decide_block(const double* __restrict__ vpart, int nblk, long long npix, DevState* st,
-                                             double* __restrict__ vtrace) {
+__device__ __forceinline__ void decide_block(const double* __restrict__ vpart_, int nblk, long long npix, DevState* st,
+                                             double* __restrict__ vtrace_) {
+    const N2F_GLOBAL double* __restrict__ vpart = as_global(vpart_);
+    N2F_GLOBAL double* __restrict__ vtrace = as_global(vtrace_);
     __shared__ double sv[kBlock];
     if (st->done) {
         if (threadIdx.x == 0) st->acc = 0;
@@ -717,9 +727,12 @@ __device__ __forceinline__ void decide_block(const double* __restrict__ vpart, i
 
 // Fold the last validation output into the running sum: a new best empties
 // the sum and becomes the best output; otherwise the output is added.
-__device__ __forceinline__ void accumulate_block(const float* __restrict__ y, float* __restrict__ S,
-                                                 float* __restrict__ ybest, long long npix, const DevState* st,
+__device__ __forceinline__ void accumulate_block(const float* __restrict__ y_, float* __restrict__ S_,
+                                                 float* __restrict__ ybest_, long long npix, const DevState* st,
                                                  const int bid, const int nb) {
+    const N2F_GLOBAL float* __restrict__ y = as_global(y_);
+    N2F_GLOBAL float* __restrict__ S = as_global(S_);
+    N2F_GLOBAL float* __restrict__ ybest = as_global(ybest_);
     if (!st->acc) return;
     const int improved = st->improved;
     for (long long i = (long long)bid * kBlock + threadIdx.x; i < npix; i += (long long)nb * kBlock) {
@@ -784,13 +797,24 @@ constexpr int kAdamConvBlocks = (kLayers - 1) * kAdamWPL;
 constexpr int kAdamV0 = 4;                               // first layer: values per block
 constexpr int kAdamVH = 1;                               // head: values per block
 
-__device__ __forceinline__ void adam_block(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
-                                           float* __restrict__ g, const float* __restrict__ part,
-                                           const float* __restrict__ ginj, const ParamTable& pt, float lr,
-                                           double beta1, double beta2, float eps, float* fwd, float* bwd,
-                                           uint16_t* fwd16, uint16_t* bwd16, const double* __restrict__ lpart,
+__device__ __forceinline__ void adam_block(float* __restrict__ theta_, float* __restrict__ m_, float* __restrict__ v_,
+                                           float* __restrict__ g_, const float* __restrict__ part_,
+                                           const float* __restrict__ ginj_, const ParamTable& pt, float lr,
+                                           double beta1, double beta2, float eps, float* fwd_, float* bwd_,
+                                           uint16_t* fwd16_, uint16_t* bwd16_, const double* __restrict__ lpart_,
                                            int nloss, long long loss_npix, DevState* st, const int bid,
                                            const int nb) {
+    N2F_GLOBAL float* __restrict__ theta = as_global(theta_);
+    N2F_GLOBAL float* __restrict__ m = as_global(m_);
+    N2F_GLOBAL float* __restrict__ v = as_global(v_);
+    N2F_GLOBAL float* __restrict__ g = as_global(g_);
+    const N2F_GLOBAL float* __restrict__ part = as_global(part_);
+    const N2F_GLOBAL float* __restrict__ ginj = as_global(ginj_);
+    N2F_GLOBAL float* fwd = as_global(fwd_);
+    N2F_GLOBAL float* bwd = as_global(bwd_);
+    N2F_GLOBAL uint16_t* fwd16 = as_global(fwd16_);
+    N2F_GLOBAL uint16_t* bwd16 = as_global(bwd16_);
+    const N2F_GLOBAL double* __restrict__ lpart = as_global(lpart_);
     if (finished(st)) return;
     __shared__ float red[kBlock];
     __shared__ double lred[kBlock];
