@@ -844,21 +844,31 @@ int conv_bf16_blocks(int h, int w) {
 // row-lane r addresses pixel p0 + r/4 and channels c0 + 4(r%4).., and lane
 // L then holds channel c0 + L of pixels p0..p0+3; two such loads give the 8
 // K values of an MFMA fragment.  A tap shift is only a different row
-// address.  Tiles flow global -> registers -> LDS two tiles ahead (two
-// LDS buffers, one barrier per tile).  The bias gradient is summed from the
-// staged delta with 16-byte reads, a quarter of it in each quarter block.
-// At the end the waves' sums are added in wave order through LDS, five taps
-// at a time.
-constexpr int kWgPSA = 16;                                // bf16 per staged halo pixel (one quarter)
-constexpr int kWgPSB = 64;                                // bf16 per staged delta pixel (chunks XOR-placed)
-constexpr int kWgHaloE = kHalo * kHalo * kWgPSA;
-constexpr int kWgBufE = kWgHaloE + kTile * kTile * kWgPSB;
-constexpr int kWgHaloChunks = kHalo * kHalo * 2;          // 16-byte chunks of a halo quarter
-constexpr int kWgChunks = kWgHaloChunks + kTile * kTile * 8;
-constexpr int kWgPf = (kWgChunks + 511) / 512;            // chunks each thread carries
-constexpr int kWgRedT = 5;                                 // taps per pass of the final reduction
-constexpr int kWgRedBytes = 8 * 2 * kWgRedT * 64 * 16;     // 8 waves x (taps x 2) tiles x 64 lanes x 16 B
-constexpr int kWgLdsBytes = (2 * kWgBufE * 2 > kWgRedBytes) ? 2 * kWgBufE * 2 : kWgRedBytes;
+// address.
+//
+// Tiles go from global memory straight into LDS (16-byte buffer loads that
+// write LDS), three buffers deep: while tile it is multiplied, tile it + 1
+// may still be landing and tile it + 2 is requested.  A wave's load
+// instruction fills 64 consecutive 16-byte LDS slots, one per lane, so
+// each lane fetches the chunk that the (bank-spreading) layout puts in its
+// slot; chunks outside the image come back as zeros (out-of-range buffer
+// offsets read zero).  Each thread issues the same six loads per tile, so
+// a wave waits only for the loads two tiles old, and the barriers wait for
+// LDS traffic only.  The bias gradient is summed from the staged delta with
+// 16-byte reads, a quarter of it in each quarter block.  At the end the
+// waves' sums are added in wave order through LDS, three taps at a time.
+constexpr int kWgPSA = 16;                                 // bf16 per staged halo pixel (one quarter)
+constexpr int kWgPSB = 64;                                 // bf16 per staged delta pixel (chunks XOR-placed)
+constexpr int kWgHaloSlots = 704;                          // 16-byte slots of the halo quarter (648 used): 11 x 64
+constexpr int kWgSlots = 3072;                             // slots per buffer: halo, delta (2048), unused rest
+constexpr int kWgDma = kWgSlots / 512;                     // loads per thread per tile
+constexpr int kWgHaloE = kWgHaloSlots * 8;                 // bf16 offset of the delta in a buffer
+constexpr int kWgBufE = kWgSlots * 8;                      // bf16 per buffer (48 KB)
+constexpr int kWgRedT = 3;                                 // taps per pass of the final reduction
+static_assert(kWgHaloSlots >= kHalo * kHalo * 2 && kWgHaloSlots % 64 == 0, "halo slots");
+static_assert(kWgHaloSlots + kTile * kTile * 8 <= kWgSlots && kWgSlots % 512 == 0, "buffer slots");
+static_assert(8 * 2 * kWgRedT * 64 * 16 <= kWgBufE * 2, "one pass of the reduction fits a buffer");
+static_assert((256 + 32) * 16 * 4 <= kWgBufE * 2, "the bias sums fit a buffer");
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
@@ -877,50 +887,49 @@ __device__ __forceinline__ bf16x8 tr16_frag(const uint16_t* p0, const uint16_t* 
 // halves, so the columns x and x + 8 that two lane groups read together
 // never share a bank, and a row shift stays a constant offset); delta
 // pixel p keeps its 128-byte row and its 16-byte chunk c moves to
-// c ^ wg_dswz(p).
+// c ^ wg_dswz(p).  Both maps are their own inverses.
 __device__ __forceinline__ int wg_hslot(int hx) { return hx ^ (((hx >> 3) & 1) << 2); }
 __device__ __forceinline__ int wg_dswz(int p) { return (p & 2) | ((p >> 1) & 4); }
 __device__ __forceinline__ int wg_dt(int p, int ch) { return p * kWgPSB + ((((ch >> 3) ^ wg_dswz(p))) << 3) + (ch & 7); }
 
-// Global -> registers: the halo quarter (channels 16q..16q+15 of the 18x18
-// pixels around the tile) and the 16x16x64 delta tile, zero outside.
-__device__ __forceinline__ void wg_load(uint4 (&pf)[kWgPf], const N2F_GLOBAL uint16_t* __restrict__ src,
-                                        const N2F_GLOBAL uint16_t* __restrict__ dlt, int tile, int tiles_x, int q,
-                                        int h, int w) {
-    const int x0 = (tile % tiles_x) * kTile, y0 = (tile / tiles_x) * kTile;
+// Request tile (x0, y0) into the LDS buffer `buf`: the halo quarter
+// (channels 16q..16q+15 of the 18x18 pixels around the tile) and the
+// 16x16x64 delta tile.  Load k of wave wv fills slots 64 (wv + 8k) ..; the
+// first 11 such groups are the halo's, the next 32 the delta's.
+__device__ __forceinline__ void wg_request(uint16_t* buf, const N2F_GLOBAL uint16_t* src,
+                                           const N2F_GLOBAL uint16_t* dlt, int x0, int y0, int q, int h, int w) {
+    typedef __attribute__((address_space(3))) void lds_void;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr uint32_t kOut = 0x80000000u;   // beyond num_records: reads zero
+    // byte bases: the halo's top-left pixel (y0 - 1, x0 - 1) and the tile's (y0, x0)
+    const long long hb = ((long long)(y0 - 1) * w + (x0 - 1)) * (2 * kWidth);
+    const long long db = ((long long)y0 * w + x0) * (2 * kWidth);
+    const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(reinterpret_cast<const N2F_GLOBAL char*>(src) + hb), (short)0, 0x7fffffff, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(reinterpret_cast<const N2F_GLOBAL char*>(dlt) + db), (short)0, 0x7fffffff, 0x00020000);
 #pragma unroll
-    for (int k = 0; k < kWgPf; ++k) {
-        const int c = threadIdx.x + 512 * k;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (c < kWgHaloChunks) {
-            const int hp = c >> 1, hh = c & 1;
-            const int hy = hp / kHalo, hx = hp - hy * kHalo;
+    for (int k = 0; k < kWgDma; ++k) {
+        const int grp = wv + 8 * k;   // wave-uniform
+        const int sl = 64 * grp + lane;
+        uint32_t off = kOut;
+        if (grp < kWgHaloSlots / 64) {
+            // halo slot sl: pixel slot sl / 2 = hy * 18 + wg_hslot(hx), half sl % 2
+            const int ps = sl >> 1, hy = ps / kHalo, hx = wg_hslot(ps - hy * kHalo);
             const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
-            if (gy >= 0 && gy < h && gx >= 0 && gx < w)
-                v = *reinterpret_cast<const N2F_GLOBAL uint4*>(src + ((long long)gy * w + gx) * kWidth + 16 * q +
-                                                                8 * hh);
-        } else if (c < kWgChunks) {
-            const int c2 = c - kWgHaloChunks;
-            const int p = c2 >> 3, qd = c2 & 7;
-            const int gy = y0 + (p >> 4), gx = x0 + (p & 15);
-            if (gy < h && gx < w)
-                v = *reinterpret_cast<const N2F_GLOBAL uint4*>(dlt + ((long long)gy * w + gx) * kWidth + 8 * qd);
+            if (sl < kHalo * kHalo * 2 && gy >= 0 && gy < h && gx >= 0 && gx < w)
+                off = (uint32_t)((hy * w + hx) * (2 * kWidth) + 2 * (16 * q + 8 * (sl & 1)));
+        } else {
+            // delta slot: pixel p = d / 8, chunk (d % 8) ^ wg_dswz(p)
+            const int d = sl - kWgHaloSlots;
+            const int p = d >> 3, cq = (d & 7) ^ wg_dswz(p);
+            const int py = p >> 4, px = p & 15;
+            if (d < kTile * kTile * 8 && y0 + py < h && x0 + px < w)
+                off = (uint32_t)((py * w + px) * (2 * kWidth) + 16 * cq);
         }
-        pf[k] = v;
-    }
-}
-
-__device__ __forceinline__ void wg_store(const uint4 (&pf)[kWgPf], uint16_t* buf) {
-#pragma unroll
-    for (int k = 0; k < kWgPf; ++k) {
-        const int c = threadIdx.x + 512 * k;
-        if (c < kWgHaloChunks) {
-            const int hp = c >> 1, hy = hp / kHalo, hx = hp - hy * kHalo;
-            *reinterpret_cast<uint4*>(buf + (hy * kHalo + wg_hslot(hx)) * kWgPSA + 8 * (c & 1)) = pf[k];
-        } else if (c < kWgChunks) {
-            const int c2 = c - kWgHaloChunks;
-            *reinterpret_cast<uint4*>(buf + kWgHaloE + wg_dt(c2 >> 3, 8 * (c2 & 7))) = pf[k];
-        }
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(grp < kWgHaloSlots / 64 ? rh : rd, (lds_void*)(buf + 512 * grp), 16,
+                                                 off, 0, 0, 0);
     }
 }
 
@@ -931,10 +940,11 @@ __device__ __forceinline__ void wgrad_bf16_block(const uint16_t* __restrict__ sr
     const N2F_GLOBAL uint16_t* src = as_global(src_);
     const N2F_GLOBAL uint16_t* dlt = as_global(dlt_);
     const int stop = *as_global(&st->done);   // tested once the first tiles' loads are in flight
-    __shared__ __attribute__((aligned(16))) unsigned char lds[kWgLdsBytes];
-    __shared__ float dbs[256][16];     // bias gradient: per-thread sums of this block's 16 channels
-    __shared__ float dbs2[32][16];
-    uint16_t* bufs = reinterpret_cast<uint16_t*>(lds);
+    // three tile buffers, separate objects so that the compiler tracks the
+    // loads into each one apart
+    __shared__ __attribute__((aligned(16))) uint16_t buf0[kWgBufE];
+    __shared__ __attribute__((aligned(16))) uint16_t buf1[kWgBufE];
+    __shared__ __attribute__((aligned(16))) uint16_t buf2[kWgBufE];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int g = lane >> 4, r = lane & 15;
     // wave wv: pixels 64 (wv / 2) .. + 63 of each tile (two K steps) and
@@ -963,24 +973,33 @@ __device__ __forceinline__ void wgrad_bf16_block(const uint16_t* __restrict__ sr
     // block does a quarter of the work
     float db[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
-    // tiles flow global -> registers -> LDS two tiles ahead: while tile it is
-    // multiplied from one LDS buffer, tile it + 1 waits in one register set
-    // and tile it + 2 loads into the other
-    uint4 pfa[kWgPf], pfb[kWgPf];
-    if (nmine > 0) wg_load(pfa, src, dlt, sp, tiles_x, q, h, w);
-    if (nmine > 1) wg_load(pfb, src, dlt, sp + nsplit, tiles_x, q, h, w);
-    asm volatile("" ::: "memory");   // keeps those loads ahead of the test
-    if (stop) return;
-    if (nmine > 0) wg_store(pfa, bufs);
-    __syncthreads();
+    // the requests past the block's last tile repeat that tile, so that
+    // every step issues the same loads and the waits stay exact
+    auto request = [&](uint16_t* buf, int it) __attribute__((always_inline)) {
+        const int tile = sp + min(it, nmine - 1) * nsplit;
+        wg_request(buf, src, dlt, (tile % tiles_x) * kTile, (tile / tiles_x) * kTile, q, h, w);
+    };
+    if (nmine > 0) {
+        request(buf0, 0);
+        request(buf1, 1);
+    }
+    if (stop) {
+        wait_vmcnt<0>();   // the LDS the loads write stays allocated until they land
+        return;
+    }
     const int rp = r >> 2, rc = 4 * (r & 3);
 
-    // multiply tile `it` from LDS; `ld` takes the loads of tile it + 2 (it
-    // held tile it, already in LDS); `sv` holds tile it + 1, stored at the end
-    auto step = [&](uint4 (&ld)[kWgPf], uint4 (&sv)[kWgPf], int it) __attribute__((always_inline)) {
-        const uint16_t* halo = bufs + (it & 1) * kWgBufE;
-        const uint16_t* dt = halo + kWgHaloE;
-        if (it + 2 < nmine) wg_load(ld, src, dlt, sp + (it + 2) * nsplit, tiles_x, q, h, w);
+    // tile `it` is in `cur` (loaded two steps ago); `nxt` held tile it - 1.
+    // The steps past the last tile (up to two, rounding the loop to whole
+    // buffer cycles) still wait, synchronise and request, so that every
+    // path issues the same loads, and only skip the multiply.
+    auto step = [&](const uint16_t* cur, uint16_t* nxt, int it) __attribute__((always_inline)) {
+        wait_vmcnt<kWgDma>();   // this wave's loads of tile it have landed (tile it + 1's may not)
+        lds_barrier();          // every wave's have, and every wave is done with tile it - 1
+        request(nxt, it + 2);
+        if (it >= nmine) return;
+        const uint16_t* halo = cur;
+        const uint16_t* dt = cur + kWgHaloE;
         {
             const uint4 v = *reinterpret_cast<const uint4*>(dt + wg_dt(tid >> 1, 8 * (2 * q + (tid & 1))));
             const uint32_t u[4] = {v.x, v.y, v.z, v.w};
@@ -1017,34 +1036,33 @@ __device__ __forceinline__ void wgrad_bf16_block(const uint16_t* __restrict__ sr
                     acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[j], acc[t][j], 0, 0, 0);
             }
         }
-        if (it + 1 < nmine) wg_store(sv, bufs + ((it + 1) & 1) * kWgBufE);
-        __syncthreads();
     };
-    for (int it = 0; it < nmine; it += 2) {
-        step(pfa, pfb, it);
-        if (it + 1 < nmine) step(pfb, pfa, it + 1);
+    for (int it = 0; it < nmine; it += 3) {
+        step(buf0, buf2, it);
+        step(buf1, buf0, it + 1);
+        step(buf2, buf1, it + 2);
     }
+    wait_vmcnt<0>();   // the requests past the last tile
+    lds_barrier();     // every wave is done with the tiles: the buffers are free
 
-    // sum the 4 waves of each channel half in order, taps 0-4 then 5-8: a
+    // sum the 4 waves of each channel half in order, three taps per pass: a
     // lane's 4 accumulator values (rows 4 (lane / 16) + e, column lane % 16
     // of an MFMA tile) move as one 16-byte LDS word; a reader adds the same
     // word of the 4 waves and stores its 4 rows
-    float4* red = reinterpret_cast<float4*>(lds);
+    float4* red = reinterpret_cast<float4*>(buf0);
     N2F_GLOBAL float* pp = as_global(part) + (long long)sp * kConvN;
 #pragma unroll
-    for (int pass = 0; pass < 2; ++pass) {
-        const int t0 = pass * kWgRedT, nt = pass == 0 ? kWgRedT : kTaps - kWgRedT;
+    for (int pass = 0; pass < kTaps / kWgRedT; ++pass) {
+        const int t0 = pass * kWgRedT;
 #pragma unroll
         for (int tt = 0; tt < kWgRedT; ++tt)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                if (tt < nt) {
-                    const floatx4 v = acc[t0 + tt][j];
-                    red[(wv * 2 * kWgRedT + tt * 2 + j) * 64 + lane] = make_float4(v[0], v[1], v[2], v[3]);
-                }
+                const floatx4 v = acc[t0 + tt][j];
+                red[(wv * 2 * kWgRedT + tt * 2 + j) * 64 + lane] = make_float4(v[0], v[1], v[2], v[3]);
             }
-        __syncthreads();
-        for (int gi = tid; gi < nt * 2 * 2 * 64; gi += 512) {
+        lds_barrier();
+        for (int gi = tid; gi < kWgRedT * 2 * 2 * 64; gi += 512) {
             const int ln = gi & 63, jj = (gi >> 6) & 1, ohh = (gi >> 7) & 1, tt = gi >> 8;
             float4 sum = red[(ohh * 2 * kWgRedT + tt * 2 + jj) * 64 + ln];
 #pragma unroll
@@ -1062,12 +1080,15 @@ __device__ __forceinline__ void wgrad_bf16_block(const uint16_t* __restrict__ sr
             o[2 * kWidth] = sum.z;
             o[3 * kWidth] = sum.w;
         }
-        __syncthreads();
+        lds_barrier();
     }
-    // the 256 pixel slots of each channel: 32 runs of 8 slots, then the runs, in order
+    // the 256 pixel slots of each channel: 32 runs of 8 slots, then the runs,
+    // in order (per-thread sums of the block's 16 channels, in a tile buffer)
+    float (*dbs)[16] = reinterpret_cast<float (*)[16]>(buf1);
+    float (*dbs2)[16] = dbs + 256;
 #pragma unroll
     for (int e = 0; e < 8; ++e) dbs[tid >> 1][8 * (tid & 1) + e] = db[e];
-    __syncthreads();
+    lds_barrier();
     {
         const int c = tid & 15, run = tid >> 4;
         float sum = dbs[8 * run][c];
@@ -1075,7 +1096,7 @@ __device__ __forceinline__ void wgrad_bf16_block(const uint16_t* __restrict__ sr
         for (int k = 1; k < 8; ++k) sum += dbs[8 * run + k][c];
         dbs2[run][c] = sum;
     }
-    __syncthreads();
+    lds_barrier();
     if (tid < 16) {
         float sum = dbs2[0][tid];
 #pragma unroll

@@ -247,6 +247,20 @@ template <class T>
 __device__ __forceinline__ N2F_GLOBAL T* as_global(T* p) {
     return (N2F_GLOBAL T*)p;
 }
+// Barrier for LDS traffic: waits for this wave's LDS operations, then for
+// the other waves of the block.  __syncthreads() also waits for the wave's
+// global loads in flight (its release fence covers global memory, and the
+// loads share a counter with the stores), so a tile loaded ahead across it
+// would always be waited for at the barrier.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+// Wait until at most N of this wave's vector-memory operations are in
+// flight (they complete in order for loads).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    // s_waitcnt fields: vmcnt[3:0], expcnt[6:4] (7: no wait), lgkmcnt[11:8] (15: no wait), vmcnt[5:4] at [15:14]
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
 // Device side: walk the virtual blocks of a grouped launch, block b taking
 // b, b + gridDim.x, ...; f(run, virtual block, virtual blocks of that run).
 // The barrier frees the block's shared memory for the next virtual block.
