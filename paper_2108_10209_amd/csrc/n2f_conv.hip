@@ -419,6 +419,9 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in_
     constexpr bool kHead = (MODE == 2 || MODE == 3);   // head in the epilogue
     constexpr bool kFirst = (MODE == 4);               // first layer computed into the halo
     constexpr bool kFwd = (MODE == 0 || MODE == 4);    // plain forward epilogue
+    // the data gradient: counted buffer loads and stores, LDS-only barriers
+    // (measured: 2.7% faster; the forward measured 4% slower with them)
+    constexpr bool kBufIO = (MODE == 1);
     // nblk = gridDim.x, passed among the first arguments: reading the
     // hidden grid size after the head arguments costs a second round trip
     // of scalar loads before the first global load
@@ -445,19 +448,31 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in_
     auto iters_of = [&](int v) { return (ntiles - 2 * v + stride - 1) / stride; };
     const int vb_work = min(vb_hi, max(vb_lo, (ntiles + 1) / 2));
 
+    // the halo of `tile`, zeros outside the image.  The data gradient
+    // (kBufIO): buffer loads relative to the halo's top-left pixel, issued by
+    // every lane (a tile past the last one reads nothing), so the compiler
+    // counts them; the other modes load only the chunks inside.
     uint4 pf[kPf];
     auto fetch = [&](int tile) {
         const bool have = tile < ntiles;
         const int x0 = have ? (tile % tiles_x) * kTile : 0, y0 = have ? (tile / tiles_x) * kTile : 0;
+        const auto rs = buf_rsrc(reinterpret_cast<const N2F_GLOBAL char*>(in) +
+                                 ((long long)(y0 - 1) * w + (x0 - 1)) * (2 * kWidth));
 #pragma unroll
         for (int u = 0; u < kPf; ++u) {
             const int idx = gt + 256 * u;
             const int pix = idx >> 3, q = idx & 7;
             const int hy = pix / kHalo, hx = pix - hy * kHalo;
             const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
-            pf[u] = make_uint4(0u, 0u, 0u, 0u);
-            if (have && idx < kHaloChunks && gy >= 0 && gy < h && gx >= 0 && gx < w)
-                pf[u] = *reinterpret_cast<const uint4*>(in + ((long long)gy * w + gx) * kWidth + 8 * q);
+            const bool ok = have && idx < kHaloChunks && gy >= 0 && gy < h && gx >= 0 && gx < w;
+            if constexpr (kBufIO) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(
+                    rs, ok ? (uint32_t)((hy * w + hx) * (2 * kWidth) + 16 * q) : kBufOut, 0, 0);
+                pf[u] = make_uint4(v[0], v[1], v[2], v[3]);
+            } else {
+                pf[u] = make_uint4(0u, 0u, 0u, 0u);
+                if (ok) pf[u] = *reinterpret_cast<const uint4*>(in + ((long long)gy * w + gx) * kWidth + 8 * q);
+            }
         }
     };
     // MODE 4: the input halo (tile + 2 pixels each side) of the next tile,
@@ -539,6 +554,23 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in_
         }
         const bool more = nvb < vb_work;
         const int ntile = 2 * nvb + grp + nk * stride;
+        // kBufIO: the barriers of the tile loop wait for LDS traffic only, so
+        // the next tile's loads stay in flight across them; the mask words
+        // (data gradient) load before the next tile's halo, since loads
+        // complete in order and waiting for them then leaves the halo in
+        // flight
+        const int ftile = more ? ntile : ntiles;   // past the last tile: reads nothing
+        uint32_t mk[4];
+        if constexpr (MODE == 1) {
+            const auto rm = buf_rsrc(mbits + ((long long)y0 * w + x0) * 4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int gy = y0 + 4 * wq + i, gx = x0 + n;
+                const bool ok = have && gy < h && gx < w;
+                mk[i] = __builtin_amdgcn_raw_buffer_load_b16(
+                    rm, ok ? (uint32_t)((((4 * wq + i) * w + n) * 4 + g) * 2) : kBufOut, 0, 0);
+            }
+        }
         if constexpr (kFirst) {
 #pragma unroll
             for (int u = 0; u < kXPf; ++u) {
@@ -555,8 +587,13 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in_
                 const int idx = gt + 256 * u;
                 if (idx < kHaloChunks) *reinterpret_cast<uint4*>(halo + swz(idx >> 3, idx & 7)) = pf[u];
             }
-            __syncthreads();
-            if (more) fetch(ntile);   // in flight during the MFMA loop
+            if constexpr (kBufIO) {
+                lds_barrier();
+                fetch(ftile);   // in flight during the MFMA loop
+            } else {
+                __syncthreads();
+                if (more) fetch(ntile);   // in flight during the MFMA loop
+            }
         }
 
         // head modes: target pixel gt of the tile, loaded before the MFMA loop
@@ -565,16 +602,6 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in_
         if (kHead) {
             const int gy = y0 + (gt >> 4), gx = x0 + (gt & 15);
             if (have && gy < h && gx < w) tq = as_global(hd.tgt)[((long long)gy * w + gx) * hd.C + hd.k];
-        }
-        // the data gradient's ReLU mask words of this lane's 4 pixels load
-        // before the MFMA loop, so their latency hides under it
-        uint32_t mk[4];
-        if (MODE == 1) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int gy = y0 + 4 * wq + i, gx = x0 + n;
-                mk[i] = (have && gy < h && gx < w) ? mbits[((long long)gy * w + gx) * 4 + g] : 0u;
-            }
         }
         floatx4 acc[4][4];
 #pragma unroll
@@ -719,7 +746,55 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in_
                 }
             }
         }
-        if (!kHead && have) {
+        if constexpr (kBufIO) {
+            // buffer writes relative to pixel (y0, x0): those outside the
+            // image (or of a tile past the last) are dropped
+            float bv[4][4];
+            if (kFwd) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) bv[j][r] = sbias[16 * j + 4 * g + r];
+            }
+            const int gx = x0 + n;
+            const bool want_mask = kFwd && mbits != nullptr;   // the forward's mask words (not in validation)
+            const long long t0 = (long long)y0 * w + x0;
+            const auto ro = buf_rsrc(out + t0 * kWidth);
+            const auto rmk = buf_rsrc(mbits + t0 * 4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int gy = y0 + 4 * wq + i;
+                const bool ok = have && gy < h && gx < w;
+                const int rel = (4 * wq + i) * w + n;   // pixel relative to (y0, x0)
+                uint32_t word = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float v[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] = kFwd ? fmaxf(acc[i][j][r] + bv[j][r], 0.f) : acc[i][j][r];
+                    uint2 o = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                    if (MODE == 1) {
+                        const uint32_t m = mk[i] >> (4 * j);
+                        o.x &= ((m & 1u) ? 0x0000ffffu : 0u) | ((m & 2u) ? 0xffff0000u : 0u);
+                        o.y &= ((m & 4u) ? 0x0000ffffu : 0u) | ((m & 8u) ? 0xffff0000u : 0u);
+                    } else if (want_mask) {
+                        // a BF16 value is > 0 iff its bits, as the high half of
+                        // a signed 32-bit integer, are > 0 (-0 is not)
+                        word |= ((int)(o.x << 16) > 0 ? 1u : 0u) << (4 * j);
+                        word |= ((int)(o.x & 0xffff0000u) > 0 ? 2u : 0u) << (4 * j);
+                        word |= ((int)(o.y << 16) > 0 ? 4u : 0u) << (4 * j);
+                        word |= ((int)(o.y & 0xffff0000u) > 0 ? 8u : 0u) << (4 * j);
+                    }
+                    __builtin_amdgcn_raw_buffer_store_b64((__attribute__((ext_vector_type(2))) unsigned int){o.x, o.y},
+                                                          ro, ok ? (uint32_t)((rel * kWidth + 4 * g + 16 * j) * 2)
+                                                                 : kBufOut,
+                                                          0, 0);
+                }
+                if (kFwd)
+                    __builtin_amdgcn_raw_buffer_store_b16(
+                        (unsigned short)word, rmk, ok && want_mask ? (uint32_t)((rel * 4 + g) * 2) : kBufOut, 0, 0);
+            }
+        } else if (!kHead && have) {
             float bv[4][4];
             if (kFwd) {
 #pragma unroll
@@ -741,13 +816,7 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in_
 #pragma unroll
                     for (int r = 0; r < 4; ++r) v[r] = kFwd ? fmaxf(acc[i][j][r] + bv[j][r], 0.f) : acc[i][j][r];
                     uint2 o = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
-                    if (MODE == 1) {
-                        const uint32_t m = mk[i] >> (4 * j);
-                        o.x &= ((m & 1u) ? 0x0000ffffu : 0u) | ((m & 2u) ? 0xffff0000u : 0u);
-                        o.y &= ((m & 4u) ? 0x0000ffffu : 0u) | ((m & 8u) ? 0xffff0000u : 0u);
-                    } else if (want_mask) {
-                        // a BF16 value is > 0 iff its bits, as the high half of
-                        // a signed 32-bit integer, are > 0 (-0 is not)
+                    if (want_mask) {
                         word |= ((int)(o.x << 16) > 0 ? 1u : 0u) << (4 * j);
                         word |= ((int)(o.x & 0xffff0000u) > 0 ? 2u : 0u) << (4 * j);
                         word |= ((int)(o.y << 16) > 0 ? 4u : 0u) << (4 * j);
@@ -758,7 +827,9 @@ __device__ __forceinline__ void conv_bf16_range(const uint16_t* __restrict__ in_
                 if (want_mask) mbits[((long long)gy * w + gx) * 4 + g] = (uint16_t)word;
             }
         }
-        __syncthreads();   // the next tile's halo overwrites this buffer
+        // the next tile's halo overwrites this buffer
+        if constexpr (kBufIO) lds_barrier();
+        else __syncthreads();
         if (kHead && nk == 0) flush(vb);   // block vb is complete
         vb = nvb;
         k = nk;

@@ -247,6 +247,15 @@ template <class T>
 __device__ __forceinline__ N2F_GLOBAL T* as_global(T* p) {
     return (N2F_GLOBAL T*)p;
 }
+// Buffer resource over device memory from `base` (which may lie before the
+// data: only base + offset is accessed).  Reads at offset kBufOut return
+// zeros and writes there are dropped, so a tile's loads and stores outside
+// the image need no branch: every lane issues the same accesses, which the
+// compiler can count (it then waits for exactly the ones a value needs).
+constexpr uint32_t kBufOut = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000);
+}
 // Barrier for LDS traffic: waits for this wave's LDS operations, then for
 // the other waves of the block.  __syncthreads() also waits for the wave's
 // global loads in flight (its release fence covers global memory, and the
