@@ -963,42 +963,61 @@ __device__ __forceinline__ int wg_hslot(int hx) { return hx ^ (((hx >> 3) & 1) <
 __device__ __forceinline__ int wg_dswz(int p) { return (p & 2) | ((p >> 1) & 4); }
 __device__ __forceinline__ int wg_dt(int p, int ch) { return p * kWgPSB + ((((ch >> 3) ^ wg_dswz(p))) << 3) + (ch & 7); }
 
-// Request tile (x0, y0) into the LDS buffer `buf`: the halo quarter
-// (channels 16q..16q+15 of the 18x18 pixels around the tile) and the
-// 16x16x64 delta tile.  Load k of wave wv fills slots 64 (wv + 8k) ..; the
-// first 11 such groups are the halo's, the next 32 the delta's.
-__device__ __forceinline__ void wg_request(uint16_t* buf, const N2F_GLOBAL uint16_t* src,
-                                           const N2F_GLOBAL uint16_t* dlt, int x0, int y0, int q, int h, int w) {
-    typedef __attribute__((address_space(3))) void lds_void;
+// A thread's load k of every tile fills LDS slot 64 (wv + 8k) + lane; the
+// first 11 such groups of 64 slots are the halo quarter's (channels
+// 16q..16q+15 of the 18x18 pixels around the tile), the next 32 the 16x16x64
+// delta tile's.  Which chunk a slot holds is the same for every tile, so it
+// is worked out once per block: `rel`, the chunk's byte offset from its base
+// pixel (the halo's top-left (y0 - 1, x0 - 1) or the tile's (y0, x0)), or
+// kBufOut for the slots past the operands; `rc`, the pixel's row and column
+// relative to (y0 - 1, x0 - 1), in bits 0-7 and 8-15.
+struct WgSlots {
+    uint32_t rel[kWgDma];
+    uint32_t rc[kWgDma];
+};
+__device__ __forceinline__ WgSlots wg_slots(int q, int w) {
+    WgSlots sl;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    constexpr uint32_t kOut = 0x80000000u;   // beyond num_records: reads zero
-    // byte bases: the halo's top-left pixel (y0 - 1, x0 - 1) and the tile's (y0, x0)
-    const long long hb = ((long long)(y0 - 1) * w + (x0 - 1)) * (2 * kWidth);
-    const long long db = ((long long)y0 * w + x0) * (2 * kWidth);
-    const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(reinterpret_cast<const N2F_GLOBAL char*>(src) + hb), (short)0, 0x7fffffff, 0x00020000);
-    const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(reinterpret_cast<const N2F_GLOBAL char*>(dlt) + db), (short)0, 0x7fffffff, 0x00020000);
 #pragma unroll
     for (int k = 0; k < kWgDma; ++k) {
         const int grp = wv + 8 * k;   // wave-uniform
-        const int sl = 64 * grp + lane;
-        uint32_t off = kOut;
+        const int s = 64 * grp + lane;
         if (grp < kWgHaloSlots / 64) {
-            // halo slot sl: pixel slot sl / 2 = hy * 18 + wg_hslot(hx), half sl % 2
-            const int ps = sl >> 1, hy = ps / kHalo, hx = wg_hslot(ps - hy * kHalo);
-            const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
-            if (sl < kHalo * kHalo * 2 && gy >= 0 && gy < h && gx >= 0 && gx < w)
-                off = (uint32_t)((hy * w + hx) * (2 * kWidth) + 2 * (16 * q + 8 * (sl & 1)));
+            // halo slot s: pixel slot s / 2 = hy * 18 + wg_hslot(hx), half s % 2
+            const int ps = s >> 1, hy = ps / kHalo, hx = wg_hslot(ps - hy * kHalo);
+            sl.rel[k] = s < kHalo * kHalo * 2 ? (uint32_t)((hy * w + hx) * (2 * kWidth) + 2 * (16 * q + 8 * (s & 1)))
+                                              : kBufOut;
+            sl.rc[k] = (uint32_t)(hy | (hx << 8));
         } else {
             // delta slot: pixel p = d / 8, chunk (d % 8) ^ wg_dswz(p)
-            const int d = sl - kWgHaloSlots;
+            const int d = s - kWgHaloSlots;
             const int p = d >> 3, cq = (d & 7) ^ wg_dswz(p);
             const int py = p >> 4, px = p & 15;
-            if (d < kTile * kTile * 8 && y0 + py < h && x0 + px < w)
-                off = (uint32_t)((py * w + px) * (2 * kWidth) + 16 * cq);
+            sl.rel[k] = d < kTile * kTile * 8 ? (uint32_t)((py * w + px) * (2 * kWidth) + 16 * cq) : kBufOut;
+            sl.rc[k] = (uint32_t)((py + 1) | ((px + 1) << 8));
         }
+    }
+    return sl;
+}
+
+// Request tile (x0, y0) into the LDS buffer `buf`: the slots whose pixel
+// lies outside the image (or past the operands) read zeros.
+__device__ __forceinline__ void wg_request(uint16_t* buf, const WgSlots& sl, const N2F_GLOBAL uint16_t* src,
+                                           const N2F_GLOBAL uint16_t* dlt, int x0, int y0, int h, int w) {
+    typedef __attribute__((address_space(3))) void lds_void;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // byte bases: the halo's top-left pixel (y0 - 1, x0 - 1) and the tile's (y0, x0)
+    const long long hb = ((long long)(y0 - 1) * w + (x0 - 1)) * (2 * kWidth);
+    const long long db = ((long long)y0 * w + x0) * (2 * kWidth);
+    const __amdgpu_buffer_rsrc_t rh = buf_rsrc(reinterpret_cast<const N2F_GLOBAL char*>(src) + hb);
+    const __amdgpu_buffer_rsrc_t rd = buf_rsrc(reinterpret_cast<const N2F_GLOBAL char*>(dlt) + db);
+#pragma unroll
+    for (int k = 0; k < kWgDma; ++k) {
+        const int grp = wv + 8 * k;   // wave-uniform
+        const uint32_t gy = (uint32_t)(y0 - 1 + (int)(sl.rc[k] & 0xffu));
+        const uint32_t gx = (uint32_t)(x0 - 1 + (int)((sl.rc[k] >> 8) & 0xffu));
+        const uint32_t off = (gy < (uint32_t)h && gx < (uint32_t)w) ? sl.rel[k] : kBufOut;
         __builtin_amdgcn_raw_ptr_buffer_load_lds(grp < kWgHaloSlots / 64 ? rh : rd, (lds_void*)(buf + 512 * grp), 16,
                                                  off, 0, 0, 0);
     }
@@ -1046,9 +1065,10 @@ __device__ __forceinline__ void wgrad_bf16_block(const uint16_t* __restrict__ sr
 
     // the requests past the block's last tile repeat that tile, so that
     // every step issues the same loads and the waits stay exact
+    const WgSlots slots = wg_slots(q, w);
     auto request = [&](uint16_t* buf, int it) __attribute__((always_inline)) {
         const int tile = sp + min(it, nmine - 1) * nsplit;
-        wg_request(buf, src, dlt, (tile % tiles_x) * kTile, (tile / tiles_x) * kTile, q, h, w);
+        wg_request(buf, slots, src, dlt, (tile % tiles_x) * kTile, (tile / tiles_x) * kTile, h, w);
     };
     if (nmine > 0) {
         request(buf0, 0);
