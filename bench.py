@@ -589,8 +589,8 @@ def bench_serve(args):
         "dtype": args.precision, "data": "synthetic",
         "config": {"workload": f"first {len(base)} requests of the seeded trace (seed 5), Poisson arrivals at "
                                f"{rate:.4f}/s", "precision": args.precision,
-                   "launches": ("grouped" if streams == n2f.BATCH_GROUPED else f"grouped on {-streams} streams")
-                   if grouped else f"{streams} streams", "max_active": args.max_active,
+                   "launches": f"grouped, {streams} streams" if grouped else f"{streams} streams",
+                   "max_active": args.max_active,
                    "epochs_per_step": args.epochs_per_step},
         "rate_req_per_s": round(rate, 4), "calibration": calib,
         "latency_s": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)},
